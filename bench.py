@@ -1,0 +1,222 @@
+"""Benchmark of the explicit ensemble wall step on one MI355X.
+
+Workload: straight clamped cylinder, 400 x 500 nodes (200,000 nodes, 399,200
+linear triangles, 600,000 dof), S = 256 lognormal Matern (E, h) samples,
+steady internal pressure 1.33e5 dyn/cm^2, Rayleigh alpha = 50 1/s, dt = 0.9 x
+the element-eigenvalue bound.  One "step" = one explicit time step of the
+whole hot path (stiffness apply + central-difference update + load + peak
+radial QoI) for all 256 samples.
+
+Prints ONE JSON line: throughput in dof*sample*steps/s (inputs resident in
+HBM), the roofline of the fused step kernel (algorithmic bytes per launch /
+its average duration from HIP events on the launch stream) and the CPU
+oracle timed on a bounded sample on the host.
+
+    python bench.py [--steps K] [--warmup W] [--apply f32|f64] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def step_kernel_bytes(n_nodes: int, n_el: int, S: int, apply_f32: bool) -> dict:
+    """Algorithmic HBM bytes of one fused step launch (FP64 state): read
+    u_n and u_{n-1}, write u_{n+1} (8 B per dof and sample each), read
+    (E h) per element and sample and 1/m per node and sample (4 B in the
+    FP32 apply, 8 B in FP64), read the running peak q (8 B per node and
+    sample; its write is conditional and not counted), plus the per-mesh
+    arrays read once per launch (adjacency and 3x6 stiffness blocks, load,
+    radial directions, clamp bits)."""
+    w = 4 if apply_f32 else 8
+    n_dof = 3 * n_nodes
+    n_adj = 3 * n_el
+    per_sample = 3 * n_dof * 8 + n_el * w + n_nodes * w + n_nodes * 8
+    per_mesh = n_adj * (18 * w + 4 + 8) + (n_nodes + 1) * 4 + n_nodes * (24 + 24 + 1)
+    return dict(total=per_sample * S + per_mesh, per_sample=per_sample, per_mesh=per_mesh)
+
+
+def source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("step.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2101_09059_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, variant: str, launches_bytes: int):
+    """HBM traffic per launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        rec = d.get(f"{workload}:{variant}")
+        if not rec or rec.get("source_hash") != source_hash():
+            return None
+        return int(rec["bytes_per_launch"])
+    except Exception:
+        return None
+
+
+def cpu_baseline(mesh, eh, h, F, cfg, dt, budget_s: float = 20.0) -> dict:
+    """The oracle as it stands (per-sample CSR assembly + one SpMV and update
+    per step), single process, on a bounded sample of the same workload."""
+    from oracle import element, stepper
+    t0 = time.perf_counter()
+    kh, A, _ = element.reference_stiffness(mesh.xyz, mesh.tri, cfg["nu"], cfg["shear_k"])
+    t_el = time.perf_counter() - t0
+    steps, samples = 20, [0]
+    t0 = time.perf_counter()
+    stepper.run_ensemble(mesh.tri, kh, A, eh, h, cfg["rho"], F, mesh.fixed, mesh.radial, dt, steps,
+                         cfg["alpha"], lambda t: 1.0, samples=samples)
+    t1 = time.perf_counter() - t0
+    # grow the sample within the budget
+    more = max(0, int((budget_s - t_el - t1) / max(t1, 1e-3)))
+    if more:
+        extra = list(range(1, 1 + min(more, 7)))
+        t0 = time.perf_counter()
+        stepper.run_ensemble(mesh.tri, kh, A, eh, h, cfg["rho"], F, mesh.fixed, mesh.radial, dt, steps,
+                             cfg["alpha"], lambda t: 1.0, samples=extra)
+        t1 += time.perf_counter() - t0
+        samples += extra
+    work = mesh.n_dof * len(samples) * steps
+    return {"value": work / t1, "unit": "dof*sample*steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{len(samples)} sample columns x {steps} steps of the same 600,000-dof mesh, "
+                      f"single process (per-sample CSR assembly + SpMV + update); "
+                      f"{t1:.1f} s timed, element matrices ({t_el:.1f} s) excluded; host nproc={os.cpu_count()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--apply", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--also-f64", action="store_true", default=True)
+    ap.add_argument("--no-also-f64", dest="also_f64", action="store_false")
+    ap.add_argument("--no-cpu-baseline", dest="cpu", action="store_false", default=True)
+    ap.add_argument("--sample-block", type=int, default=0)
+    ap.add_argument("--sb-inner", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy 10 times (counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: the ensemble shards over samples with no per-step "
+              "exchange, and no multi-GPU figure is produced here (use --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+
+    if args.calib_copy:
+        n = 1 << 30
+        a = torch.empty(n // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calib_copy_bytes_read": n, "calib_copy_bytes_written": n, "launches": 10}))
+        return
+
+    from paper_2101_09059_amd import ensfem, inputs
+    cfg = inputs.CONFIGS["c2_cylinder"]
+    t0 = time.perf_counter()
+    mesh = inputs.cylinder(cfg["R"], cfg["L"], cfg["n_theta"], cfg["n_z"])
+    eh, h = inputs.lognormal_fields(mesh, cfg["S"], cfg["seed"])
+    F = inputs.traction_load(mesh, cfg["p0"])
+    log(f"inputs ready in {time.perf_counter() - t0:.1f} s: {mesh.n_nodes} nodes, {mesh.n_el} tri, S={cfg['S']}")
+
+    def run(apply_f32: bool, steps: int, warmup: int):
+        ens = ensfem.setup_case(mesh, eh, h, F, nu=cfg["nu"], shear_k=cfg["shear_k"], rho=cfg["rho"],
+                                alpha=cfg["alpha"], apply_prec=ensfem.F32 if apply_f32 else ensfem.F64,
+                                sample_block=args.sample_block, sb_inner=args.sb_inner)
+        dt = ens.cfl_dt(cfg["safety"])
+        ens.init_state()
+        stream = torch.cuda.current_stream()
+        ens.step(warmup, dt, stream=stream)
+        ens.sync()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ens.step(steps, dt, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        ens.sync()
+        info = ens.info()
+        ens.close()
+        del ens
+        torch.cuda.empty_cache()
+        return ms, dt, info
+
+    results = {}
+    order = [args.apply == "f32"] + ([args.apply != "f32"] if args.also_f64 else [])
+    for f32 in order:
+        ms, dt, info = run(f32, args.steps, args.warmup)
+        results["f32" if f32 else "f64"] = (ms, dt, info)
+        log(f"apply={'f32' if f32 else 'f64'}: {ms / args.steps:.4f} ms/step")
+
+    ms, dt, info = results[args.apply]
+    S = cfg["S"]
+    work = mesh.n_dof * S * args.steps
+    value = work / (ms * 1e-3)
+    apply_f32 = args.apply == "f32"
+    b = step_kernel_bytes(mesh.n_nodes, mesh.n_el, info["S_pad"], apply_f32)
+    per_launch_s = ms * 1e-3 / args.steps
+    achieved = b["total"] / per_launch_s / 1e9
+    variant = f"fused_step_{args.apply}apply_f64state"
+    traffic = measured_traffic("c2_cylinder", variant, b["total"])
+    out = {
+        "metric": "ensemble dof*sample*steps/s",
+        "value": value,
+        "unit": "dof*sample*steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 apply / f64 state" if apply_f32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": "clamped cylinder 400x500 nodes (600,000 dof), S=256 lognormal Matern E,h, "
+                               "steady pressure, alpha=50, dt=0.9 x element bound",
+                   "n_dof": mesh.n_dof, "samples": S, "dt": dt, "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": f"k_step ({variant})", "algorithmic_bytes_per_launch": b["total"]},
+    }
+    for k, (ms2, _, _) in results.items():
+        out[f"ms_per_step_{k}_apply"] = ms2 / args.steps
+        out[f"value_{k}_apply"] = work / (ms2 * 1e-3)
+    if args.cpu:
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(mesh, eh, h, F, cfg, dt)
+        log(f"cpu baseline in {time.perf_counter() - t0:.1f} s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

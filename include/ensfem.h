@@ -1,0 +1,183 @@
+/*
+ * ensfem -- explicit-in-time ensemble solver for the three-dof linear shell
+ * wall model (Li & Schiavazzi, arXiv 2101.09059), MI355X (gfx950) HIP library.
+ *
+ * One context = one wall mesh stepped for S material realizations at once
+ * (Sec. 2.3-2.4).  Per step:  R = K(E h)_s U  (element stiffness of Sec. 2.2.1
+ * scaled per element and sample by (E h)_{e,s}), then the lumped-mass
+ * central-difference update with mass-proportional damping (eq.
+ * dynamicsCD) under the wall-traction load f_n = g(t_n) F (Sec. 2.2.3).
+ *
+ * Conventions
+ *  - Every call returns int32: ENS_OK (0) or a negative ENS_E* code.  The
+ *    message of the last failure is ens_last_error(ctx) (valid until the
+ *    next call on that context).  No C++ exception crosses this interface.
+ *  - Host arrays passed in are COPIED before the call returns; the caller
+ *    keeps ownership and may free them at once.
+ *  - The library allocates no large device memory of its own: the caller
+ *    asks ens_workspace_size() and binds a device buffer of at least that
+ *    size with ens_bind_workspace() (the buffer is BORROWED: it must stay
+ *    alive and untouched until ens_destroy or a re-bind).  Only a few
+ *    hundred bytes of per-context bookkeeping are allocated internally.
+ *  - Device pointers given to ens_apply are borrowed for the call.
+ *  - Layouts are row-major with samples fastest: an ensemble block is
+ *    [rows][S] on the host and [rows][S_pad] on the device, S_pad >= S
+ *    (query ens_info); dof index = 3*node + component (x, y, z).
+ *  - Work is enqueued on the stream given to ens_step / ens_apply (a
+ *    hipStream_t; NULL = the legacy default stream).  Set-up calls and
+ *    read-backs synchronize.
+ *  - Calls on one context are not thread-safe.  Distinct contexts are
+ *    independent.
+ */
+#ifndef ENSFEM_H
+#define ENSFEM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ens_ctx ens_ctx;
+
+enum {
+  ENS_OK = 0,
+  ENS_EINVAL = -1,      /* bad argument: size, index, value range, NaN      */
+  ENS_ESTATE = -2,      /* call out of order (missing mesh / ensemble / ...) */
+  ENS_EWORKSPACE = -3,  /* workspace unbound or smaller than required       */
+  ENS_EDEVICE = -4,     /* HIP runtime failure                               */
+  ENS_EUNSTABLE = -5,   /* dt above the element-eigenvalue stability bound   */
+  ENS_ENONFINITE = -6,  /* NaN / Inf found in the state by the watchdog      */
+  ENS_EUNSUPPORTED = -7 /* option combination not implemented               */
+};
+
+/* precision of the stiffness apply */
+enum { ENS_F64 = 0, ENS_F32 = 1 };
+/* displacement state:
+ *   F64        two-level (u_n, u_{n-1}) in FP64
+ *   F32_KAHAN  velocity form (u, v) in FP32 with a Kahan-compensated
+ *              u <- u + dt v (compensation term kept per dof)
+ *   F32        velocity form in plain FP32 (shows what compensation buys) */
+enum { ENS_STATE_F64 = 0, ENS_STATE_F32_KAHAN = 1, ENS_STATE_F32 = 2 };
+/* apply kernel variant */
+enum { ENS_VARIANT_AUTO = 0, ENS_VARIANT_NODE_GATHER = 1, ENS_VARIANT_CSR_SHARED = 3 };
+/* load time factor g(t):  STEP g = 1;  RAMP_SINE g = sin(pi t / (2 t_ramp))
+ * for t < t_ramp, else 1 (sine ramp of Sec. 3.1.2);  PULSATILE = RAMP_SINE
+ * times (1 + amp sin(2 pi t / period)). */
+enum { ENS_LOAD_STEP = 0, ENS_LOAD_RAMP_SINE = 1, ENS_LOAD_PULSATILE = 2 };
+typedef struct {
+  int32_t kind;
+  double t_ramp;
+  double amp;
+  double period;
+} ens_schedule;
+/* quantities of interest */
+enum { ENS_QOI_PEAK_RADIAL = 1 };
+
+typedef struct {
+  int64_t n_nodes, n_el, n_dof;
+  int32_t S, S_pad, sample_block;
+  int32_t apply_prec, state_prec, variant;
+  int32_t shared_stiffness; /* 1 when every (E h) row is constant over samples */
+  int64_t steps_done;
+  double dt;                /* 0 until the first ens_step */
+  size_t workspace_bytes;
+} ens_info_t;
+
+/* Lifetime.  ENS_EDEVICE if the HIP device cannot be selected. */
+int32_t ens_create(int32_t device, ens_ctx** out);
+int32_t ens_destroy(ens_ctx* ctx);
+const char* ens_last_error(const ens_ctx* ctx);
+int32_t ens_info(ens_ctx* ctx, ens_info_t* out);
+
+/* Wall mesh (Sec. 2.2.1): xyz[n_nodes*3] node coordinates, tri[n_el*3]
+ * node indices (counter-clockwise seen from outside), fixed_dof[n_nodes*3]
+ * 1 = clamped (held at zero, its load ignored), radial[n_nodes*3] unit
+ * outward radial direction per node (QoI, Sec. 2.2.3 local frame).
+ * ENS_EINVAL for an index out of range, a degenerate triangle or a radial
+ * vector that is not unit length (|1 - |r|| > 1e-6). */
+int32_t ens_set_mesh(ens_ctx* ctx, int64_t n_nodes, const double* xyz, int64_t n_el,
+                     const int32_t* tri, const uint8_t* fixed_dof, const double* radial);
+
+/* Material (Sec. 2.2.1 constitutive matrix; Sec. 2.3 damping C = alpha M):
+ * 0 <= nu < 0.5, shear_k >= 0, rho > 0 (g/cm^3), alpha >= 0 (1/s). */
+int32_t ens_set_material(ens_ctx* ctx, double nu, double shear_k, double rho, double alpha);
+
+/* Ensemble fields: eh[n_el*S] = (E h)_{e,s} (element-wise product of
+ * modulus and thickness, the scalar that multiplies the reference element
+ * stiffness, Sec. 2.2.1 / Sec. 2.4) and h[n_el*S] thickness (lumped mass
+ * rho h A / 3 per node, Sec. 2.3).  ENS_EINVAL if S < 1 or any value is not
+ * finite and positive. */
+int32_t ens_set_ensemble(ens_ctx* ctx, int32_t S, const double* eh, const double* h);
+
+/* Load: F[n_nodes*3] nodal traction force (shared by all samples) and its
+ * time factor; f_n = g(n dt) F. */
+int32_t ens_set_load(ens_ctx* ctx, const double* F, ens_schedule sched);
+
+/* Precision / variant / outputs.  qoi_mask: ENS_QOI_PEAK_RADIAL to track
+ * q_{i,s} = max_n e_r,i . u_{i,s}(t_n).  energy_every > 0 records the
+ * discrete energy 1/2 v^T M v + 1/2 u_{n+1}^T K u_n per sample at steps
+ * n with n % energy_every == 0 (the most recent 4096 records are kept).
+ * ENS_VARIANT_CSR_SHARED needs shared stiffness (checked at bind). */
+int32_t ens_configure(ens_ctx* ctx, int32_t apply_prec, int32_t state_prec, int32_t variant,
+                      int32_t qoi_mask, int32_t energy_every);
+
+/* Device workspace: size for the current mesh / ensemble / configuration,
+ * then bind.  Binding uploads everything and runs the set-up kernels
+ * (element matrices, lumped mass, stability bound).  ENS_EWORKSPACE if
+ * bytes is below the required size or dptr is NULL or not 256-B aligned. */
+int32_t ens_workspace_size(ens_ctx* ctx, size_t* bytes);
+int32_t ens_bind_workspace(ens_ctx* ctx, void* dptr, size_t bytes);
+
+/* Largest stable step times `safety`: dt = safety * 2 / omega_hat with
+ * omega_hat^2 = max_{e,s} 3 E_{e,s} lambda_max(Khat_e) / (rho A_e), an upper
+ * bound on the assembled pencil's largest eigenvalue. */
+int32_t ens_cfl_dt(ens_ctx* ctx, double safety, double* dt_out);
+
+/* Initial state u0, v0 [n_nodes*3*S] (NULL = zero).  Resets the step count,
+ * the QoI and the energy log.  The Taylor starter u_{-1} is formed at the
+ * first ens_step, when dt is known. */
+int32_t ens_init_state(ens_ctx* ctx, const double* u0, const double* v0);
+
+/* Enqueue n_steps explicit steps of size dt on `stream` (hipStream_t).  dt
+ * is fixed by the first call after ens_init_state; later calls must pass the
+ * same value (ENS_EINVAL otherwise).  ENS_EUNSTABLE if dt exceeds the
+ * stability bound (2 / omega_hat) unless `force` is nonzero.  ENS_ESTATE if
+ * mesh, ensemble, load, state or workspace is missing. */
+int32_t ens_step(ens_ctx* ctx, int64_t n_steps, double dt, int32_t force, void* stream);
+
+/* Wait for the context's work; ENS_ENONFINITE if the state holds NaN/Inf. */
+int32_t ens_sync(ens_ctx* ctx);
+
+/* Read-backs into caller-owned host buffers (synchronizing):
+ * state u_n [n_nodes*3*S]; QoI [n_nodes*S]; energy records (up to
+ * max_records most recent, chronological): steps_out[k], e_out[k*S];
+ * per-node ensemble mean and unbiased variance of the QoI [n_nodes]. */
+int32_t ens_read_state(ens_ctx* ctx, double* u);
+int32_t ens_read_qoi(ens_ctx* ctx, int32_t kind, double* out);
+int32_t ens_read_energy(ens_ctx* ctx, int64_t max_records, int64_t* steps_out, double* e_out,
+                        int64_t* n_out);
+int32_t ens_moments(ens_ctx* ctx, double* mean, double* var);
+
+/* Stand-alone stiffness apply R = K(E h)_s U on device buffers of
+ * [n_nodes*3][S_pad] in `prec` (ENS_F64: double, ENS_F32: float), using
+ * the bound context's mesh and fields, no boundary conditions. */
+int32_t ens_apply(ens_ctx* ctx, int32_t prec, const void* U_dev, void* R_dev, void* stream);
+
+/* Performance tuning of the step kernels (no effect on results beyond
+ * rounding order): sample_block in {0 = auto, 8, 16, 32, 64} samples per
+ * lane group, sb_inner = 1 orders workgroups sample-block-fastest.  A
+ * change of the padded width drops the workspace binding (re-bind). */
+int32_t ens_set_tuning(ens_ctx* ctx, int32_t sample_block, int32_t sb_inner);
+
+/* Checkpoint of the time-stepping state (state arrays, step count, dt,
+ * QoI).  ens_save with host == NULL writes the size to *bytes. */
+int32_t ens_save(ens_ctx* ctx, void* host, size_t* bytes);
+int32_t ens_load(ens_ctx* ctx, const void* host, size_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ENSFEM_H */

@@ -1,0 +1,899 @@
+// Host side of libensfem: the C ABI declared in include/ensfem.h, argument
+// checking, the mesh adjacency and workspace planners, uploads, the step
+// driver and read-backs.  All arithmetic of the method runs in the kernels
+// of setup.hip and step.hip.
+#include "ensfem.h"
+#include "internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace ensfem;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kChunk = 1024;  // steps per load-factor table
+
+size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
+
+struct Layout {
+  size_t xyz, tri, khat, area, lam, flags, adj_ptr, adj_el, adj_nb, adj_loc, k64, k32, fixed,
+      radial, F, eh64, eh32, h, minv64, minv32, u[2], uh[2], uc, v, q, epart, erec, gtab, base,
+      mean, var, aux, total;
+};
+
+struct Flags {  // small device scalars
+  int32_t bad;
+  int32_t nonfinite;
+  unsigned long long omega2_bits;
+};
+
+}  // namespace
+
+struct ens_ctx {
+  int device = 0;
+  std::string err;
+  // mesh
+  int64_t n_nodes = 0, n_el = 0;
+  std::vector<double> xyz, radial;
+  std::vector<int32_t> tri;
+  std::vector<uint8_t> fixed;  // bits per node
+  bool have_mesh = false;
+  // adjacency
+  std::vector<int32_t> adj_ptr, adj_el;
+  std::vector<int2> adj_nb;
+  std::vector<uint8_t> adj_loc;
+  // material
+  double nu = 0.49, shear_k = 5.0 / 6.0, rho = 1.0, alpha = 0.0;
+  bool have_material = false;
+  // ensemble (padded [n_el][ld])
+  int32_t S = 0, ld = 0, SB = 0;
+  std::vector<double> eh, h;
+  bool have_ens = false, shared = false;
+  // load
+  std::vector<double> F;
+  Schedule sched{0, 0.0, 0.0, 1.0};
+  bool have_load = false;
+  // configuration
+  int32_t apply_prec = ENS_F64, state_prec = ENS_STATE_F64, variant = ENS_VARIANT_AUTO;
+  int32_t qoi_mask = ENS_QOI_PEAK_RADIAL, energy_every = 0;
+  int32_t tune_sb = 0, sb_inner = 0;
+  // device
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  Layout L{};
+  bool bound = false;
+  double omega2 = 0.0;
+  // state
+  bool state_init = false, started = false, u0_zero = true;
+  int cur = 0;
+  double dt = 0.0;
+  int64_t steps = 0;
+  int64_t energy_records = 0;
+  std::vector<int64_t> energy_steps;
+  hipStream_t last_stream = nullptr;
+
+  template <class T>
+  T* p(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  int32_t fail(int32_t code, const std::string& msg) {
+    err = msg;
+    return code;
+  }
+};
+
+#define HIPC(expr)                                                                          \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return ctx->fail(ENS_EDEVICE, std::string("HIP error: ") + hipGetErrorString(e_) +    \
+                                        " at " #expr);                                      \
+  } while (0)
+
+#define GUARD_BEGIN try {
+#define GUARD_END                                                   \
+  }                                                                 \
+  catch (const std::bad_alloc&) {                                   \
+    return ctx->fail(ENS_EINVAL, "host allocation failed");         \
+  }                                                                 \
+  catch (const std::exception& ex) {                                \
+    return ctx->fail(ENS_EINVAL, ex.what());                        \
+  }                                                                 \
+  catch (...) {                                                     \
+    return ctx->fail(ENS_EINVAL, "unknown error");                  \
+  }
+
+namespace {
+
+int pick_sample_block(int S, int requested) {
+  if (requested == 8 || requested == 16 || requested == 32 || requested == 64) return requested;
+  int sb = 8;
+  while (sb < S && sb < 64) sb <<= 1;
+  return sb;
+}
+
+Layout plan(const ens_ctx* c) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  const int64_t nn = c->n_nodes, ne = c->n_el, nadj = 3 * ne, ld = c->ld;
+  const int64_t ndof = 3 * nn;
+  L.xyz = take(sizeof(double) * 3 * nn);
+  L.tri = take(sizeof(int32_t) * 3 * ne);
+  L.khat = take(sizeof(double) * 81 * ne);
+  L.area = take(sizeof(double) * ne);
+  L.lam = take(sizeof(double) * ne);
+  L.flags = take(sizeof(Flags));
+  L.adj_ptr = take(sizeof(int32_t) * (nn + 1));
+  L.adj_el = take(sizeof(int32_t) * nadj);
+  L.adj_nb = take(sizeof(int2) * nadj);
+  L.adj_loc = take(nadj);
+  L.k64 = take(sizeof(double) * 18 * nadj);
+  L.k32 = take(sizeof(float) * 18 * nadj);
+  L.fixed = take(nn);
+  L.radial = take(sizeof(double) * 3 * nn);
+  L.F = take(sizeof(double) * 3 * nn);
+  L.eh64 = take(sizeof(double) * ne * ld);
+  L.eh32 = take(sizeof(float) * ne * ld);
+  L.h = take(sizeof(double) * ne * ld);
+  L.minv64 = take(sizeof(double) * nn * ld);
+  L.minv32 = take(sizeof(float) * nn * ld);
+  if (c->state_prec == ENS_STATE_F64) {
+    L.u[0] = take(sizeof(double) * ndof * ld);
+    L.u[1] = take(sizeof(double) * ndof * ld);
+  } else {
+    L.uh[0] = take(sizeof(float) * ndof * ld);
+    L.uh[1] = take(sizeof(float) * ndof * ld);
+    if (c->state_prec == ENS_STATE_F32_KAHAN) L.uc = take(sizeof(float) * ndof * ld);
+    L.v = take(sizeof(float) * ndof * ld);
+  }
+  L.q = take(sizeof(double) * nn * ld);
+  const int64_t n_nb = (nn + (kBlock / c->SB) - 1) / (kBlock / c->SB);
+  L.epart = take(sizeof(double) * (n_nb + 256) * ld);
+  L.erec = take(sizeof(double) * kEnergyCap * ld);
+  L.gtab = take(sizeof(double) * kChunk);
+  L.base = take(sizeof(int64_t));
+  L.mean = take(sizeof(double) * nn);
+  L.var = take(sizeof(double) * nn);
+  L.aux = take(sizeof(double) * ndof * ld);
+  L.total = off;
+  return L;
+}
+
+void build_adjacency(ens_ctx* c) {
+  const int64_t nn = c->n_nodes, ne = c->n_el;
+  c->adj_ptr.assign(nn + 1, 0);
+  for (int64_t i = 0; i < 3 * ne; ++i) c->adj_ptr[c->tri[i] + 1]++;
+  for (int64_t i = 0; i < nn; ++i) c->adj_ptr[i + 1] += c->adj_ptr[i];
+  std::vector<int32_t> next(c->adj_ptr.begin(), c->adj_ptr.end() - 1);
+  c->adj_el.resize(3 * ne);
+  c->adj_nb.resize(3 * ne);
+  c->adj_loc.resize(3 * ne);
+  for (int64_t e = 0; e < ne; ++e) {
+    for (int a = 0; a < 3; ++a) {
+      const int32_t node = c->tri[3 * e + a];
+      const int32_t pos = next[node]++;
+      c->adj_el[pos] = (int32_t)e;
+      c->adj_nb[pos] = make_int2(c->tri[3 * e + (a + 1) % 3], c->tri[3 * e + (a + 2) % 3]);
+      c->adj_loc[pos] = (uint8_t)a;
+    }
+  }
+}
+
+bool ready_for_workspace(const ens_ctx* c, std::string* why) {
+  if (!c->have_mesh) { *why = "mesh not set"; return false; }
+  if (!c->have_ens) { *why = "ensemble not set"; return false; }
+  return true;
+}
+
+StepArgs base_args(const ens_ctx* c, bool f32) {
+  StepArgs a{};
+  a.n_nodes = (int32_t)c->n_nodes;
+  a.ld = c->ld;
+  const int npb = kBlock / c->SB;
+  a.n_nb = (int32_t)((c->n_nodes + npb - 1) / npb);
+  a.n_sb = c->ld / c->SB;
+  a.sb_inner = c->sb_inner;
+  a.adj.ptr = c->p<int32_t>(c->L.adj_ptr);
+  a.adj.el = c->p<int32_t>(c->L.adj_el);
+  a.adj.nb = c->p<int2>(c->L.adj_nb);
+  a.adj.k = f32 ? (const void*)c->p<float>(c->L.k32) : (const void*)c->p<double>(c->L.k64);
+  a.eh = f32 ? (const void*)c->p<float>(c->L.eh32) : (const void*)c->p<double>(c->L.eh64);
+  a.minv = f32 ? (const void*)c->p<float>(c->L.minv32) : (const void*)c->p<double>(c->L.minv64);
+  a.F = c->p<double>(c->L.F);
+  a.fixed = c->p<uint8_t>(c->L.fixed);
+  a.radial = c->p<double>(c->L.radial);
+  a.q = c->p<double>(c->L.q);
+  a.gtab = c->p<double>(c->L.gtab);
+  a.energy_part = c->p<double>(c->L.epart);
+  return a;
+}
+
+// pad [rows][S] host data to [rows][ld], pads copy column 0
+void pad_rows(const double* src, int64_t rows, int S, int ld, std::vector<double>& dst) {
+  dst.resize((size_t)rows * ld);
+  for (int64_t r = 0; r < rows; ++r) {
+    const double* s = src + r * S;
+    double* d = dst.data() + r * ld;
+    std::memcpy(d, s, sizeof(double) * S);
+    for (int k = S; k < ld; ++k) d[k] = s[0];
+  }
+}
+
+void unpad_rows(const double* src, int64_t rows, int S, int ld, double* dst) {
+  for (int64_t r = 0; r < rows; ++r) std::memcpy(dst + r * S, src + r * ld, sizeof(double) * S);
+}
+
+int32_t upload_all(ens_ctx* ctx) {
+  const Layout& L = ctx->L;
+  hipStream_t st = nullptr;
+  const int64_t nn = ctx->n_nodes, ne = ctx->n_el, ld = ctx->ld;
+  HIPC(hipMemcpy(ctx->p<void>(L.xyz), ctx->xyz.data(), sizeof(double) * 3 * nn, hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(ctx->p<void>(L.tri), ctx->tri.data(), sizeof(int32_t) * 3 * ne, hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(ctx->p<void>(L.adj_ptr), ctx->adj_ptr.data(), sizeof(int32_t) * (nn + 1), hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(ctx->p<void>(L.adj_el), ctx->adj_el.data(), sizeof(int32_t) * 3 * ne, hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(ctx->p<void>(L.adj_nb), ctx->adj_nb.data(), sizeof(int2) * 3 * ne, hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(ctx->p<void>(L.adj_loc), ctx->adj_loc.data(), 3 * ne, hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(ctx->p<void>(L.fixed), ctx->fixed.data(), nn, hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(ctx->p<void>(L.radial), ctx->radial.data(), sizeof(double) * 3 * nn, hipMemcpyHostToDevice));
+  if (ctx->have_load)
+    HIPC(hipMemcpy(ctx->p<void>(L.F), ctx->F.data(), sizeof(double) * 3 * nn, hipMemcpyHostToDevice));
+  else
+    HIPC(hipMemset(ctx->p<void>(L.F), 0, sizeof(double) * 3 * nn));
+  HIPC(hipMemcpy(ctx->p<void>(L.eh64), ctx->eh.data(), sizeof(double) * ne * ld, hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(ctx->p<void>(L.h), ctx->h.data(), sizeof(double) * ne * ld, hipMemcpyHostToDevice));
+  HIPC(hipMemset(ctx->p<void>(L.flags), 0, sizeof(Flags)));
+  Flags* fl = ctx->p<Flags>(L.flags);
+  HIPC(launch_element_setup(ne, ctx->p<double>(L.xyz), ctx->p<int32_t>(L.tri), ctx->nu, ctx->shear_k,
+                            ctx->p<double>(L.khat), ctx->p<double>(L.area), ctx->p<double>(L.lam),
+                            &fl->bad, st));
+  HIPC(launch_adjacency_blocks(3 * ne, ctx->p<int32_t>(L.adj_el), ctx->p<uint8_t>(L.adj_loc),
+                               ctx->p<double>(L.khat), ctx->p<double>(L.k64), ctx->p<float>(L.k32), st));
+  HIPC(launch_cast_f32(ne * ld, ctx->p<double>(L.eh64), ctx->p<float>(L.eh32), st));
+  HIPC(launch_lumped_mass((int32_t)nn, (int32_t)ld, ctx->p<int32_t>(L.adj_ptr), ctx->p<int32_t>(L.adj_el),
+                          ctx->p<double>(L.area), ctx->p<double>(L.h), ctx->rho,
+                          ctx->p<double>(L.minv64), ctx->p<float>(L.minv32), st));
+  HIPC(launch_cfl_max(ne, (int32_t)ld, ctx->S, ctx->p<double>(L.eh64), ctx->p<double>(L.h),
+                      ctx->p<double>(L.lam), ctx->p<double>(L.area), ctx->rho, &fl->omega2_bits, st));
+  HIPC(hipDeviceSynchronize());
+  Flags hf{};
+  HIPC(hipMemcpy(&hf, fl, sizeof(Flags), hipMemcpyDeviceToHost));
+  if (hf.bad) return ctx->fail(ENS_EINVAL, "degenerate triangle found by the element set-up");
+  double w2;
+  std::memcpy(&w2, &hf.omega2_bits, sizeof(double));
+  if (!(w2 > 0.0) || !std::isfinite(w2)) return ctx->fail(ENS_EINVAL, "stability bound is not finite");
+  ctx->omega2 = w2;
+  return ENS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t ens_create(int32_t device, ens_ctx** out) {
+  if (!out) return ENS_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return ENS_EDEVICE;
+  if (hipSetDevice(device) != hipSuccess) return ENS_EDEVICE;
+  ens_ctx* c = new (std::nothrow) ens_ctx();
+  if (!c) return ENS_EINVAL;
+  c->device = device;
+  *out = c;
+  return ENS_OK;
+}
+
+int32_t ens_destroy(ens_ctx* ctx) {
+  if (!ctx) return ENS_EINVAL;
+  if (ctx->bound) hipDeviceSynchronize();
+  delete ctx;
+  return ENS_OK;
+}
+
+const char* ens_last_error(const ens_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int32_t ens_info(ens_ctx* ctx, ens_info_t* out) {
+  if (!ctx || !out) return ENS_EINVAL;
+  out->n_nodes = ctx->n_nodes;
+  out->n_el = ctx->n_el;
+  out->n_dof = 3 * ctx->n_nodes;
+  out->S = ctx->S;
+  out->S_pad = ctx->ld;
+  out->sample_block = ctx->SB;
+  out->apply_prec = ctx->apply_prec;
+  out->state_prec = ctx->state_prec;
+  out->variant = ctx->variant;
+  out->shared_stiffness = ctx->shared ? 1 : 0;
+  out->steps_done = ctx->steps;
+  out->dt = ctx->dt;
+  out->workspace_bytes = ctx->have_mesh && ctx->have_ens ? plan(ctx).total : 0;
+  return ENS_OK;
+}
+
+int32_t ens_set_mesh(ens_ctx* ctx, int64_t n_nodes, const double* xyz, int64_t n_el,
+                     const int32_t* tri, const uint8_t* fixed_dof, const double* radial) {
+  if (!ctx) return ENS_EINVAL;
+  GUARD_BEGIN
+  if (n_nodes < 3 || n_el < 1 || !xyz || !tri || !fixed_dof || !radial)
+    return ctx->fail(ENS_EINVAL, "ens_set_mesh: need n_nodes >= 3, n_el >= 1 and non-null arrays");
+  if (n_nodes > INT32_MAX / 3 || n_el > INT32_MAX / 3)
+    return ctx->fail(ENS_EINVAL, "ens_set_mesh: mesh too large for 32-bit indices");
+  for (int64_t i = 0; i < 3 * n_el; ++i)
+    if (tri[i] < 0 || tri[i] >= n_nodes)
+      return ctx->fail(ENS_EINVAL, "ens_set_mesh: element index out of range at entry " + std::to_string(i));
+  for (int64_t i = 0; i < 3 * n_nodes; ++i)
+    if (!std::isfinite(xyz[i])) return ctx->fail(ENS_EINVAL, "ens_set_mesh: non-finite coordinate");
+  for (int64_t e = 0; e < n_el; ++e) {  // reject degenerate triangles up front
+    const int32_t* t = tri + 3 * e;
+    if (t[0] == t[1] || t[1] == t[2] || t[0] == t[2])
+      return ctx->fail(ENS_EINVAL, "ens_set_mesh: repeated node in element " + std::to_string(e));
+    double a[3], b[3];
+    for (int k = 0; k < 3; ++k) {
+      a[k] = xyz[3 * t[1] + k] - xyz[3 * t[0] + k];
+      b[k] = xyz[3 * t[2] + k] - xyz[3 * t[0] + k];
+    }
+    const double cx = a[1] * b[2] - a[2] * b[1], cy = a[2] * b[0] - a[0] * b[2], cz = a[0] * b[1] - a[1] * b[0];
+    if (!(cx * cx + cy * cy + cz * cz > 0.0))
+      return ctx->fail(ENS_EINVAL, "ens_set_mesh: degenerate triangle " + std::to_string(e));
+  }
+  for (int64_t i = 0; i < n_nodes; ++i) {
+    const double* r = radial + 3 * i;
+    const double nrm = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    if (!(std::fabs(nrm - 1.0) <= 1e-6))
+      return ctx->fail(ENS_EINVAL, "ens_set_mesh: radial vector of node " + std::to_string(i) + " is not unit length");
+  }
+  ctx->n_nodes = n_nodes;
+  ctx->n_el = n_el;
+  ctx->xyz.assign(xyz, xyz + 3 * n_nodes);
+  ctx->tri.assign(tri, tri + 3 * n_el);
+  ctx->radial.assign(radial, radial + 3 * n_nodes);
+  ctx->fixed.assign(n_nodes, 0);
+  for (int64_t i = 0; i < n_nodes; ++i)
+    for (int k = 0; k < 3; ++k)
+      if (fixed_dof[3 * i + k]) ctx->fixed[i] |= (uint8_t)(1u << k);
+  build_adjacency(ctx);
+  ctx->have_mesh = true;
+  ctx->have_ens = false;  // fields are per element: re-set them for a new mesh
+  ctx->have_load = false;
+  ctx->bound = false;
+  ctx->state_init = false;
+  return ENS_OK;
+  GUARD_END
+}
+
+int32_t ens_set_material(ens_ctx* ctx, double nu, double shear_k, double rho, double alpha) {
+  if (!ctx) return ENS_EINVAL;
+  if (!(nu >= 0.0 && nu < 0.5) || !(shear_k >= 0.0) || !(rho > 0.0) || !(alpha >= 0.0) ||
+      !std::isfinite(shear_k) || !std::isfinite(rho) || !std::isfinite(alpha))
+    return ctx->fail(ENS_EINVAL, "ens_set_material: need 0 <= nu < 0.5, k >= 0, rho > 0, alpha >= 0");
+  ctx->nu = nu;
+  ctx->shear_k = shear_k;
+  ctx->rho = rho;
+  ctx->alpha = alpha;
+  ctx->have_material = true;
+  ctx->bound = false;
+  ctx->state_init = false;
+  return ENS_OK;
+}
+
+int32_t ens_set_ensemble(ens_ctx* ctx, int32_t S, const double* eh, const double* h) {
+  if (!ctx) return ENS_EINVAL;
+  GUARD_BEGIN
+  if (!ctx->have_mesh) return ctx->fail(ENS_ESTATE, "ens_set_ensemble: set the mesh first");
+  if (S < 1 || !eh || !h) return ctx->fail(ENS_EINVAL, "ens_set_ensemble: need S >= 1 and non-null arrays");
+  const int64_t n = ctx->n_el * (int64_t)S;
+  for (int64_t i = 0; i < n; ++i)
+    if (!(eh[i] > 0.0) || !(h[i] > 0.0) || !std::isfinite(eh[i]) || !std::isfinite(h[i]))
+      return ctx->fail(ENS_EINVAL, "ens_set_ensemble: (E h) and h must be finite and positive (entry " +
+                                       std::to_string(i) + ")");
+  ctx->S = S;
+  ctx->SB = pick_sample_block(S, ctx->tune_sb);
+  ctx->ld = ((S + ctx->SB - 1) / ctx->SB) * ctx->SB;
+  pad_rows(eh, ctx->n_el, S, ctx->ld, ctx->eh);
+  pad_rows(h, ctx->n_el, S, ctx->ld, ctx->h);
+  bool shared = true;
+  for (int64_t e = 0; e < ctx->n_el && shared; ++e)
+    for (int s = 1; s < S; ++s)
+      if (eh[e * S + s] != eh[e * S]) { shared = false; break; }
+  ctx->shared = shared;
+  ctx->have_ens = true;
+  ctx->bound = false;
+  ctx->state_init = false;
+  return ENS_OK;
+  GUARD_END
+}
+
+int32_t ens_set_load(ens_ctx* ctx, const double* F, ens_schedule sched) {
+  if (!ctx) return ENS_EINVAL;
+  GUARD_BEGIN
+  if (!ctx->have_mesh) return ctx->fail(ENS_ESTATE, "ens_set_load: set the mesh first");
+  if (!F) return ctx->fail(ENS_EINVAL, "ens_set_load: null load");
+  if (sched.kind < ENS_LOAD_STEP || sched.kind > ENS_LOAD_PULSATILE)
+    return ctx->fail(ENS_EINVAL, "ens_set_load: unknown schedule kind");
+  if (sched.kind != ENS_LOAD_STEP && !(sched.t_ramp > 0.0))
+    return ctx->fail(ENS_EINVAL, "ens_set_load: ramp time must be positive");
+  if (sched.kind == ENS_LOAD_PULSATILE && !(sched.period > 0.0))
+    return ctx->fail(ENS_EINVAL, "ens_set_load: period must be positive");
+  for (int64_t i = 0; i < 3 * ctx->n_nodes; ++i)
+    if (!std::isfinite(F[i])) return ctx->fail(ENS_EINVAL, "ens_set_load: non-finite load");
+  ctx->F.assign(F, F + 3 * ctx->n_nodes);
+  ctx->sched = Schedule{sched.kind, sched.t_ramp, sched.amp, sched.period};
+  ctx->have_load = true;
+  if (ctx->bound) {
+    hipError_t e = hipMemcpy(ctx->p<void>(ctx->L.F), ctx->F.data(), sizeof(double) * 3 * ctx->n_nodes,
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) return ctx->fail(ENS_EDEVICE, hipGetErrorString(e));
+  }
+  return ENS_OK;
+  GUARD_END
+}
+
+int32_t ens_configure(ens_ctx* ctx, int32_t apply_prec, int32_t state_prec, int32_t variant,
+                      int32_t qoi_mask, int32_t energy_every) {
+  if (!ctx) return ENS_EINVAL;
+  if (apply_prec != ENS_F64 && apply_prec != ENS_F32)
+    return ctx->fail(ENS_EINVAL, "ens_configure: apply_prec must be ENS_F64 or ENS_F32");
+  if (state_prec < ENS_STATE_F64 || state_prec > ENS_STATE_F32)
+    return ctx->fail(ENS_EINVAL, "ens_configure: unknown state precision");
+  if (state_prec != ENS_STATE_F64 && apply_prec != ENS_F32)
+    return ctx->fail(ENS_EUNSUPPORTED, "ens_configure: FP32 states need the FP32 apply");
+  if (variant != ENS_VARIANT_AUTO && variant != ENS_VARIANT_NODE_GATHER)
+    return ctx->fail(ENS_EUNSUPPORTED, "ens_configure: variant not available");
+  if (qoi_mask & ~ENS_QOI_PEAK_RADIAL) return ctx->fail(ENS_EINVAL, "ens_configure: unknown QoI bit");
+  if (energy_every < 0) return ctx->fail(ENS_EINVAL, "ens_configure: energy_every must be >= 0");
+  const bool relayout = state_prec != ctx->state_prec;
+  ctx->apply_prec = apply_prec;
+  ctx->state_prec = state_prec;
+  ctx->variant = variant;
+  ctx->qoi_mask = qoi_mask;
+  ctx->energy_every = energy_every;
+  if (relayout) {
+    ctx->bound = false;
+    ctx->state_init = false;
+  }
+  return ENS_OK;
+}
+
+int32_t ens_set_tuning(ens_ctx* ctx, int32_t sample_block, int32_t sb_inner);
+
+int32_t ens_workspace_size(ens_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return ENS_EINVAL;
+  std::string why;
+  if (!ready_for_workspace(ctx, &why)) return ctx->fail(ENS_ESTATE, "ens_workspace_size: " + why);
+  *bytes = plan(ctx).total;
+  return ENS_OK;
+}
+
+int32_t ens_bind_workspace(ens_ctx* ctx, void* dptr, size_t bytes) {
+  if (!ctx) return ENS_EINVAL;
+  GUARD_BEGIN
+  std::string why;
+  if (!ready_for_workspace(ctx, &why)) return ctx->fail(ENS_ESTATE, "ens_bind_workspace: " + why);
+  const Layout L = plan(ctx);
+  if (!dptr || (reinterpret_cast<uintptr_t>(dptr) % kAlign) != 0)
+    return ctx->fail(ENS_EWORKSPACE, "ens_bind_workspace: null or unaligned (256 B) buffer");
+  if (bytes < L.total)
+    return ctx->fail(ENS_EWORKSPACE, "ens_bind_workspace: need " + std::to_string(L.total) + " bytes, got " +
+                                         std::to_string(bytes));
+  HIPC(hipSetDevice(ctx->device));
+  ctx->ws = static_cast<char*>(dptr);
+  ctx->ws_bytes = bytes;
+  ctx->L = L;
+  ctx->bound = false;
+  ctx->state_init = false;
+  const int32_t rc = upload_all(ctx);
+  if (rc != ENS_OK) return rc;
+  ctx->bound = true;
+  return ENS_OK;
+  GUARD_END
+}
+
+int32_t ens_cfl_dt(ens_ctx* ctx, double safety, double* dt_out) {
+  if (!ctx || !dt_out) return ENS_EINVAL;
+  if (!ctx->bound) return ctx->fail(ENS_EWORKSPACE, "ens_cfl_dt: bind a workspace first");
+  if (!(safety > 0.0)) return ctx->fail(ENS_EINVAL, "ens_cfl_dt: safety must be positive");
+  *dt_out = safety * 2.0 / std::sqrt(ctx->omega2);
+  return ENS_OK;
+}
+
+int32_t ens_init_state(ens_ctx* ctx, const double* u0, const double* v0) {
+  if (!ctx) return ENS_EINVAL;
+  GUARD_BEGIN
+  if (!ctx->bound) return ctx->fail(ENS_EWORKSPACE, "ens_init_state: bind a workspace first");
+  const Layout& L = ctx->L;
+  const int64_t ndof = 3 * ctx->n_nodes, ld = ctx->ld, n = ndof * ld;
+  std::vector<double> buf;
+  hipStream_t st = nullptr;
+  ctx->u0_zero = (u0 == nullptr);
+  if (u0)
+    for (int64_t i = 0; i < ndof * ctx->S; ++i)
+      if (!std::isfinite(u0[i]) || (v0 && !std::isfinite(v0[i])))
+        return ctx->fail(ENS_EINVAL, "ens_init_state: non-finite initial state");
+  if (ctx->state_prec == ENS_STATE_F64) {
+    if (u0) {
+      pad_rows(u0, ndof, ctx->S, (int)ld, buf);
+      HIPC(hipMemcpy(ctx->p<void>(L.u[0]), buf.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+    } else {
+      HIPC(hipMemset(ctx->p<void>(L.u[0]), 0, sizeof(double) * n));
+    }
+    if (v0) {
+      pad_rows(v0, ndof, ctx->S, (int)ld, buf);
+      HIPC(hipMemcpy(ctx->p<void>(L.u[1]), buf.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+    } else {
+      HIPC(hipMemset(ctx->p<void>(L.u[1]), 0, sizeof(double) * n));
+    }
+    HIPC(launch_qoi_init((int32_t)ctx->n_nodes, (int32_t)ld, ctx->p<double>(L.radial),
+                         ctx->p<double>(L.u[0]), nullptr, nullptr, ctx->p<double>(L.q), st));
+  } else {
+    float* uc = ctx->state_prec == ENS_STATE_F32_KAHAN ? ctx->p<float>(L.uc) : nullptr;
+    if (u0) {
+      pad_rows(u0, ndof, ctx->S, (int)ld, buf);
+      HIPC(hipMemcpy(ctx->p<void>(L.aux), buf.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+      HIPC(launch_split_f32(n, ctx->p<double>(L.aux), ctx->p<float>(L.uh[0]), uc, st));
+    } else {
+      HIPC(hipMemset(ctx->p<void>(L.uh[0]), 0, sizeof(float) * n));
+      if (uc) HIPC(hipMemset(uc, 0, sizeof(float) * n));
+    }
+    if (v0) {
+      pad_rows(v0, ndof, ctx->S, (int)ld, buf);
+      HIPC(hipMemcpy(ctx->p<void>(L.aux), buf.data(), sizeof(double) * n, hipMemcpyHostToDevice));
+      HIPC(launch_cast_f32(n, ctx->p<double>(L.aux), ctx->p<float>(L.v), st));
+    } else {
+      HIPC(hipMemset(ctx->p<void>(L.v), 0, sizeof(float) * n));
+    }
+    HIPC(launch_qoi_init((int32_t)ctx->n_nodes, (int32_t)ld, ctx->p<double>(L.radial), nullptr,
+                         ctx->p<float>(L.uh[0]), uc, ctx->p<double>(L.q), st));
+  }
+  HIPC(hipMemset(ctx->p<void>(L.base), 0, sizeof(int64_t)));
+  HIPC(hipDeviceSynchronize());
+  ctx->cur = 0;
+  ctx->steps = 0;
+  ctx->dt = 0.0;
+  ctx->started = false;
+  ctx->energy_records = 0;
+  ctx->energy_steps.assign(kEnergyCap, -1);
+  ctx->state_init = true;
+  return ENS_OK;
+  GUARD_END
+}
+
+namespace {
+
+int32_t run_starter(ens_ctx* ctx, double dt, hipStream_t st) {
+  const Layout& L = ctx->L;
+  const int64_t n = 3 * ctx->n_nodes * (int64_t)ctx->ld;
+  if (ctx->state_prec == ENS_STATE_F64) {
+    double* R = ctx->p<double>(L.aux);
+    if (ctx->u0_zero) {
+      HIPC(hipMemsetAsync(R, 0, sizeof(double) * n, st));
+    } else {
+      StepArgs a = base_args(ctx, false);
+      HIPC(launch_apply(a, false, ctx->SB, ctx->p<double>(L.u[ctx->cur]), R, st));
+    }
+    HIPC(launch_starter_f64((int32_t)ctx->n_nodes, ctx->ld, R, ctx->p<double>(L.minv64), ctx->p<double>(L.F),
+                            ctx->p<uint8_t>(L.fixed), ctx->p<double>(L.u[ctx->cur]),
+                            ctx->p<double>(L.u[1 - ctx->cur]), ctx->p<double>(L.gtab), dt, ctx->alpha, st));
+  } else {
+    float* R = ctx->p<float>(L.aux);
+    if (ctx->u0_zero) {
+      HIPC(hipMemsetAsync(R, 0, sizeof(float) * n, st));
+    } else {
+      StepArgs a = base_args(ctx, true);
+      HIPC(launch_apply(a, true, ctx->SB, ctx->p<float>(L.uh[ctx->cur]), R, st));
+    }
+    HIPC(launch_starter_f32((int32_t)ctx->n_nodes, ctx->ld, R, ctx->p<float>(L.minv32), ctx->p<double>(L.F),
+                            ctx->p<uint8_t>(L.fixed), ctx->p<float>(L.v), ctx->p<double>(L.gtab), dt,
+                            ctx->alpha, st));
+  }
+  return ENS_OK;
+}
+
+}  // namespace
+
+int32_t ens_step(ens_ctx* ctx, int64_t n_steps, double dt, int32_t force, void* stream) {
+  if (!ctx) return ENS_EINVAL;
+  GUARD_BEGIN
+  if (!ctx->bound) return ctx->fail(ENS_EWORKSPACE, "ens_step: bind a workspace first");
+  if (!ctx->have_load) return ctx->fail(ENS_ESTATE, "ens_step: load not set");
+  if (!ctx->have_material) return ctx->fail(ENS_ESTATE, "ens_step: material not set");
+  if (!ctx->state_init) return ctx->fail(ENS_ESTATE, "ens_step: call ens_init_state first");
+  if (n_steps < 0) return ctx->fail(ENS_EINVAL, "ens_step: n_steps must be >= 0");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return ctx->fail(ENS_EINVAL, "ens_step: dt must be positive");
+  if (ctx->started && dt != ctx->dt)
+    return ctx->fail(ENS_EINVAL, "ens_step: dt is fixed once stepping has started (re-init the state to change it)");
+  const double dt_max = 2.0 / std::sqrt(ctx->omega2);
+  if (dt > dt_max && !force)
+    return ctx->fail(ENS_EUNSTABLE, "ens_step: dt " + std::to_string(dt) + " exceeds the stability bound " +
+                                        std::to_string(dt_max));
+  HIPC(hipSetDevice(ctx->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  ctx->last_stream = st;
+  const Layout& L = ctx->L;
+  const bool f32 = ctx->apply_prec == ENS_F32;
+  const bool qoi = (ctx->qoi_mask & ENS_QOI_PEAK_RADIAL) != 0;
+  StepArgs a = base_args(ctx, f32);
+  a.dt = dt;
+  a.a = 0.5 * ctx->alpha * dt;
+  int64_t left = n_steps;
+  while (left > 0) {
+    const int k = (int)std::min<int64_t>(left, kChunk);
+    HIPC(launch_schedule(ctx->p<double>(L.gtab), ctx->p<int64_t>(L.base), k, dt, ctx->sched, st));
+    if (!ctx->started) {
+      const int32_t rc = run_starter(ctx, dt, st);
+      if (rc != ENS_OK) return rc;
+      ctx->started = true;
+      ctx->dt = dt;
+    }
+    for (int j = 0; j < k; ++j) {
+      const int64_t n = ctx->steps + j;
+      const bool energy = ctx->energy_every > 0 && (n % ctx->energy_every) == 0;
+      a.j = j;
+      if (ctx->state_prec == ENS_STATE_F64) {
+        a.u_cur = ctx->p<double>(L.u[ctx->cur]);
+        a.u_prev = ctx->p<double>(L.u[1 - ctx->cur]);
+        a.u_next = ctx->p<double>(L.u[1 - ctx->cur]);
+      } else {
+        a.uh_cur = ctx->p<float>(L.uh[ctx->cur]);
+        a.uh_next = ctx->p<float>(L.uh[1 - ctx->cur]);
+        a.uc = ctx->state_prec == ENS_STATE_F32_KAHAN ? ctx->p<float>(L.uc) : nullptr;
+        a.v = ctx->p<float>(L.v);
+      }
+      HIPC(launch_step(a, f32, ctx->state_prec, ctx->SB, qoi, energy, st));
+      if (energy) {
+        const int64_t rec = ctx->energy_records % kEnergyCap;
+        HIPC(launch_energy_reduce(ctx->p<double>(L.epart), a.n_nb, ctx->ld, ctx->ld,
+                                  ctx->p<double>(L.erec) + rec * ctx->ld, st));
+        ctx->energy_steps[rec] = n;
+        ctx->energy_records++;
+      }
+      ctx->cur = 1 - ctx->cur;
+    }
+    HIPC(launch_advance(ctx->p<int64_t>(L.base), k, st));
+    ctx->steps += k;
+    left -= k;
+  }
+  return ENS_OK;
+  GUARD_END
+}
+
+int32_t ens_sync(ens_ctx* ctx) {
+  if (!ctx) return ENS_EINVAL;
+  if (!ctx->bound || !ctx->state_init) return ctx->fail(ENS_ESTATE, "ens_sync: nothing to wait for");
+  HIPC(hipSetDevice(ctx->device));
+  HIPC(hipDeviceSynchronize());
+  const Layout& L = ctx->L;
+  Flags* fl = ctx->p<Flags>(L.flags);
+  HIPC(hipMemset(&fl->nonfinite, 0, sizeof(int32_t)));
+  const int64_t n = 3 * ctx->n_nodes * (int64_t)ctx->ld;
+  if (ctx->state_prec == ENS_STATE_F64)
+    HIPC(launch_check_finite(n, ctx->p<double>(L.u[ctx->cur]), 0, &fl->nonfinite, nullptr));
+  else
+    HIPC(launch_check_finite(n, ctx->p<float>(L.uh[ctx->cur]), 1, &fl->nonfinite, nullptr));
+  int32_t bad = 0;
+  HIPC(hipMemcpy(&bad, &fl->nonfinite, sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (bad) return ctx->fail(ENS_ENONFINITE, "ens_sync: non-finite values in the displacement state");
+  return ENS_OK;
+}
+
+int32_t ens_read_state(ens_ctx* ctx, double* u) {
+  if (!ctx || !u) return ENS_EINVAL;
+  GUARD_BEGIN
+  if (!ctx->bound || !ctx->state_init) return ctx->fail(ENS_ESTATE, "ens_read_state: no state");
+  HIPC(hipSetDevice(ctx->device));
+  HIPC(hipDeviceSynchronize());
+  const Layout& L = ctx->L;
+  const int64_t ndof = 3 * ctx->n_nodes, n = ndof * ctx->ld;
+  std::vector<double> buf(n);
+  if (ctx->state_prec == ENS_STATE_F64) {
+    HIPC(hipMemcpy(buf.data(), ctx->p<void>(L.u[ctx->cur]), sizeof(double) * n, hipMemcpyDeviceToHost));
+  } else {
+    const float* uc = ctx->state_prec == ENS_STATE_F32_KAHAN ? ctx->p<float>(L.uc) : nullptr;
+    HIPC(launch_combine_f32(n, ctx->p<float>(L.uh[ctx->cur]), uc, ctx->p<double>(L.aux), nullptr));
+    HIPC(hipMemcpy(buf.data(), ctx->p<void>(L.aux), sizeof(double) * n, hipMemcpyDeviceToHost));
+  }
+  unpad_rows(buf.data(), ndof, ctx->S, ctx->ld, u);
+  return ENS_OK;
+  GUARD_END
+}
+
+int32_t ens_read_qoi(ens_ctx* ctx, int32_t kind, double* out) {
+  if (!ctx || !out) return ENS_EINVAL;
+  GUARD_BEGIN
+  if (kind != ENS_QOI_PEAK_RADIAL) return ctx->fail(ENS_EINVAL, "ens_read_qoi: unknown kind");
+  if (!(ctx->qoi_mask & ENS_QOI_PEAK_RADIAL)) return ctx->fail(ENS_ESTATE, "ens_read_qoi: QoI not enabled");
+  if (!ctx->bound || !ctx->state_init) return ctx->fail(ENS_ESTATE, "ens_read_qoi: no state");
+  HIPC(hipSetDevice(ctx->device));
+  HIPC(hipDeviceSynchronize());
+  const int64_t n = ctx->n_nodes * ctx->ld;
+  std::vector<double> buf(n);
+  HIPC(hipMemcpy(buf.data(), ctx->p<void>(ctx->L.q), sizeof(double) * n, hipMemcpyDeviceToHost));
+  unpad_rows(buf.data(), ctx->n_nodes, ctx->S, ctx->ld, out);
+  return ENS_OK;
+  GUARD_END
+}
+
+int32_t ens_read_energy(ens_ctx* ctx, int64_t max_records, int64_t* steps_out, double* e_out,
+                        int64_t* n_out) {
+  if (!ctx || !n_out || max_records < 0) return ENS_EINVAL;
+  GUARD_BEGIN
+  if (!ctx->bound || !ctx->state_init) return ctx->fail(ENS_ESTATE, "ens_read_energy: no state");
+  HIPC(hipSetDevice(ctx->device));
+  HIPC(hipDeviceSynchronize());
+  const int64_t have = std::min<int64_t>(ctx->energy_records, kEnergyCap);
+  const int64_t take = std::min<int64_t>(have, max_records);
+  *n_out = take;
+  if (take == 0) return ENS_OK;
+  if (!steps_out || !e_out) return ctx->fail(ENS_EINVAL, "ens_read_energy: null output");
+  std::vector<double> row(ctx->ld);
+  for (int64_t k = 0; k < take; ++k) {
+    const int64_t r = ctx->energy_records - take + k;
+    const int64_t slot = r % kEnergyCap;
+    HIPC(hipMemcpy(row.data(), ctx->p<double>(ctx->L.erec) + slot * ctx->ld, sizeof(double) * ctx->ld,
+                   hipMemcpyDeviceToHost));
+    std::memcpy(e_out + k * ctx->S, row.data(), sizeof(double) * ctx->S);
+    steps_out[k] = ctx->energy_steps[slot];
+  }
+  return ENS_OK;
+  GUARD_END
+}
+
+int32_t ens_moments(ens_ctx* ctx, double* mean, double* var) {
+  if (!ctx || !mean || !var) return ENS_EINVAL;
+  if (!(ctx->qoi_mask & ENS_QOI_PEAK_RADIAL)) return ctx->fail(ENS_ESTATE, "ens_moments: QoI not enabled");
+  if (!ctx->bound || !ctx->state_init) return ctx->fail(ENS_ESTATE, "ens_moments: no state");
+  HIPC(hipSetDevice(ctx->device));
+  HIPC(hipDeviceSynchronize());
+  const Layout& L = ctx->L;
+  HIPC(launch_moments((int32_t)ctx->n_nodes, ctx->ld, ctx->S, ctx->p<double>(L.q), ctx->p<double>(L.mean),
+                      ctx->p<double>(L.var), nullptr));
+  HIPC(hipMemcpy(mean, ctx->p<void>(L.mean), sizeof(double) * ctx->n_nodes, hipMemcpyDeviceToHost));
+  HIPC(hipMemcpy(var, ctx->p<void>(L.var), sizeof(double) * ctx->n_nodes, hipMemcpyDeviceToHost));
+  return ENS_OK;
+}
+
+int32_t ens_apply(ens_ctx* ctx, int32_t prec, const void* U_dev, void* R_dev, void* stream) {
+  if (!ctx) return ENS_EINVAL;
+  if (!ctx->bound) return ctx->fail(ENS_EWORKSPACE, "ens_apply: bind a workspace first");
+  if (prec != ENS_F64 && prec != ENS_F32) return ctx->fail(ENS_EINVAL, "ens_apply: prec must be ENS_F64 or ENS_F32");
+  if (!U_dev || !R_dev) return ctx->fail(ENS_EINVAL, "ens_apply: null device buffer");
+  HIPC(hipSetDevice(ctx->device));
+  StepArgs a = base_args(ctx, prec == ENS_F32);
+  HIPC(launch_apply(a, prec == ENS_F32, ctx->SB, U_dev, R_dev, static_cast<hipStream_t>(stream)));
+  return ENS_OK;
+}
+
+namespace {
+struct CkptHeader {
+  uint64_t magic;
+  int64_t n_dof, ld, S, state_prec, steps, started, u0_zero;
+  double dt;
+};
+constexpr uint64_t kMagic = 0x31764b43464e45ull;  // "ENFCKv1"
+}  // namespace
+
+int32_t ens_save(ens_ctx* ctx, void* host, size_t* bytes) {
+  if (!ctx || !bytes) return ENS_EINVAL;
+  GUARD_BEGIN
+  if (!ctx->bound || !ctx->state_init) return ctx->fail(ENS_ESTATE, "ens_save: no state");
+  const Layout& L = ctx->L;
+  const int64_t n = 3 * ctx->n_nodes * (int64_t)ctx->ld, nq = ctx->n_nodes * (int64_t)ctx->ld;
+  const bool f64 = ctx->state_prec == ENS_STATE_F64;
+  const size_t state_bytes = f64 ? 2 * sizeof(double) * n : 3 * sizeof(float) * n;
+  const size_t need = sizeof(CkptHeader) + state_bytes + sizeof(double) * nq;
+  if (!host) {
+    *bytes = need;
+    return ENS_OK;
+  }
+  if (*bytes < need) return ctx->fail(ENS_EINVAL, "ens_save: buffer too small");
+  HIPC(hipSetDevice(ctx->device));
+  HIPC(hipDeviceSynchronize());
+  char* o = static_cast<char*>(host);
+  CkptHeader hd{kMagic, 3 * ctx->n_nodes, ctx->ld, ctx->S, ctx->state_prec, ctx->steps, ctx->started ? 1 : 0,
+                ctx->u0_zero ? 1 : 0, ctx->dt};
+  std::memcpy(o, &hd, sizeof hd);
+  o += sizeof hd;
+  if (f64) {
+    HIPC(hipMemcpy(o, ctx->p<void>(L.u[ctx->cur]), sizeof(double) * n, hipMemcpyDeviceToHost));
+    o += sizeof(double) * n;
+    HIPC(hipMemcpy(o, ctx->p<void>(L.u[1 - ctx->cur]), sizeof(double) * n, hipMemcpyDeviceToHost));
+    o += sizeof(double) * n;
+  } else {
+    HIPC(hipMemcpy(o, ctx->p<void>(L.uh[ctx->cur]), sizeof(float) * n, hipMemcpyDeviceToHost));
+    o += sizeof(float) * n;
+    if (L.uc && ctx->state_prec == ENS_STATE_F32_KAHAN)
+      HIPC(hipMemcpy(o, ctx->p<void>(L.uc), sizeof(float) * n, hipMemcpyDeviceToHost));
+    else
+      std::memset(o, 0, sizeof(float) * n);
+    o += sizeof(float) * n;
+    HIPC(hipMemcpy(o, ctx->p<void>(L.v), sizeof(float) * n, hipMemcpyDeviceToHost));
+    o += sizeof(float) * n;
+  }
+  HIPC(hipMemcpy(o, ctx->p<void>(L.q), sizeof(double) * nq, hipMemcpyDeviceToHost));
+  *bytes = need;
+  return ENS_OK;
+  GUARD_END
+}
+
+int32_t ens_load(ens_ctx* ctx, const void* host, size_t bytes) {
+  if (!ctx || !host) return ENS_EINVAL;
+  GUARD_BEGIN
+  if (!ctx->bound) return ctx->fail(ENS_EWORKSPACE, "ens_load: bind a workspace first");
+  if (bytes < sizeof(CkptHeader)) return ctx->fail(ENS_EINVAL, "ens_load: truncated checkpoint");
+  CkptHeader hd;
+  std::memcpy(&hd, host, sizeof hd);
+  const int64_t n = 3 * ctx->n_nodes * (int64_t)ctx->ld, nq = ctx->n_nodes * (int64_t)ctx->ld;
+  if (hd.magic != kMagic || hd.n_dof != 3 * ctx->n_nodes || hd.ld != ctx->ld || hd.S != ctx->S ||
+      hd.state_prec != ctx->state_prec)
+    return ctx->fail(ENS_EINVAL, "ens_load: checkpoint does not match this context");
+  const bool f64 = ctx->state_prec == ENS_STATE_F64;
+  const size_t need = sizeof(CkptHeader) + (f64 ? 2 * sizeof(double) * n : 3 * sizeof(float) * n) + sizeof(double) * nq;
+  if (bytes < need) return ctx->fail(ENS_EINVAL, "ens_load: truncated checkpoint");
+  HIPC(hipSetDevice(ctx->device));
+  HIPC(hipDeviceSynchronize());
+  const Layout& L = ctx->L;
+  const char* o = static_cast<const char*>(host) + sizeof hd;
+  ctx->cur = 0;
+  if (f64) {
+    HIPC(hipMemcpy(ctx->p<void>(L.u[0]), o, sizeof(double) * n, hipMemcpyHostToDevice));
+    o += sizeof(double) * n;
+    HIPC(hipMemcpy(ctx->p<void>(L.u[1]), o, sizeof(double) * n, hipMemcpyHostToDevice));
+    o += sizeof(double) * n;
+  } else {
+    HIPC(hipMemcpy(ctx->p<void>(L.uh[0]), o, sizeof(float) * n, hipMemcpyHostToDevice));
+    o += sizeof(float) * n;
+    if (ctx->state_prec == ENS_STATE_F32_KAHAN)
+      HIPC(hipMemcpy(ctx->p<void>(L.uc), o, sizeof(float) * n, hipMemcpyHostToDevice));
+    o += sizeof(float) * n;
+    HIPC(hipMemcpy(ctx->p<void>(L.v), o, sizeof(float) * n, hipMemcpyHostToDevice));
+    o += sizeof(float) * n;
+  }
+  HIPC(hipMemcpy(ctx->p<void>(L.q), o, sizeof(double) * nq, hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(ctx->p<void>(L.base), &hd.steps, sizeof(int64_t), hipMemcpyHostToDevice));
+  HIPC(hipDeviceSynchronize());
+  ctx->steps = hd.steps;
+  ctx->started = hd.started != 0;
+  ctx->u0_zero = hd.u0_zero != 0;
+  ctx->dt = hd.dt;
+  ctx->energy_records = 0;
+  ctx->energy_steps.assign(kEnergyCap, -1);
+  ctx->state_init = true;
+  return ENS_OK;
+  GUARD_END
+}
+
+int32_t ens_set_tuning(ens_ctx* ctx, int32_t sample_block, int32_t sb_inner) {
+  if (!ctx) return ENS_EINVAL;
+  if (sample_block != 0 && sample_block != 8 && sample_block != 16 && sample_block != 32 && sample_block != 64)
+    return ctx->fail(ENS_EINVAL, "ens_set_tuning: sample block must be 0 (auto), 8, 16, 32 or 64");
+  ctx->tune_sb = sample_block;
+  ctx->sb_inner = sb_inner ? 1 : 0;
+  if (ctx->have_ens) {
+    const int sb = pick_sample_block(ctx->S, sample_block);
+    const int ld = ((ctx->S + sb - 1) / sb) * sb;
+    if (sb != ctx->SB) {
+      // the padded width may change: re-pad the fields, drop the binding
+      std::vector<double> eh(ctx->n_el * (int64_t)ctx->S), h(eh.size());
+      unpad_rows(ctx->eh.data(), ctx->n_el, ctx->S, ctx->ld, eh.data());
+      unpad_rows(ctx->h.data(), ctx->n_el, ctx->S, ctx->ld, h.data());
+      ctx->SB = sb;
+      ctx->ld = ld;
+      pad_rows(eh.data(), ctx->n_el, ctx->S, ld, ctx->eh);
+      pad_rows(h.data(), ctx->n_el, ctx->S, ld, ctx->h);
+      ctx->bound = false;
+      ctx->state_init = false;
+    }
+  }
+  return ENS_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,107 @@
+// Internal declarations shared by the host API and the kernel translation
+// units of libensfem.  Each .hip file launches only its own kernels through
+// the launch_* wrappers declared here, so no relocatable device code is
+// needed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ensfem {
+
+constexpr int kBlock = 256;       // threads per workgroup for the ensemble kernels
+constexpr int kEnergyCap = 4096;  // energy records kept (ring)
+
+// Load-schedule kinds (mirror the public enum).
+struct Schedule {
+  int kind;
+  double t_ramp, amp, period;
+};
+
+// Node-gather adjacency: for node i, entries adj_ptr[i] .. adj_ptr[i+1]-1,
+// one per incident element e, with the element's other two nodes (b, c) in
+// cyclic order after i and the 3x6 block [Khat_ib | Khat_ic] (global frame).
+struct Adjacency {
+  const int32_t* ptr;
+  const int32_t* el;
+  const int2* nb;
+  const void* k;  // double[18] or float[18] per entry
+};
+
+// State storage modes.
+enum StateMode { kStateF64 = 0, kStateF32Kahan = 1, kStateF32 = 2 };
+
+struct StepArgs {
+  int32_t n_nodes;
+  int32_t ld;          // padded sample count (row stride of every ensemble array)
+  int32_t n_nb;        // node blocks
+  int32_t n_sb;        // sample blocks
+  int32_t sb_inner;    // workgroup order: sample block fastest (1) or node block fastest (0)
+  Adjacency adj;
+  const void* eh;      // (E h)_{e,s} in the apply precision, [n_el][ld]
+  const void* minv;    // 1/m per node and sample, double (F64 apply) or float, [n_nodes][ld]
+  const double* F;     // nodal load [n_nodes][3]
+  const uint8_t* fixed;   // clamped-dof bits per node
+  const double* radial;   // [n_nodes][3]
+  // FP64 two-level state
+  const double* u_cur;
+  const double* u_prev;
+  double* u_next;
+  // FP32 velocity-form state
+  const float* uh_cur;
+  float* uh_next;
+  float* uc;           // Kahan compensation (in place)
+  float* v;            // velocity v_{n-1/2} -> v_{n+1/2} (in place)
+  double* q;           // running peak radial displacement [n_nodes][ld]
+  const double* gtab;  // load factors of the current chunk
+  int32_t j;           // index into gtab
+  double dt, a;        // step, alpha dt / 2
+  double* energy_part; // [n_nb][ld] per node-block energy partial sums
+};
+
+// ---- set-up kernels (setup.hip) -------------------------------------------
+hipError_t launch_element_setup(int64_t n_el, const double* xyz, const int32_t* tri, double nu,
+                                double shear_k, double* khat, double* area, double* lam,
+                                int32_t* bad, hipStream_t st);
+hipError_t launch_adjacency_blocks(int64_t n_adj, const int32_t* adj_el, const uint8_t* adj_loc,
+                                   const double* khat, double* k64, float* k32, hipStream_t st);
+hipError_t launch_lumped_mass(int32_t n_nodes, int32_t ld, const int32_t* adj_ptr,
+                              const int32_t* adj_el, const double* area, const double* h, double rho,
+                              double* minv64, float* minv32, hipStream_t st);
+hipError_t launch_cfl_max(int64_t n_el, int32_t ld, int32_t S, const double* eh, const double* h,
+                          const double* lam, const double* area, double rho,
+                          unsigned long long* out_bits, hipStream_t st);
+hipError_t launch_cast_f32(int64_t n, const double* src, float* dst, hipStream_t st);
+
+// ---- time-stepping kernels (step.hip) -------------------------------------
+// One explicit step of the node-gather fused kernel.  apply_f32 selects
+// the apply precision; mode the state storage; qoi / energy the outputs.
+hipError_t launch_step(const StepArgs& a, bool apply_f32, int mode, int sample_block, bool qoi,
+                       bool energy, hipStream_t st);
+hipError_t launch_apply(const StepArgs& a, bool f32, int sample_block, const void* U, void* R,
+                        hipStream_t st);
+hipError_t launch_schedule(double* gtab, int64_t* base, int32_t k, double dt, Schedule s,
+                           hipStream_t st);
+hipError_t launch_advance(int64_t* base, int32_t k, hipStream_t st);
+hipError_t launch_energy_reduce(const double* part, int32_t n_nb, int32_t ld, int32_t S,
+                                double* out_row, hipStream_t st);
+hipError_t launch_starter_f64(int32_t n_nodes, int32_t ld, const double* R, const double* minv,
+                              const double* F, const uint8_t* fixed, const double* u0,
+                              double* vprev_io, const double* gtab, double dt, double alpha,
+                              hipStream_t st);
+hipError_t launch_starter_f32(int32_t n_nodes, int32_t ld, const float* R, const float* minv,
+                              const double* F, const uint8_t* fixed, float* v_io,
+                              const double* gtab, double dt, double alpha, hipStream_t st);
+hipError_t launch_split_f32(int64_t n, const double* u0, float* uh, float* uc, hipStream_t st);
+hipError_t launch_qoi_init(int32_t n_nodes, int32_t ld, const double* radial, const double* u_f64,
+                           const float* uh, const float* uc, double* q, hipStream_t st);
+hipError_t launch_combine_f32(int64_t n, const float* uh, const float* uc, double* out,
+                              hipStream_t st);
+hipError_t launch_moments(int32_t n_nodes, int32_t ld, int32_t S, const double* q, double* mean,
+                          double* var, hipStream_t st);
+hipError_t launch_check_finite(int64_t n, const void* x, int is_f32, int32_t* flag,
+                               hipStream_t st);
+
+}  // namespace ensfem

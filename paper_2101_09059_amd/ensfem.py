@@ -1,0 +1,283 @@
+"""ctypes binding of libensfem (include/ensfem.h): argument marshalling only.
+
+Every step of the method runs in the HIP library; this module converts
+numpy / torch arguments to pointers, allocates the device workspace with
+torch (device memory is the only thing torch is used for, besides handing
+over its current stream) and turns error codes into exceptions.  If the
+library has not been built, importing works but creating a context raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libensfem.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "ensfem.h")
+
+ENS_OK, ENS_EINVAL, ENS_ESTATE, ENS_EWORKSPACE, ENS_EDEVICE, ENS_EUNSTABLE, ENS_ENONFINITE, \
+    ENS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+F64, F32 = 0, 1
+STATE_F64, STATE_F32_KAHAN, STATE_F32 = 0, 1, 2
+VARIANT_AUTO, VARIANT_NODE_GATHER, VARIANT_CSR_SHARED = 0, 1, 3
+LOAD_STEP, LOAD_RAMP_SINE, LOAD_PULSATILE = 0, 1, 2
+QOI_PEAK_RADIAL = 1
+
+_CODES = {ENS_EINVAL: "EINVAL", ENS_ESTATE: "ESTATE", ENS_EWORKSPACE: "EWORKSPACE",
+          ENS_EDEVICE: "EDEVICE", ENS_EUNSTABLE: "EUNSTABLE", ENS_ENONFINITE: "ENONFINITE",
+          ENS_EUNSUPPORTED: "EUNSUPPORTED"}
+
+
+class EnsfemError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{_CODES.get(code, code)}: {message}")
+        self.code = code
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("t_ramp", ctypes.c_double), ("amp", ctypes.c_double),
+                ("period", ctypes.c_double)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("n_el", ctypes.c_int64), ("n_dof", ctypes.c_int64),
+                ("S", ctypes.c_int32), ("S_pad", ctypes.c_int32), ("sample_block", ctypes.c_int32),
+                ("apply_prec", ctypes.c_int32), ("state_prec", ctypes.c_int32),
+                ("variant", ctypes.c_int32), ("shared_stiffness", ctypes.c_int32),
+                ("steps_done", ctypes.c_int64), ("dt", ctypes.c_double),
+                ("workspace_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+
+_P = ctypes.c_void_p
+_I32, _I64, _D, _SZ = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+_SIGS = {
+    "ens_create": (_I32, [_I32, ctypes.POINTER(_P)]),
+    "ens_destroy": (_I32, [_P]),
+    "ens_last_error": (ctypes.c_char_p, [_P]),
+    "ens_info": (_I32, [_P, ctypes.POINTER(Info)]),
+    "ens_set_mesh": (_I32, [_P, _I64, _P, _I64, _P, _P, _P]),
+    "ens_set_material": (_I32, [_P, _D, _D, _D, _D]),
+    "ens_set_ensemble": (_I32, [_P, _I32, _P, _P]),
+    "ens_set_load": (_I32, [_P, _P, Schedule]),
+    "ens_configure": (_I32, [_P, _I32, _I32, _I32, _I32, _I32]),
+    "ens_set_tuning": (_I32, [_P, _I32, _I32]),
+    "ens_workspace_size": (_I32, [_P, ctypes.POINTER(_SZ)]),
+    "ens_bind_workspace": (_I32, [_P, _P, _SZ]),
+    "ens_cfl_dt": (_I32, [_P, _D, ctypes.POINTER(_D)]),
+    "ens_init_state": (_I32, [_P, _P, _P]),
+    "ens_step": (_I32, [_P, _I64, _D, _I32, _P]),
+    "ens_sync": (_I32, [_P]),
+    "ens_read_state": (_I32, [_P, _P]),
+    "ens_read_qoi": (_I32, [_P, _I32, _P]),
+    "ens_read_energy": (_I32, [_P, _I64, _P, _P, ctypes.POINTER(_I64)]),
+    "ens_moments": (_I32, [_P, _P, _P]),
+    "ens_apply": (_I32, [_P, _I32, _P, _P, _P]),
+    "ens_save": (_I32, [_P, _P, ctypes.POINTER(_SZ)]),
+    "ens_load": (_I32, [_P, _P, _SZ]),
+}
+
+
+def header_functions() -> list:
+    """Names of the functions include/ensfem.h declares."""
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ens_[a-z_]+)\s*\(", txt)) - {"ens_ctx"})
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libensfem.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"libensfem.so not built at {path}: run python -m paper_2101_09059_amd.build")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _SIGS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class Ensemble:
+    """One mesh stepped for S samples at once (a libensfem context)."""
+
+    def __init__(self, device: int = 0):
+        self._lib = load_library()
+        self.device = device
+        h = _P()
+        rc = self._lib.ens_create(device, ctypes.byref(h))
+        if rc != ENS_OK:
+            raise EnsfemError(rc, f"ens_create(device={device}) failed")
+        self._h = h
+        self._ws = None
+        self.n_nodes = self.n_el = self.S = 0
+
+    # ---- plumbing -------------------------------------------------------
+    def _check(self, rc: int):
+        if rc != ENS_OK:
+            msg = self._lib.ens_last_error(self._h)
+            raise EnsfemError(rc, msg.decode() if msg else "")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ens_destroy(self._h)
+            self._h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        inf = Info()
+        self._check(self._lib.ens_info(self._h, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in Info._fields_}
+
+    # ---- set-up ---------------------------------------------------------
+    def set_mesh(self, xyz, tri, fixed, radial):
+        xyz, radial = _f64(xyz), _f64(radial)
+        tri = np.ascontiguousarray(tri, dtype=np.int32)
+        fixed = np.ascontiguousarray(fixed, dtype=np.uint8)
+        self._check(self._lib.ens_set_mesh(self._h, xyz.shape[0], _ptr(xyz), tri.shape[0], _ptr(tri),
+                                           _ptr(fixed), _ptr(radial)))
+        self.n_nodes, self.n_el = xyz.shape[0], tri.shape[0]
+
+    def set_material(self, nu: float, shear_k: float, rho: float, alpha: float):
+        self._check(self._lib.ens_set_material(self._h, nu, shear_k, rho, alpha))
+
+    def set_ensemble(self, eh, h):
+        eh, h = _f64(eh), _f64(h)
+        if eh.shape != h.shape or eh.ndim != 2:
+            raise ValueError("eh and h must both be [n_el, S]")
+        self._check(self._lib.ens_set_ensemble(self._h, eh.shape[1], _ptr(eh), _ptr(h)))
+        self.S = eh.shape[1]
+
+    def set_load(self, F, kind: int = LOAD_STEP, t_ramp: float = 0.0, amp: float = 0.0,
+                 period: float = 1.0):
+        F = _f64(F)
+        self._check(self._lib.ens_set_load(self._h, _ptr(F), Schedule(kind, t_ramp, amp, period)))
+
+    def configure(self, apply_prec: int = F64, state_prec: int = STATE_F64,
+                  variant: int = VARIANT_AUTO, qoi: bool = True, energy_every: int = 0):
+        self._check(self._lib.ens_configure(self._h, apply_prec, state_prec, variant,
+                                            QOI_PEAK_RADIAL if qoi else 0, energy_every))
+
+    def set_tuning(self, sample_block: int = 0, sb_inner: bool = False):
+        self._check(self._lib.ens_set_tuning(self._h, sample_block, 1 if sb_inner else 0))
+
+    def workspace_size(self) -> int:
+        n = _SZ()
+        self._check(self._lib.ens_workspace_size(self._h, ctypes.byref(n)))
+        return n.value
+
+    def bind_workspace(self, buffer=None):
+        """Bind `buffer` (a CUDA uint8 tensor) or allocate one with torch."""
+        import torch
+        n = self.workspace_size()
+        if buffer is None:
+            buffer = torch.empty(max(n, 1), dtype=torch.uint8, device=f"cuda:{self.device}")
+        self._check(self._lib.ens_bind_workspace(self._h, buffer.data_ptr(), buffer.numel()))
+        self._ws = buffer
+        return buffer
+
+    def cfl_dt(self, safety: float = 0.9) -> float:
+        d = _D()
+        self._check(self._lib.ens_cfl_dt(self._h, safety, ctypes.byref(d)))
+        return d.value
+
+    # ---- stepping -------------------------------------------------------
+    def init_state(self, u0=None, v0=None):
+        a = None if u0 is None else _f64(u0)
+        b = None if v0 is None else _f64(v0)
+        self._check(self._lib.ens_init_state(self._h, None if a is None else _ptr(a),
+                                             None if b is None else _ptr(b)))
+
+    def step(self, n_steps: int, dt: float, force: bool = False, stream=None):
+        self._check(self._lib.ens_step(self._h, int(n_steps), float(dt), 1 if force else 0,
+                                       _stream_handle(stream)))
+
+    def sync(self):
+        self._check(self._lib.ens_sync(self._h))
+
+    # ---- read-back ------------------------------------------------------
+    def read_state(self) -> np.ndarray:
+        out = np.empty((3 * self.n_nodes, self.S))
+        self._check(self._lib.ens_read_state(self._h, _ptr(out)))
+        return out
+
+    def read_qoi(self) -> np.ndarray:
+        out = np.empty((self.n_nodes, self.S))
+        self._check(self._lib.ens_read_qoi(self._h, QOI_PEAK_RADIAL, _ptr(out)))
+        return out
+
+    def read_energy(self, max_records: int = 4096):
+        steps = np.empty(max_records, dtype=np.int64)
+        e = np.empty((max_records, self.S))
+        n = _I64()
+        self._check(self._lib.ens_read_energy(self._h, max_records, _ptr(steps), _ptr(e), ctypes.byref(n)))
+        return steps[:n.value], e[:n.value]
+
+    def moments(self):
+        mean = np.empty(self.n_nodes)
+        var = np.empty(self.n_nodes)
+        self._check(self._lib.ens_moments(self._h, _ptr(mean), _ptr(var)))
+        return mean, var
+
+    def apply(self, U, R, prec: int = F64, stream=None):
+        """R = K(Eh) U on CUDA tensors of shape [n_dof, S_pad]."""
+        self._check(self._lib.ens_apply(self._h, prec, U.data_ptr(), R.data_ptr(), _stream_handle(stream)))
+
+    def save(self) -> bytes:
+        n = _SZ()
+        self._check(self._lib.ens_save(self._h, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        self._check(self._lib.ens_save(self._h, ctypes.addressof(buf), ctypes.byref(n)))
+        return buf.raw[:n.value]
+
+    def load(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        self._check(self._lib.ens_load(self._h, ctypes.addressof(buf), len(blob)))
+
+
+def setup_case(mesh, eh, h, F, nu=0.49, shear_k=5.0 / 6.0, rho=1.0, alpha=50.0,
+               kind=LOAD_STEP, t_ramp=0.0, amp=0.0, period=1.0, apply_prec=F64,
+               state_prec=STATE_F64, qoi=True, energy_every=0, device=0,
+               sample_block=0, sb_inner=False) -> Ensemble:
+    """Create, fill, configure and bind a context for one mesh and ensemble."""
+    ens = Ensemble(device)
+    ens.set_mesh(mesh.xyz, mesh.tri, mesh.fixed, mesh.radial)
+    ens.set_material(nu, shear_k, rho, alpha)
+    ens.set_ensemble(eh, h)
+    ens.set_load(F, kind, t_ramp, amp, period)
+    ens.configure(apply_prec, state_prec, VARIANT_AUTO, qoi, energy_every)
+    if sample_block or sb_inner:
+        ens.set_tuning(sample_block, sb_inner)
+    ens.bind_workspace()
+    return ens

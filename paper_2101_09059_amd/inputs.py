@@ -199,16 +199,21 @@ def matern_nodal_lattice(mesh: Mesh, n_samples: int, rng: np.random.Generator,
     lam = np.fft.fft2(c).real
     lam = np.maximum(lam, 0.0)
     scale = np.sqrt(lam / (mz * nt))
-    out = np.empty((nz * nt, n_samples), dtype=np.float64)
+    out = np.empty((n_samples, nz * nt), dtype=np.float64)
+    batch = 16
     k = 0
     while k < n_samples:
-        z = rng.standard_normal((mz, nt)) + 1j * rng.standard_normal((mz, nt))
-        f = np.fft.fft2(scale * z)
-        out[:, k] = f.real[:nz].reshape(-1)
-        if k + 1 < n_samples:
-            out[:, k + 1] = f.imag[:nz].reshape(-1)
-        k += 2
-    return out
+        b = min(batch, (n_samples - k + 1) // 2)
+        z = rng.standard_normal((b, mz, nt)) + 1j * rng.standard_normal((b, mz, nt))
+        f = np.fft.fft2(scale[None] * z, axes=(1, 2))[:, :nz, :].reshape(b, -1)
+        for i in range(b):
+            if k < n_samples:
+                out[k] = f[i].real
+                k += 1
+            if k < n_samples:
+                out[k] = f[i].imag
+                k += 1
+    return np.ascontiguousarray(out.T)
 
 
 def centroid_average(mesh: Mesh, nodal: np.ndarray) -> np.ndarray:

@@ -1,0 +1,57 @@
+"""Workload set-ups shared by the GPU tests: the same seeded inputs go to
+the HIP path and to the oracle; the oracle also supplies the step size."""
+import math
+import sys
+
+import numpy as np
+
+from paper_2101_09059_amd import inputs
+from oracle import assembly, cfl, element, matern, stepper
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+class Case:
+    pass
+
+
+def c1_case():
+    c = inputs.CONFIGS["c1_tiny"]
+    m = inputs.cylinder(c["R"], c["L"], c["n_theta"], c["n_z"])
+    kh, A, _ = element.reference_stiffness(m.xyz, m.tri, c["nu"], c["shear_k"])
+    eh, h = matern.lognormal_fields(m.xyz, m.tri, c["S"], c["seed"])
+    cs = Case()
+    cs.cfg, cs.mesh, cs.khat, cs.area, cs.eh, cs.h = c, m, kh, A, eh, h
+    cs.F = inputs.traction_load(m, c["p0"])
+    cs.dt = cfl.stable_dt(kh, A, eh, h, c["rho"], c["safety"])
+    cs.g = lambda t: stepper.load_factor(c["ramp"], t, c["T_ramp"])
+    return cs
+
+
+def small_case(n_theta, n_z, S, seed=0, R=1.0, L=4.0, k=5.0 / 6.0):
+    m = inputs.cylinder(R, L, n_theta, n_z)
+    kh, A, _ = element.reference_stiffness(m.xyz, m.tri, 0.49, k)
+    rng = np.random.default_rng(seed)
+    eh = 7e5 * np.exp(0.2 * rng.standard_normal((m.n_el, S)))
+    h = 0.1 * np.exp(0.2 * rng.standard_normal((m.n_el, S)))
+    cs = Case()
+    cs.mesh, cs.khat, cs.area, cs.eh, cs.h = m, kh, A, eh, h
+    cs.F = inputs.traction_load(m, 1.33e5)
+    cs.dt = cfl.stable_dt(kh, A, eh, h, 1.0, 0.9)
+    return cs
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def oracle_apply(cs, U):
+    """K_s U[:, s] for every sample, one CSR matrix per sample."""
+    out = np.empty_like(U)
+    for s in range(U.shape[1]):
+        K = assembly.assemble_stiffness(cs.mesh.tri, cs.khat, cs.eh[:, s], cs.mesh.n_nodes)
+        out[:, s] = K @ U[:, s]
+    return out

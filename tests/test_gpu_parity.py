@@ -1,0 +1,276 @@
+"""GPU parity of the HIP path against the FP64 oracle (through the C ABI).
+
+Tolerances: FP64 path 1e-10 relative L2 over the [n_dof x S] block (at the
+final step and at 10 checkpoints); FP32 apply with FP64 or Kahan-compensated
+FP32 state 1e-5.  Apply-only: FP64 1e-13, FP32 1e-5 per sample.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import stats, stepper, cfl
+from paper_2101_09059_amd import ensfem, inputs
+from tests._cases import c1_case, small_case, say, rel_l2, oracle_apply
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(cs, **kw):
+    kw.setdefault("alpha", 50.0)
+    return ensfem.setup_case(cs.mesh, cs.eh, cs.h, cs.F, **kw)
+
+
+def test_cfl_dt_matches_oracle():
+    cs = c1_case()
+    say("case: C1 cfl")
+    ens = _ctx(cs)
+    assert abs(ens.cfl_dt(0.9) / cs.dt - 1.0) < 1e-12
+    ens.close()
+
+
+@pytest.mark.parametrize("nt,nz,S", [(40, 20, 8), (37, 23, 13), (16, 9, 1), (30, 12, 100), (24, 10, 64),
+                                     (48, 30, 200)])
+@pytest.mark.parametrize("prec", [ensfem.F64, ensfem.F32])
+def test_apply_parity(nt, nz, S, prec):
+    say(f"case: apply nt={nt} nz={nz} S={S} prec={prec}")
+    cs = small_case(nt, nz, S, seed=nt * 7 + S)
+    ens = _ctx(cs)
+    info = ens.info()
+    ld = info["S_pad"]
+    rng = np.random.default_rng(S)
+    U = rng.standard_normal((cs.mesh.n_dof, S))
+    dt = torch.float64 if prec == ensfem.F64 else torch.float32
+    Ud = torch.zeros((cs.mesh.n_dof, ld), dtype=dt, device="cuda")
+    Ud[:, :S] = torch.from_numpy(U).to(dt)
+    Rd = torch.full((cs.mesh.n_dof, ld), float("nan"), dtype=dt, device="cuda")
+    ens.apply(Ud, Rd, prec)
+    torch.cuda.synchronize()
+    R = Rd[:, :S].double().cpu().numpy()
+    Uo = Ud[:, :S].double().cpu().numpy()  # the exact input the kernel saw
+    ref = oracle_apply(cs, Uo)
+    tol = 1e-13 if prec == ensfem.F64 else 1e-5
+    for s in range(S):
+        assert np.linalg.norm(R[:, s] - ref[:, s]) <= tol * np.linalg.norm(ref[:, s]), s
+    ens.close()
+
+
+def _run_gpu(cs, n_total, chunk, **kw):
+    ens = _ctx(cs, kind=ensfem.LOAD_RAMP_SINE, t_ramp=cs.cfg["T_ramp"], **kw)
+    ens.init_state()
+    cps = {}
+    done = 0
+    while done < n_total:
+        ens.step(chunk, cs.dt)
+        done += chunk
+        cps[done] = ens.read_state()
+    q = ens.read_qoi()
+    mean, var = ens.moments()
+    ens.close()
+    return cps, q, mean, var
+
+
+def test_c1_fp64_2000_steps_vs_oracle():
+    cs = c1_case()
+    c = cs.cfg
+    say("case: C1 FP64 2000 steps")
+    cps, q, mean, var = _run_gpu(cs, 2000, 200)
+    ref = stepper.run_ensemble(cs.mesh.tri, cs.khat, cs.area, cs.eh, cs.h, c["rho"], cs.F, cs.mesh.fixed,
+                               cs.mesh.radial, cs.dt, 2000, c["alpha"], cs.g,
+                               checkpoints=tuple(range(200, 2001, 200)))
+    for n, u in cps.items():
+        assert rel_l2(u, ref["checkpoints"][n]) <= 1e-10, n
+    assert rel_l2(q, ref["q"]) <= 1e-10
+    m_ref, v_ref = stats.moments(ref["q"])
+    assert rel_l2(mean, m_ref) <= 1e-10
+    assert rel_l2(var, v_ref) <= 1e-9
+
+
+@pytest.mark.parametrize("mode,tol", [("f64", 1e-10), ("f32_kahan", 1e-5), ("f32_apply_f64_state", 1e-5)])
+def test_c1_100k_steps_vs_golden(mode, tol):
+    g = np.load("tests/golden/c1_reference.npz")
+    cs = c1_case()
+    assert cs.dt == float(g["dt"])
+    kw = dict(f64={}, f32_kahan=dict(apply_prec=ensfem.F32, state_prec=ensfem.STATE_F32_KAHAN),
+              f32_apply_f64_state=dict(apply_prec=ensfem.F32))[mode]
+    say(f"case: C1 100k steps {mode}")
+    cps, q, _, _ = _run_gpu(cs, 100_000, 10_000, **kw)
+    errs = [rel_l2(cps[int(n)], g["u"][i]) for i, n in enumerate(g["steps"])]
+    say(f"  {mode}: rel L2 per checkpoint {['%.2e' % e for e in errs]}")
+    assert max(errs) <= tol
+    assert rel_l2(q, g["q"]) <= tol
+
+
+def test_c1_plain_fp32_state_is_worse_than_kahan():
+    g = np.load("tests/golden/c1_reference.npz")
+    cs = c1_case()
+    say("case: C1 100k steps plain FP32 state")
+    cps, _, _, _ = _run_gpu(cs, 100_000, 50_000, apply_prec=ensfem.F32, state_prec=ensfem.STATE_F32)
+    cpk, _, _, _ = _run_gpu(cs, 100_000, 50_000, apply_prec=ensfem.F32, state_prec=ensfem.STATE_F32_KAHAN)
+    e_plain = rel_l2(cps[100_000], g["u"][-1])
+    e_kahan = rel_l2(cpk[100_000], g["u"][-1])
+    say(f"  plain FP32 state {e_plain:.3e}  Kahan {e_kahan:.3e}")
+    assert np.isfinite(e_plain) and e_kahan <= e_plain
+
+
+def test_nonzero_initial_state_and_pulsatile_load():
+    cs = small_case(20, 12, 6, seed=3)
+    rng = np.random.default_rng(4)
+    free = ~cs.mesh.fixed.reshape(-1).astype(bool)
+    u0 = rng.standard_normal((cs.mesh.n_dof, 6)) * 1e-3 * free[:, None]
+    v0 = rng.standard_normal((cs.mesh.n_dof, 6)) * 1e-1 * free[:, None]
+    n = 3000
+    g = lambda t: stepper.load_factor("sine_pulse", t, 0.01, 0.02, 0.3)
+    ref = []
+    from oracle import assembly
+    for s in range(6):
+        K = assembly.assemble_stiffness(cs.mesh.tri, cs.khat, cs.eh[:, s], cs.mesh.n_nodes)
+        m = assembly.lumped_mass(cs.mesh.tri, cs.area, cs.h[:, s], 1.0, cs.mesh.n_nodes)
+        ref.append(stepper.run_sample(K, m, cs.F.reshape(-1), ~free, cs.dt, n, 20.0, g,
+                                      u0=u0[:, s], v0=v0[:, s])["u"])
+    ref = np.stack(ref, axis=1)
+    for mode, tol, kw in [("f64", 1e-10, {}),
+                          ("kahan", 1e-5, dict(apply_prec=ensfem.F32, state_prec=ensfem.STATE_F32_KAHAN))]:
+        say(f"case: nonzero start + pulsatile, {mode}")
+        ens = ensfem.setup_case(cs.mesh, cs.eh, cs.h, cs.F, alpha=20.0, kind=ensfem.LOAD_PULSATILE,
+                                t_ramp=0.01, amp=0.3, period=0.02, **kw)
+        ens.init_state(u0, v0)
+        ens.step(n, cs.dt)
+        u = ens.read_state()
+        ens.close()
+        assert rel_l2(u, ref) <= tol, mode
+
+
+def test_energy_conserved_and_matches_oracle():
+    cs = small_case(18, 10, 4, seed=5)
+    free = ~cs.mesh.fixed.reshape(-1).astype(bool)
+    rng = np.random.default_rng(6)
+    u0 = rng.standard_normal((cs.mesh.n_dof, 4)) * 1e-3 * free[:, None]
+    F0 = np.zeros_like(cs.F)
+    n = 1000
+    say("case: energy conservation, undamped, unforced")
+    ens = ensfem.setup_case(cs.mesh, cs.eh, cs.h, F0, alpha=0.0, energy_every=10)
+    ens.init_state(u0)
+    ens.step(n, cs.dt)
+    steps, E = ens.read_energy()
+    ens.close()
+    assert len(steps) == n // 10 and steps[0] == 0 and steps[-1] == n - 10
+    from oracle import assembly
+    for s in range(4):
+        K = assembly.assemble_stiffness(cs.mesh.tri, cs.khat, cs.eh[:, s], cs.mesh.n_nodes)
+        m = assembly.lumped_mass(cs.mesh.tri, cs.area, cs.h[:, s], 1.0, cs.mesh.n_nodes)
+        r = stepper.run_sample(K, m, np.zeros(cs.mesh.n_dof), ~free, cs.dt, n, 0.0, lambda t: 0.0,
+                               u0=u0[:, s], energy_every=10)
+        e_ref = np.array([e for _, e in r["energy"]])
+        assert np.max(np.abs(E[:, s] - e_ref)) <= 1e-10 * abs(e_ref[0])
+        assert np.max(np.abs(E[:, s] - E[0, s])) <= 1e-11 * abs(E[0, s])
+
+
+@pytest.mark.parametrize("state", [ensfem.STATE_F64, ensfem.STATE_F32_KAHAN])
+def test_checkpoint_resume_is_bitwise(state):
+    cs = c1_case()
+    kw = dict(kind=ensfem.LOAD_RAMP_SINE, t_ramp=0.05, state_prec=state,
+              apply_prec=ensfem.F64 if state == ensfem.STATE_F64 else ensfem.F32)
+    say(f"case: checkpoint state={state}")
+    a = ensfem.setup_case(cs.mesh, cs.eh, cs.h, cs.F, **kw)
+    a.init_state()
+    a.step(1000, cs.dt)
+    full = a.read_state()
+    qa = a.read_qoi()
+    a.close()
+    b = ensfem.setup_case(cs.mesh, cs.eh, cs.h, cs.F, **kw)
+    b.init_state()
+    b.step(500, cs.dt)
+    blob = b.save()
+    b.close()
+    c = ensfem.setup_case(cs.mesh, cs.eh, cs.h, cs.F, **kw)
+    c.load(blob)
+    c.step(500, cs.dt)
+    assert np.array_equal(c.read_state(), full)
+    assert np.array_equal(c.read_qoi(), qa)
+    c.close()
+
+
+def test_error_paths():
+    cs = small_case(10, 6, 2)
+    m = cs.mesh
+    say("case: error paths")
+    ens = ensfem.Ensemble(0)
+    bad_tri = m.tri.copy()
+    bad_tri[3, 1] = m.n_nodes + 5
+    with pytest.raises(ensfem.EnsfemError) as ei:
+        ens.set_mesh(m.xyz, bad_tri, m.fixed, m.radial)
+    assert ei.value.code == ensfem.ENS_EINVAL
+    with pytest.raises(ensfem.EnsfemError) as ei:
+        ens.set_mesh(m.xyz, m.tri, m.fixed, 2.0 * m.radial)
+    assert ei.value.code == ensfem.ENS_EINVAL
+    with pytest.raises(ensfem.EnsfemError) as ei:
+        ens.set_ensemble(cs.eh, cs.h)
+    assert ei.value.code == ensfem.ENS_ESTATE
+    ens.set_mesh(m.xyz, m.tri, m.fixed, m.radial)
+    eh = cs.eh.copy()
+    eh[2, 1] = np.nan
+    with pytest.raises(ensfem.EnsfemError) as ei:
+        ens.set_ensemble(eh, cs.h)
+    assert ei.value.code == ensfem.ENS_EINVAL
+    ens.set_material(0.49, 5 / 6, 1.0, 0.0)
+    ens.set_ensemble(cs.eh, cs.h)
+    ens.set_load(cs.F)
+    with pytest.raises(ensfem.EnsfemError) as ei:
+        ens.step(1, cs.dt)
+    assert ei.value.code == ensfem.ENS_EWORKSPACE
+    small = torch.empty(1024, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ensfem.EnsfemError) as ei:
+        ens.bind_workspace(small)
+    assert ei.value.code == ensfem.ENS_EWORKSPACE
+    ens.bind_workspace()
+    with pytest.raises(ensfem.EnsfemError) as ei:
+        ens.step(1, cs.dt)
+    assert ei.value.code == ensfem.ENS_ESTATE
+    ens.init_state()
+    bound = ens.cfl_dt(1.0)
+    with pytest.raises(ensfem.EnsfemError) as ei:
+        ens.step(1, 1.01 * bound)
+    assert ei.value.code == ensfem.ENS_EUNSTABLE
+    ens.step(10, cs.dt)
+    with pytest.raises(ensfem.EnsfemError) as ei:
+        ens.step(1, 0.5 * cs.dt)
+    assert ei.value.code == ensfem.ENS_EINVAL
+    ens.sync()
+    # forcing an unstable step size: the watchdog reports non-finite values
+    ens.init_state()
+    ens.step(3000, 3.0 * bound, force=True)
+    with pytest.raises(ensfem.EnsfemError) as ei:
+        ens.sync()
+    assert ei.value.code == ensfem.ENS_ENONFINITE
+    ens.close()
+
+
+@pytest.mark.parametrize("apply_prec", [ensfem.F64, ensfem.F32])
+def test_c2_full_size_sampled_columns(apply_prec):
+    """The bench workload (400 x 500 cylinder, S = 256) in the bench's launch
+    configuration, 40 steps, two sample columns checked against the oracle."""
+    c = inputs.CONFIGS["c2_cylinder"]
+    say(f"case: C2 full size, apply_prec={apply_prec}")
+    m = inputs.cylinder(c["R"], c["L"], c["n_theta"], c["n_z"])
+    eh, h = inputs.lognormal_fields(m, c["S"], c["seed"])
+    F = inputs.traction_load(m, c["p0"])
+    from oracle import element, assembly
+    kh, A, _ = element.reference_stiffness(m.xyz, m.tri, c["nu"], c["shear_k"])
+    dt = cfl.stable_dt(kh, A, eh, h, c["rho"], c["safety"])
+    ens = ensfem.setup_case(m, eh, h, F, alpha=c["alpha"], apply_prec=apply_prec)
+    assert abs(ens.cfl_dt(0.9) / dt - 1) < 1e-12
+    ens.init_state()
+    n = 40
+    ens.step(n, dt)
+    u = ens.read_state()
+    q = ens.read_qoi()
+    ens.close()
+    g = lambda t: 1.0
+    cols = [0, 137, 255]
+    ref = stepper.run_ensemble(m.tri, kh, A, eh, h, c["rho"], F, m.fixed, m.radial, dt, n, c["alpha"], g,
+                               samples=cols)
+    tol = 1e-10 if apply_prec == ensfem.F64 else 1e-5
+    assert rel_l2(u[:, cols], ref["u"]) <= tol
+    assert rel_l2(q[:, cols], ref["q"]) <= tol
