@@ -112,7 +112,7 @@ def main():
     ap.add_argument("--also-f64", action="store_true", default=True)
     ap.add_argument("--no-also-f64", dest="also_f64", action="store_false")
     ap.add_argument("--no-cpu-baseline", dest="cpu", action="store_false", default=True)
-    ap.add_argument("--sample-block", type=int, default=0)
+    ap.add_argument("--sample-block", type=int, default=0, help="0 = library default")
     ap.add_argument("--sb-inner", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 10 times (counter calibration)")

@@ -166,8 +166,10 @@ int32_t ens_moments(ens_ctx* ctx, double* mean, double* var);
 int32_t ens_apply(ens_ctx* ctx, int32_t prec, const void* U_dev, void* R_dev, void* stream);
 
 /* Performance tuning of the step kernels (no effect on results beyond
- * rounding order): sample_block in {0 = auto, 8, 16, 32, 64} samples per
- * lane group, sb_inner = 1 orders workgroups sample-block-fastest.  A
+ * rounding order): sample_block in {0 = auto, 8, 16, 32, 64, 128, 256}
+ * samples per node per workgroup pass (128 and 256 give each of 64 lanes 2
+ * or 4 consecutive samples), sb_inner = 1 orders workgroups
+ * sample-block-fastest.  A
  * change of the padded width drops the workspace binding (re-bind). */
 int32_t ens_set_tuning(ens_ctx* ctx, int32_t sample_block, int32_t sb_inner);
 

@@ -26,7 +26,6 @@
 namespace ensfem {
 namespace {
 
-template <int SB>
 __device__ __forceinline__ bool wg_coords(const StepArgs& p, int& nb, int& sb) {
   // Workgroups are dealt round-robin to the 8 XCDs; give each XCD a
   // contiguous range of logical tiles so neighbouring node blocks share an L2.
@@ -44,165 +43,268 @@ __device__ __forceinline__ bool wg_coords(const StepArgs& p, int& nb, int& sb) {
   return nb < p.n_nb && sb < p.n_sb;
 }
 
-template <typename AT, typename ST>
-__device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_t ld, int s,
-                                             const ST* __restrict__ U, ST ua0, ST ua1, ST ua2,
-                                             AT& r0, AT& r1, AT& r2) {
+// N consecutive samples per lane: one vector memory access per row.
+template <typename T, int N> struct VecOf;
+template <typename T> struct VecOf<T, 1> { typedef T type; };
+template <> struct VecOf<float, 2> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct VecOf<float, 4> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct VecOf<double, 2> { typedef double type __attribute__((ext_vector_type(2))); };
+template <> struct VecOf<double, 4> { typedef double type __attribute__((ext_vector_type(4))); };
+
+template <int N, bool NT, typename T>
+__device__ __forceinline__ void vload(const T* __restrict__ ptr, T (&out)[N]) {
+  typedef typename VecOf<T, N>::type V;
+  V v;
+  if constexpr (NT) v = __builtin_nontemporal_load(reinterpret_cast<const V*>(ptr));
+  else v = *reinterpret_cast<const V*>(ptr);
+  if constexpr (N == 1) {
+    out[0] = v;
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) out[i] = v[i];
+  }
+}
+
+template <int N, bool NT, typename T>
+__device__ __forceinline__ void vstore(T* __restrict__ ptr, const T (&in)[N]) {
+  typedef typename VecOf<T, N>::type V;
+  V v;
+  if constexpr (N == 1) {
+    v = in[0];
+  } else {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = in[i];
+  }
+  if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<V*>(ptr));
+  else *reinterpret_cast<V*>(ptr) = v;
+}
+
+// One row of the 3x6 block times the six differences, as a fixed chain of
+// fused multiply-adds (the library is built without implicit contraction so
+// every lane mapping performs exactly these operations).
+template <typename AT>
+__device__ __forceinline__ AT row6(const AT* __restrict__ k, AT d0, AT d1, AT d2, AT d3, AT d4, AT d5) {
+  AT f = k[0] * d0;
+  f = fma(k[1], d1, f);
+  f = fma(k[2], d2, f);
+  f = fma(k[3], d3, f);
+  f = fma(k[4], d4, f);
+  return fma(k[5], d5, f);
+}
+
+// R for one node and SPL consecutive samples starting at s0.
+template <typename AT, typename ST, int SPL>
+__device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_t ld, int s0,
+                                             const ST* __restrict__ U, const ST (&ua)[3][SPL],
+                                             AT (&r)[3][SPL]) {
   const int kb = p.adj.ptr[node];
   const int ke = p.adj.ptr[node + 1];
   const AT* __restrict__ KB = static_cast<const AT*>(p.adj.k);
   const AT* __restrict__ EH = static_cast<const AT*>(p.eh);
-  r0 = r1 = r2 = AT(0);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < SPL; ++i) r[c][i] = AT(0);
 #pragma unroll 2
   for (int k = kb; k < ke; ++k) {
     const int64_t e = p.adj.el[k];
     const int2 bc = p.adj.nb[k];
     const AT* __restrict__ kk = KB + (int64_t)k * 18;
-    const AT eh = EH[e * ld + s];
+    AT eh[SPL];
+    vload<SPL, false>(EH + e * ld + s0, eh);
     const int64_t rb = (int64_t)bc.x * 3, rc = (int64_t)bc.y * 3;
-    const AT d0 = (AT)(U[(rb + 0) * ld + s] - ua0);
-    const AT d1 = (AT)(U[(rb + 1) * ld + s] - ua1);
-    const AT d2 = (AT)(U[(rb + 2) * ld + s] - ua2);
-    const AT d3 = (AT)(U[(rc + 0) * ld + s] - ua0);
-    const AT d4 = (AT)(U[(rc + 1) * ld + s] - ua1);
-    const AT d5 = (AT)(U[(rc + 2) * ld + s] - ua2);
-    const AT f0 = kk[0] * d0 + kk[1] * d1 + kk[2] * d2 + kk[3] * d3 + kk[4] * d4 + kk[5] * d5;
-    const AT f1 = kk[6] * d0 + kk[7] * d1 + kk[8] * d2 + kk[9] * d3 + kk[10] * d4 + kk[11] * d5;
-    const AT f2 = kk[12] * d0 + kk[13] * d1 + kk[14] * d2 + kk[15] * d3 + kk[16] * d4 + kk[17] * d5;
-    r0 += eh * f0;
-    r1 += eh * f1;
-    r2 += eh * f2;
+    ST ub[3][SPL], uc[3][SPL];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      vload<SPL, false>(U + (rb + c) * ld + s0, ub[c]);
+      vload<SPL, false>(U + (rc + c) * ld + s0, uc[c]);
+    }
+#pragma unroll
+    for (int i = 0; i < SPL; ++i) {
+      const AT d0 = (AT)(ub[0][i] - ua[0][i]);
+      const AT d1 = (AT)(ub[1][i] - ua[1][i]);
+      const AT d2 = (AT)(ub[2][i] - ua[2][i]);
+      const AT d3 = (AT)(uc[0][i] - ua[0][i]);
+      const AT d4 = (AT)(uc[1][i] - ua[1][i]);
+      const AT d5 = (AT)(uc[2][i] - ua[2][i]);
+      const AT f0 = row6(kk + 0, d0, d1, d2, d3, d4, d5);
+      const AT f1 = row6(kk + 6, d0, d1, d2, d3, d4, d5);
+      const AT f2 = row6(kk + 12, d0, d1, d2, d3, d4, d5);
+      r[0][i] = fma(eh[i], f0, r[0][i]);
+      r[1][i] = fma(eh[i], f1, r[1][i]);
+      r[2][i] = fma(eh[i], f2, r[2][i]);
+    }
   }
 }
 
-template <typename AT, int MODE, int SB, bool QOI, bool ENERGY>
+// LPN lanes per node, SPL consecutive samples per lane: a workgroup covers
+// kBlock/LPN nodes times LPN*SPL samples.  With LPN = 64 a wave owns one
+// node, so adjacency and stiffness blocks are wave-uniform (scalar loads).
+template <typename AT, int MODE, int LPN, int SPL, bool QOI, bool ENERGY>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
-  constexpr int NPB = kBlock / SB;
+  constexpr int SB = LPN * SPL;
+  constexpr int NPB = kBlock / LPN;
   int nb, sbk;
-  if (!wg_coords<SB>(p, nb, sbk)) return;  // uniform over the workgroup
-  const int ln = threadIdx.x / SB;
-  const int ls = threadIdx.x % SB;
+  if (!wg_coords(p, nb, sbk)) return;  // uniform over the workgroup
+  const int ln = threadIdx.x / LPN;
+  const int lane = threadIdx.x % LPN;
   int node = nb * NPB + ln;
-  if (SB >= 64) node = __builtin_amdgcn_readfirstlane(node);
-  const int s = sbk * SB + ls;
+  if (LPN >= 64) node = __builtin_amdgcn_readfirstlane(node);
+  const int s0 = sbk * SB + lane * SPL;
   const int64_t ld = p.ld;
   const bool active = node < p.n_nodes;
-  double e_loc = 0.0;
+  double e_loc[SPL];
+#pragma unroll
+  for (int i = 0; i < SPL; ++i) e_loc[i] = 0.0;
   if (active) {
     using ST = typename std::conditional<MODE == kStateF64, double, float>::type;
     const ST* __restrict__ U = nullptr;
     if constexpr (MODE == kStateF64) U = p.u_cur; else U = p.uh_cur;
     const int64_t row = (int64_t)node * 3;
-    const ST ua0 = U[(row + 0) * ld + s];
-    const ST ua1 = U[(row + 1) * ld + s];
-    const ST ua2 = U[(row + 2) * ld + s];
-    AT r0, r1, r2;
-    gather_apply<AT, ST>(p, node, ld, s, U, ua0, ua1, ua2, r0, r1, r2);
+    ST ua[3][SPL];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (row + c) * ld + s0, ua[c]);
+    AT r[3][SPL];
+    gather_apply<AT, ST, SPL>(p, node, ld, s0, U, ua, r);
 
     const double g = p.gtab[p.j];
     const unsigned fx = p.fixed[node];
-    const int64_t ms = (int64_t)node * ld + s;
-    double un[3];
+    const int64_t ms = (int64_t)node * ld + s0;
+    double un[3][SPL];
     if constexpr (MODE == kStateF64) {
-      const double minv = std::is_same<AT, double>::value
-                              ? static_cast<const double*>(p.minv)[ms]
-                              : (double)static_cast<const float*>(p.minv)[ms];
-      const double dt2m = p.dt * p.dt * minv;
+      double minv[SPL];
+      if constexpr (std::is_same<AT, double>::value) {
+        vload<SPL, true>(static_cast<const double*>(p.minv) + ms, minv);
+      } else {
+        float mf[SPL];
+        vload<SPL, true>(static_cast<const float*>(p.minv) + ms, mf);
+#pragma unroll
+        for (int i = 0; i < SPL; ++i) minv[i] = (double)mf[i];
+      }
+      const double dt2 = p.dt * p.dt;
       const double inv1pa = 1.0 / (1.0 + p.a);
       const double oma = 1.0 - p.a;
-      const double ua[3] = {ua0, ua1, ua2};
-      const double rr[3] = {(double)r0, (double)r1, (double)r2};
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const int64_t idx = (row + c) * ld + s;
-        const double up = p.u_prev[idx];
-        double v = (dt2m * (g * p.F[row + c] - rr[c]) + 2.0 * ua[c] - oma * up) * inv1pa;
-        if (fx & (1u << c)) v = 0.0;
-        p.u_next[idx] = v;
-        un[c] = v;
+        const int64_t idx = (row + c) * ld + s0;
+        double up[SPL];
+        vload<SPL, true>(p.u_prev + idx, up);
+        const double fc = g * p.F[row + c];
+#pragma unroll
+        for (int i = 0; i < SPL; ++i) {
+          const double acc = (dt2 * minv[i]) * (fc - (double)r[c][i]);
+          double v = fma(-oma, up[i], fma(2.0, ua[c][i], acc)) * inv1pa;
+          if (fx & (1u << c)) v = 0.0;
+          un[c][i] = v;
+        }
+        vstore<SPL, true>(p.u_next + idx, un[c]);
       }
       if constexpr (ENERGY) {
-        const double m = 1.0 / minv;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          const double vel = (un[c] - ua[c]) / p.dt;
-          e_loc += 0.5 * m * vel * vel + 0.5 * un[c] * rr[c];
+        for (int i = 0; i < SPL; ++i) {
+          const double m = 1.0 / minv[i];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            const double vel = (un[c][i] - ua[c][i]) / p.dt;
+            e_loc[i] += 0.5 * m * vel * vel + 0.5 * un[c][i] * (double)r[c][i];
+          }
         }
       }
     } else {
-      const float minv = static_cast<const float*>(p.minv)[ms];
+      float minv[SPL];
+      vload<SPL, true>(static_cast<const float*>(p.minv) + ms, minv);
       const float dtf = (float)p.dt;
       const float inv1pa = (float)(1.0 / (1.0 + p.a));
       const float oma = (float)(1.0 - p.a);
-      const float ua[3] = {ua0, ua1, ua2};
-      const float rr[3] = {(float)r0, (float)r1, (float)r2};
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const int64_t idx = (row + c) * ld + s;
-        const float acc = minv * ((float)(g * p.F[row + c]) - rr[c]);
-        float vel = (oma * p.v[idx] + dtf * acc) * inv1pa;
-        float uh = ua[c];
-        float cc = 0.0f;
-        if constexpr (MODE == kStateF32Kahan) {
-          cc = p.uc[idx];
-          const float y = dtf * vel - cc;
-          const float t = uh + y;
-          cc = (t - uh) - y;
-          uh = t;
-        } else {
-          uh = uh + dtf * vel;
+        const int64_t idx = (row + c) * ld + s0;
+        const float fc = (float)(g * p.F[row + c]);
+        float vel[SPL], cc[SPL], uh[SPL];
+        vload<SPL, true>(p.v + idx, vel);
+        if constexpr (MODE == kStateF32Kahan) vload<SPL, true>(p.uc + idx, cc);
+#pragma unroll
+        for (int i = 0; i < SPL; ++i) {
+          const float acc = minv[i] * (fc - (float)r[c][i]);
+          vel[i] = fmaf(dtf, acc, oma * vel[i]) * inv1pa;
+          uh[i] = ua[c][i];
+          if constexpr (MODE == kStateF32Kahan) {
+            const float y = fmaf(dtf, vel[i], -cc[i]);
+            const float t = uh[i] + y;
+            cc[i] = (t - uh[i]) - y;
+            uh[i] = t;
+          } else {
+            cc[i] = 0.0f;
+            uh[i] = fmaf(dtf, vel[i], uh[i]);
+          }
+          if (fx & (1u << c)) {
+            uh[i] = 0.0f;
+            cc[i] = 0.0f;
+            vel[i] = 0.0f;
+          }
+          un[c][i] = (double)uh[i] - (double)cc[i];
+          if constexpr (ENERGY) {
+            e_loc[i] += 0.5 / (double)minv[i] * (double)vel[i] * (double)vel[i] +
+                        0.5 * un[c][i] * (double)r[c][i];
+          }
         }
-        if (fx & (1u << c)) {
-          uh = 0.0f;
-          cc = 0.0f;
-          vel = 0.0f;
-        }
-        p.uh_next[idx] = uh;
-        if constexpr (MODE == kStateF32Kahan) p.uc[idx] = cc;
-        p.v[idx] = vel;
-        un[c] = (double)uh - (double)cc;
-        if constexpr (ENERGY) {
-          e_loc += 0.5 / (double)minv * (double)vel * (double)vel + 0.5 * un[c] * (double)rr[c];
-        }
+        vstore<SPL, true>(p.uh_next + idx, uh);
+        if constexpr (MODE == kStateF32Kahan) vstore<SPL, true>(p.uc + idx, cc);
+        vstore<SPL, true>(p.v + idx, vel);
       }
     }
     if constexpr (QOI) {
-      const double qv = p.radial[row + 0] * un[0] + p.radial[row + 1] * un[1] +
-                        p.radial[row + 2] * un[2];
-      const double qo = p.q[ms];
-      if (qv > qo) p.q[ms] = qv;
+      const double e0 = p.radial[row + 0], e1 = p.radial[row + 1], e2 = p.radial[row + 2];
+      double qo[SPL];
+      vload<SPL, true>(p.q + ms, qo);
+      bool upd = false;
+#pragma unroll
+      for (int i = 0; i < SPL; ++i) {
+        const double qv = fma(e2, un[2][i], fma(e1, un[1][i], e0 * un[0][i]));
+        if (qv > qo[i]) {
+          qo[i] = qv;
+          upd = true;
+        }
+      }
+      if (upd) vstore<SPL, true>(p.q + ms, qo);
     }
   }
   if constexpr (ENERGY) {
-    __shared__ double red[kBlock];
-    red[threadIdx.x] = e_loc;
+    __shared__ double red[kBlock * SPL];
+#pragma unroll
+    for (int i = 0; i < SPL; ++i) red[threadIdx.x * SPL + i] = e_loc[i];
     __syncthreads();
     if (ln == 0) {
-      double sum = 0.0;
-      for (int i = 0; i < NPB; ++i) sum += red[i * SB + ls];
-      p.energy_part[(int64_t)nb * ld + s] = sum;
+#pragma unroll
+      for (int i = 0; i < SPL; ++i) {
+        double sum = 0.0;
+        for (int n = 0; n < NPB; ++n) sum += red[(n * LPN + lane) * SPL + i];
+        p.energy_part[(int64_t)nb * ld + s0 + i] = sum;
+      }
     }
   }
 }
 
-template <typename AT, int SB>
+template <typename AT, int LPN, int SPL>
 __global__ __launch_bounds__(kBlock) void k_apply(StepArgs p, const AT* __restrict__ U,
                                                   AT* __restrict__ R) {
-  constexpr int NPB = kBlock / SB;
+  constexpr int SB = LPN * SPL;
+  constexpr int NPB = kBlock / LPN;
   int nb, sbk;
-  if (!wg_coords<SB>(p, nb, sbk)) return;
-  int node = nb * NPB + (int)(threadIdx.x / SB);
-  if (SB >= 64) node = __builtin_amdgcn_readfirstlane(node);
+  if (!wg_coords(p, nb, sbk)) return;
+  int node = nb * NPB + (int)(threadIdx.x / LPN);
+  if (LPN >= 64) node = __builtin_amdgcn_readfirstlane(node);
   if (node >= p.n_nodes) return;
-  const int s = sbk * SB + (int)(threadIdx.x % SB);
+  const int s0 = sbk * SB + (int)(threadIdx.x % LPN) * SPL;
   const int64_t ld = p.ld;
   const int64_t row = (int64_t)node * 3;
-  AT r0, r1, r2;
-  gather_apply<AT, AT>(p, node, ld, s, U, U[(row + 0) * ld + s], U[(row + 1) * ld + s],
-                       U[(row + 2) * ld + s], r0, r1, r2);
-  R[(row + 0) * ld + s] = r0;
-  R[(row + 1) * ld + s] = r1;
-  R[(row + 2) * ld + s] = r2;
+  AT ua[3][SPL];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (row + c) * ld + s0, ua[c]);
+  AT r[3][SPL];
+  gather_apply<AT, AT, SPL>(p, node, ld, s0, U, ua, r);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) vstore<SPL, true>(R + (row + c) * ld + s0, r[c]);
 }
 
 __device__ double load_factor(const Schedule& sc, double t) {
@@ -375,23 +477,25 @@ inline unsigned step_grid(const StepArgs& a) {
   return (unsigned)(((n + 7) / 8) * 8);
 }
 
-template <typename AT, int MODE, int SB>
+template <typename AT, int MODE, int LPN, int SPL>
 hipError_t dispatch_flags(const StepArgs& a, bool qoi, bool energy, hipStream_t st) {
   const unsigned g = step_grid(a);
-  if (qoi && energy) k_step<AT, MODE, SB, true, true><<<g, kBlock, 0, st>>>(a);
-  else if (qoi) k_step<AT, MODE, SB, true, false><<<g, kBlock, 0, st>>>(a);
-  else if (energy) k_step<AT, MODE, SB, false, true><<<g, kBlock, 0, st>>>(a);
-  else k_step<AT, MODE, SB, false, false><<<g, kBlock, 0, st>>>(a);
+  if (qoi && energy) k_step<AT, MODE, LPN, SPL, true, true><<<g, kBlock, 0, st>>>(a);
+  else if (qoi) k_step<AT, MODE, LPN, SPL, true, false><<<g, kBlock, 0, st>>>(a);
+  else if (energy) k_step<AT, MODE, LPN, SPL, false, true><<<g, kBlock, 0, st>>>(a);
+  else k_step<AT, MODE, LPN, SPL, false, false><<<g, kBlock, 0, st>>>(a);
   return hipGetLastError();
 }
 
 template <typename AT, int MODE>
 hipError_t dispatch_sb(const StepArgs& a, int sb, bool qoi, bool energy, hipStream_t st) {
   switch (sb) {
-    case 8: return dispatch_flags<AT, MODE, 8>(a, qoi, energy, st);
-    case 16: return dispatch_flags<AT, MODE, 16>(a, qoi, energy, st);
-    case 32: return dispatch_flags<AT, MODE, 32>(a, qoi, energy, st);
-    case 64: return dispatch_flags<AT, MODE, 64>(a, qoi, energy, st);
+    case 8: return dispatch_flags<AT, MODE, 8, 1>(a, qoi, energy, st);
+    case 16: return dispatch_flags<AT, MODE, 16, 1>(a, qoi, energy, st);
+    case 32: return dispatch_flags<AT, MODE, 32, 1>(a, qoi, energy, st);
+    case 64: return dispatch_flags<AT, MODE, 64, 1>(a, qoi, energy, st);
+    case 128: return dispatch_flags<AT, MODE, 64, 2>(a, qoi, energy, st);
+    case 256: return dispatch_flags<AT, MODE, 64, 4>(a, qoi, energy, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -402,10 +506,12 @@ hipError_t dispatch_apply(const StepArgs& a, int sb, const void* U, void* R, hip
   const AT* u = static_cast<const AT*>(U);
   AT* r = static_cast<AT*>(R);
   switch (sb) {
-    case 8: k_apply<AT, 8><<<g, kBlock, 0, st>>>(a, u, r); break;
-    case 16: k_apply<AT, 16><<<g, kBlock, 0, st>>>(a, u, r); break;
-    case 32: k_apply<AT, 32><<<g, kBlock, 0, st>>>(a, u, r); break;
-    case 64: k_apply<AT, 64><<<g, kBlock, 0, st>>>(a, u, r); break;
+    case 8: k_apply<AT, 8, 1><<<g, kBlock, 0, st>>>(a, u, r); break;
+    case 16: k_apply<AT, 16, 1><<<g, kBlock, 0, st>>>(a, u, r); break;
+    case 32: k_apply<AT, 32, 1><<<g, kBlock, 0, st>>>(a, u, r); break;
+    case 64: k_apply<AT, 64, 1><<<g, kBlock, 0, st>>>(a, u, r); break;
+    case 128: k_apply<AT, 64, 2><<<g, kBlock, 0, st>>>(a, u, r); break;
+    case 256: k_apply<AT, 64, 4><<<g, kBlock, 0, st>>>(a, u, r); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -274,3 +274,48 @@ def test_c2_full_size_sampled_columns(apply_prec):
     tol = 1e-10 if apply_prec == ensfem.F64 else 1e-5
     assert rel_l2(u[:, cols], ref["u"]) <= tol
     assert rel_l2(q[:, cols], ref["q"]) <= tol
+
+
+@pytest.mark.parametrize("sb", [64, 128, 256])
+@pytest.mark.parametrize("prec", [ensfem.F64, ensfem.F32])
+def test_apply_parity_wide_sample_blocks(sb, prec):
+    """2 and 4 consecutive samples per lane (vector loads), ragged S."""
+    S = 200
+    say(f"case: apply wide sb={sb} prec={prec} S={S}")
+    cs = small_case(33, 17, S, seed=sb)
+    ens = ensfem.setup_case(cs.mesh, cs.eh, cs.h, cs.F, sample_block=sb)
+    ld = ens.info()["S_pad"]
+    assert ld % sb == 0 and ens.info()["sample_block"] == sb
+    rng = np.random.default_rng(sb)
+    dt = torch.float64 if prec == ensfem.F64 else torch.float32
+    Ud = torch.zeros((cs.mesh.n_dof, ld), dtype=dt, device="cuda")
+    Ud[:, :S] = torch.from_numpy(rng.standard_normal((cs.mesh.n_dof, S))).to(dt)
+    Rd = torch.full((cs.mesh.n_dof, ld), float("nan"), dtype=dt, device="cuda")
+    ens.apply(Ud, Rd, prec)
+    torch.cuda.synchronize()
+    R = Rd[:, :S].double().cpu().numpy()
+    ref = oracle_apply(cs, Ud[:, :S].double().cpu().numpy())
+    tol = 1e-13 if prec == ensfem.F64 else 1e-5
+    err = np.linalg.norm(R - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert err.max() <= tol
+    ens.close()
+
+
+@pytest.mark.parametrize("state", [ensfem.STATE_F64, ensfem.STATE_F32_KAHAN])
+def test_step_bitwise_independent_of_sample_block(state):
+    """Every (node, sample) does the same arithmetic in the same order
+    whatever the lane mapping, so the results must be bitwise equal."""
+    cs = small_case(26, 14, 256, seed=11)
+    kw = dict(state_prec=state, apply_prec=ensfem.F64 if state == ensfem.STATE_F64 else ensfem.F32,
+              energy_every=7)
+    outs = []
+    for sb in (64, 128, 256):
+        say(f"case: bitwise sb={sb} state={state}")
+        ens = ensfem.setup_case(cs.mesh, cs.eh, cs.h, cs.F, sample_block=sb, **kw)
+        ens.init_state()
+        ens.step(300, cs.dt)
+        outs.append((ens.read_state(), ens.read_qoi(), ens.read_energy()[1]))
+        ens.close()
+    for o in outs[1:]:
+        for a, b in zip(outs[0], o):
+            assert np.array_equal(a, b)
