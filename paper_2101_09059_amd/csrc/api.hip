@@ -185,22 +185,70 @@ Layout plan(const ens_ctx* c) {
   return L;
 }
 
+// Node-gather adjacency.  Each node's incident elements are ordered as a
+// walk around the node (element j+1 shares the edge (node, c_j) with
+// element j) so that consecutive entries share a neighbour: an entry whose
+// first neighbour equals the previous entry's second one is flagged (its b
+// index stored as ~b) and the kernel reuses the values already loaded.
 void build_adjacency(ens_ctx* c) {
   const int64_t nn = c->n_nodes, ne = c->n_el;
   c->adj_ptr.assign(nn + 1, 0);
   for (int64_t i = 0; i < 3 * ne; ++i) c->adj_ptr[c->tri[i] + 1]++;
   for (int64_t i = 0; i < nn; ++i) c->adj_ptr[i + 1] += c->adj_ptr[i];
   std::vector<int32_t> next(c->adj_ptr.begin(), c->adj_ptr.end() - 1);
-  c->adj_el.resize(3 * ne);
-  c->adj_nb.resize(3 * ne);
-  c->adj_loc.resize(3 * ne);
+  std::vector<int32_t> el(3 * ne);
+  std::vector<int2> nb(3 * ne);
+  std::vector<uint8_t> loc(3 * ne);
   for (int64_t e = 0; e < ne; ++e) {
     for (int a = 0; a < 3; ++a) {
       const int32_t node = c->tri[3 * e + a];
       const int32_t pos = next[node]++;
-      c->adj_el[pos] = (int32_t)e;
-      c->adj_nb[pos] = make_int2(c->tri[3 * e + (a + 1) % 3], c->tri[3 * e + (a + 2) % 3]);
-      c->adj_loc[pos] = (uint8_t)a;
+      el[pos] = (int32_t)e;
+      nb[pos] = make_int2(c->tri[3 * e + (a + 1) % 3], c->tri[3 * e + (a + 2) % 3]);
+      loc[pos] = (uint8_t)a;
+    }
+  }
+  c->adj_el.resize(3 * ne);
+  c->adj_nb.resize(3 * ne);
+  c->adj_loc.resize(3 * ne);
+  std::vector<int32_t> order;
+  std::vector<char> used;
+  for (int64_t i = 0; i < nn; ++i) {
+    const int32_t b0 = c->adj_ptr[i], b1 = c->adj_ptr[i + 1], k = b1 - b0;
+    order.clear();
+    used.assign(k, 0);
+    int32_t prev_c = -1;
+    while ((int32_t)order.size() < k) {
+      int32_t pick = -1;
+      if (prev_c >= 0)  // continue the walk across the shared edge
+        for (int32_t j = 0; j < k; ++j)
+          if (!used[j] && nb[b0 + j].x == prev_c) { pick = j; break; }
+      if (pick < 0) {  // start a walk: prefer an entry no other unused entry leads into
+        for (int32_t j = 0; j < k && pick < 0; ++j) {
+          if (used[j]) continue;
+          bool has_pred = false;
+          for (int32_t t = 0; t < k; ++t)
+            if (!used[t] && t != j && nb[b0 + t].y == nb[b0 + j].x) { has_pred = true; break; }
+          if (!has_pred) pick = j;
+        }
+        if (pick < 0)
+          for (int32_t j = 0; j < k; ++j)
+            if (!used[j]) { pick = j; break; }
+      }
+      used[pick] = 1;
+      order.push_back(pick);
+      prev_c = nb[b0 + pick].y;
+    }
+    int32_t last_c = -1;
+    for (int32_t t = 0; t < k; ++t) {
+      const int32_t src = b0 + order[t], dst = b0 + t;
+      c->adj_el[dst] = el[src];
+      c->adj_loc[dst] = loc[src];
+      int2 v = nb[src];
+      const bool reuse = (t > 0 && v.x == last_c);
+      last_c = v.y;
+      if (reuse) v.x = ~v.x;
+      c->adj_nb[dst] = v;
     }
   }
 }

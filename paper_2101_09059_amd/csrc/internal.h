@@ -23,6 +23,8 @@ struct Schedule {
 // Node-gather adjacency: for node i, entries adj_ptr[i] .. adj_ptr[i+1]-1,
 // one per incident element e, with the element's other two nodes (b, c) in
 // cyclic order after i and the 3x6 block [Khat_ib | Khat_ic] (global frame).
+// Entries walk around the node; nb.x < 0 (stored as ~b) marks an entry whose
+// b is the previous entry's c.
 struct Adjacency {
   const int32_t* ptr;
   const int32_t* el;

@@ -105,6 +105,7 @@ __device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int i = 0; i < SPL; ++i) r[c][i] = AT(0);
+  ST ub[3][SPL], uc[3][SPL];
 #pragma unroll 2
   for (int k = kb; k < ke; ++k) {
     const int64_t e = p.adj.el[k];
@@ -112,13 +113,20 @@ __device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_
     const AT* __restrict__ kk = KB + (int64_t)k * 18;
     AT eh[SPL];
     vload<SPL, false>(EH + e * ld + s0, eh);
-    const int64_t rb = (int64_t)bc.x * 3, rc = (int64_t)bc.y * 3;
-    ST ub[3][SPL], uc[3][SPL];
+    // bc.x < 0: this element's first neighbour is the previous one's second
+    if (bc.x >= 0) {
+      const int64_t rb = (int64_t)bc.x * 3;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      vload<SPL, false>(U + (rb + c) * ld + s0, ub[c]);
-      vload<SPL, false>(U + (rc + c) * ld + s0, uc[c]);
+      for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (rb + c) * ld + s0, ub[c]);
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int i = 0; i < SPL; ++i) ub[c][i] = uc[c][i];
     }
+    const int64_t rc = (int64_t)bc.y * 3;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (rc + c) * ld + s0, uc[c]);
 #pragma unroll
     for (int i = 0; i < SPL; ++i) {
       const AT d0 = (AT)(ub[0][i] - ua[0][i]);
