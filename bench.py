@@ -39,16 +39,17 @@ def step_kernel_bytes(n_nodes: int, n_el: int, S: int, apply_f32: bool) -> dict:
     """Algorithmic HBM bytes of one fused step launch (FP64 state): read
     u_n and u_{n-1}, write u_{n+1} (8 B per dof and sample each), read
     (E h) per element and sample and 1/m per node and sample (4 B in the
-    FP32 apply, 8 B in FP64), read the running peak q (8 B per node and
-    sample; its write is conditional and not counted), plus the per-mesh
-    arrays read once per launch (adjacency and 3x6 stiffness blocks, load,
-    radial directions, clamp bits)."""
+    FP32 apply, 8 B in FP64), read and write the at-max bit of the running
+    peak (1/8 B each per node and sample; the stored peak itself is only
+    touched where the radial displacement turns, so it is not counted),
+    plus the per-mesh arrays read once per launch (adjacency and 3x6
+    stiffness blocks, load, radial directions, clamp bits)."""
     w = 4 if apply_f32 else 8
     n_dof = 3 * n_nodes
     n_adj = 3 * n_el
-    per_sample = 3 * n_dof * 8 + n_el * w + n_nodes * w + n_nodes * 8
+    per_sample = 3 * n_dof * 8 + n_el * w + n_nodes * w + n_nodes * 0.25
     per_mesh = n_adj * (18 * w + 4 + 8) + (n_nodes + 1) * 4 + n_nodes * (24 + 24 + 1)
-    return dict(total=per_sample * S + per_mesh, per_sample=per_sample, per_mesh=per_mesh)
+    return dict(total=int(per_sample * S + per_mesh), per_sample=per_sample, per_mesh=per_mesh)
 
 
 def source_hash() -> str:

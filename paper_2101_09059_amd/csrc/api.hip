@@ -25,7 +25,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
   size_t xyz, tri, khat, area, lam, flags, adj_ptr, adj_el, adj_nb, adj_loc, k64, k32, fixed,
-      radial, F, eh64, eh32, h, minv64, minv32, u[2], uh[2], uc, v, q, epart, erec, gtab, base,
+      radial, F, eh64, eh32, h, minv64, minv32, u[2], uh[2], uc, v, q, qmask, epart, erec, gtab, base,
       mean, var, aux, total;
 };
 
@@ -173,6 +173,7 @@ Layout plan(const ens_ctx* c) {
     L.v = take(sizeof(float) * ndof * ld);
   }
   L.q = take(sizeof(double) * nn * ld);
+  L.qmask = take(sizeof(uint64_t) * nn * ((ld + 63) / 64));
   const int64_t n_nb = (nn + nodes_per_block(c->SB) - 1) / nodes_per_block(c->SB);
   L.epart = take(sizeof(double) * (n_nb + 256) * ld);
   L.erec = take(sizeof(double) * kEnergyCap * ld);
@@ -277,6 +278,8 @@ StepArgs base_args(const ens_ctx* c, bool f32) {
   a.fixed = c->p<uint8_t>(c->L.fixed);
   a.radial = c->p<double>(c->L.radial);
   a.q = c->p<double>(c->L.q);
+  a.qmask = c->p<uint64_t>(c->L.qmask);
+  a.qwords = (c->ld + 63) / 64;
   a.gtab = c->p<double>(c->L.gtab);
   a.energy_part = c->p<double>(c->L.epart);
   return a;
@@ -617,6 +620,7 @@ int32_t ens_init_state(ens_ctx* ctx, const double* u0, const double* v0) {
     HIPC(launch_qoi_init((int32_t)ctx->n_nodes, (int32_t)ld, ctx->p<double>(L.radial), nullptr,
                          ctx->p<float>(L.uh[0]), uc, ctx->p<double>(L.q), st));
   }
+  HIPC(hipMemset(ctx->p<void>(L.qmask), 0, sizeof(uint64_t) * ctx->n_nodes * ((ld + 63) / 64)));
   HIPC(hipMemset(ctx->p<void>(L.base), 0, sizeof(int64_t)));
   HIPC(hipDeviceSynchronize());
   ctx->cur = 0;
@@ -658,6 +662,22 @@ int32_t run_starter(ens_ctx* ctx, double dt, hipStream_t st) {
                             ctx->p<uint8_t>(L.fixed), ctx->p<float>(L.v), ctx->p<double>(L.gtab), dt,
                             ctx->alpha, st));
   }
+  return ENS_OK;
+}
+
+// Fold the at-max bits into q so q holds every sample's running peak.
+int32_t resolve_qoi(ens_ctx* ctx) {
+  const Layout& L = ctx->L;
+  if (ctx->state_prec == ENS_STATE_F64)
+    HIPC(launch_qoi_resolve((int32_t)ctx->n_nodes, ctx->ld, ctx->SB, ctx->p<double>(L.radial),
+                            ctx->p<double>(L.u[ctx->cur]), nullptr, nullptr, ctx->p<double>(L.q),
+                            ctx->p<uint64_t>(L.qmask), nullptr));
+  else
+    HIPC(launch_qoi_resolve((int32_t)ctx->n_nodes, ctx->ld, ctx->SB, ctx->p<double>(L.radial), nullptr,
+                            ctx->p<float>(L.uh[ctx->cur]),
+                            ctx->state_prec == ENS_STATE_F32_KAHAN ? ctx->p<float>(L.uc) : nullptr,
+                            ctx->p<double>(L.q), ctx->p<uint64_t>(L.qmask), nullptr));
+  HIPC(hipDeviceSynchronize());
   return ENS_OK;
 }
 
@@ -777,6 +797,10 @@ int32_t ens_read_qoi(ens_ctx* ctx, int32_t kind, double* out) {
   if (!ctx->bound || !ctx->state_init) return ctx->fail(ENS_ESTATE, "ens_read_qoi: no state");
   HIPC(hipSetDevice(ctx->device));
   HIPC(hipDeviceSynchronize());
+  {
+    const int32_t rc = resolve_qoi(ctx);
+    if (rc != ENS_OK) return rc;
+  }
   const int64_t n = ctx->n_nodes * ctx->ld;
   std::vector<double> buf(n);
   HIPC(hipMemcpy(buf.data(), ctx->p<void>(ctx->L.q), sizeof(double) * n, hipMemcpyDeviceToHost));
@@ -816,6 +840,10 @@ int32_t ens_moments(ens_ctx* ctx, double* mean, double* var) {
   if (!ctx->bound || !ctx->state_init) return ctx->fail(ENS_ESTATE, "ens_moments: no state");
   HIPC(hipSetDevice(ctx->device));
   HIPC(hipDeviceSynchronize());
+  {
+    const int32_t rc = resolve_qoi(ctx);
+    if (rc != ENS_OK) return rc;
+  }
   const Layout& L = ctx->L;
   HIPC(launch_moments((int32_t)ctx->n_nodes, ctx->ld, ctx->S, ctx->p<double>(L.q), ctx->p<double>(L.mean),
                       ctx->p<double>(L.var), nullptr));
@@ -860,6 +888,10 @@ int32_t ens_save(ens_ctx* ctx, void* host, size_t* bytes) {
   if (*bytes < need) return ctx->fail(ENS_EINVAL, "ens_save: buffer too small");
   HIPC(hipSetDevice(ctx->device));
   HIPC(hipDeviceSynchronize());
+  {
+    const int32_t rc = resolve_qoi(ctx);
+    if (rc != ENS_OK) return rc;
+  }
   char* o = static_cast<char*>(host);
   CkptHeader hd{kMagic, 3 * ctx->n_nodes, ctx->ld, ctx->S, ctx->state_prec, ctx->steps, ctx->started ? 1 : 0,
                 ctx->u0_zero ? 1 : 0, ctx->dt};
@@ -922,6 +954,7 @@ int32_t ens_load(ens_ctx* ctx, const void* host, size_t bytes) {
   }
   HIPC(hipMemcpy(ctx->p<void>(L.q), o, sizeof(double) * nq, hipMemcpyHostToDevice));
   HIPC(hipMemcpy(ctx->p<void>(L.base), &hd.steps, sizeof(int64_t), hipMemcpyHostToDevice));
+  HIPC(hipMemset(ctx->p<void>(L.qmask), 0, sizeof(uint64_t) * ctx->n_nodes * ((ctx->ld + 63) / 64)));
   HIPC(hipDeviceSynchronize());
   ctx->steps = hd.steps;
   ctx->started = hd.started != 0;

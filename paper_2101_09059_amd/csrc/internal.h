@@ -57,6 +57,12 @@ struct StepArgs {
   float* uc;           // Kahan compensation (in place)
   float* v;            // velocity v_{n-1/2} -> v_{n+1/2} (in place)
   double* q;           // running peak radial displacement [n_nodes][ld]
+  // At-max bits (wave-per-node kernels): bit set <=> the running peak equals
+  // the current radial displacement, which is then not stored in q.
+  // Per node ld/64 words; word sb*SPL + i, bit = lane of sample
+  // sb*SB + lane*SPL + i.
+  uint64_t* qmask;
+  int32_t qwords;
   const double* gtab;  // load factors of the current chunk
   int32_t j;           // index into gtab
   double dt, a;        // step, alpha dt / 2
@@ -99,6 +105,9 @@ hipError_t launch_starter_f32(int32_t n_nodes, int32_t ld, const float* R, const
 hipError_t launch_split_f32(int64_t n, const double* u0, float* uh, float* uc, hipStream_t st);
 hipError_t launch_qoi_init(int32_t n_nodes, int32_t ld, const double* radial, const double* u_f64,
                            const float* uh, const float* uc, double* q, hipStream_t st);
+hipError_t launch_qoi_resolve(int32_t n_nodes, int32_t ld, int sample_block, const double* radial,
+                              const double* u_f64, const float* uh, const float* uc, double* q,
+                              const uint64_t* qmask, hipStream_t st);
 hipError_t launch_combine_f32(int64_t n, const float* uh, const float* uc, double* out,
                               hipStream_t st);
 hipError_t launch_moments(int32_t n_nodes, int32_t ld, int32_t S, const double* q, double* mean,

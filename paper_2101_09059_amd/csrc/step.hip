@@ -179,7 +179,12 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
     const unsigned fx = p.fixed[node];
     const int64_t ms = (int64_t)node * ld + s0;
     double un[3][SPL];
+    double uo[3][SPL];  // u_n as the QoI sees it
     if constexpr (MODE == kStateF64) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int i = 0; i < SPL; ++i) uo[c][i] = ua[c][i];
       double minv[SPL];
       if constexpr (std::is_same<AT, double>::value) {
         vload<SPL, true>(static_cast<const double*>(p.minv) + ms, minv);
@@ -233,6 +238,8 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
         if constexpr (MODE == kStateF32Kahan) vload<SPL, true>(p.uc + idx, cc);
 #pragma unroll
         for (int i = 0; i < SPL; ++i) {
+          if constexpr (MODE == kStateF32Kahan) uo[c][i] = (double)ua[c][i] - (double)cc[i];
+          else uo[c][i] = (double)ua[c][i];
           const float acc = minv[i] * (fc - (float)r[c][i]);
           vel[i] = fmaf(dtf, acc, oma * vel[i]) * inv1pa;
           uh[i] = ua[c][i];
@@ -263,18 +270,41 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
     }
     if constexpr (QOI) {
       const double e0 = p.radial[row + 0], e1 = p.radial[row + 1], e2 = p.radial[row + 2];
-      double qo[SPL];
-      vload<SPL, true>(p.q + ms, qo);
-      bool upd = false;
+      if constexpr (LPN == 64) {
+        // q is only touched when the radial displacement turns: a rise that
+        // continues from the running peak keeps the at-max bit, a fall from
+        // it writes the peak, a rise below it compares with the stored peak.
+        uint64_t* __restrict__ mw = p.qmask + (int64_t)node * p.qwords + sbk * SPL;
 #pragma unroll
-      for (int i = 0; i < SPL; ++i) {
-        const double qv = fma(e2, un[2][i], fma(e1, un[1][i], e0 * un[0][i]));
-        if (qv > qo[i]) {
-          qo[i] = qv;
-          upd = true;
+        for (int i = 0; i < SPL; ++i) {
+          const uint64_t word = mw[i];
+          const bool at = (word >> lane) & 1ull;
+          const double rc = fma(e2, uo[2][i], fma(e1, uo[1][i], e0 * uo[0][i]));
+          const double rn = fma(e2, un[2][i], fma(e1, un[1][i], e0 * un[0][i]));
+          bool nbit = false;
+          if (at) {
+            nbit = rn >= rc;
+            if (!nbit) __builtin_nontemporal_store(rc, p.q + ms + i);
+          } else if (rn > rc) {
+            nbit = rn > __builtin_nontemporal_load(p.q + ms + i);
+          }
+          const uint64_t nword = __ballot(nbit);
+          if (nword != word && lane == 0) mw[i] = nword;
         }
+      } else {
+        double qo[SPL];
+        vload<SPL, true>(p.q + ms, qo);
+        bool upd = false;
+#pragma unroll
+        for (int i = 0; i < SPL; ++i) {
+          const double qv = fma(e2, un[2][i], fma(e1, un[1][i], e0 * un[0][i]));
+          if (qv > qo[i]) {
+            qo[i] = qv;
+            upd = true;
+          }
+        }
+        if (upd) vstore<SPL, true>(p.q + ms, qo);
       }
-      if (upd) vstore<SPL, true>(p.q + ms, qo);
     }
   }
   if constexpr (ENERGY) {
@@ -431,6 +461,33 @@ __global__ __launch_bounds__(256) void k_qoi_init(int32_t n_nodes, int32_t ld,
     acc += radial[node * 3 + c] * x;
   }
   q[t] = acc;
+}
+
+// Fold the at-max bits into q: where a bit is set, store the current radial
+// displacement (same operation order as the step kernel).  Idempotent.
+__global__ __launch_bounds__(256) void k_qoi_resolve(int32_t n_nodes, int32_t ld, int SB, int SPL,
+                                                     const double* __restrict__ radial,
+                                                     const double* __restrict__ u,
+                                                     const float* __restrict__ uh,
+                                                     const float* __restrict__ uc,
+                                                     double* __restrict__ q,
+                                                     const uint64_t* __restrict__ qmask) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= (int64_t)n_nodes * ld) return;
+  const int64_t node = t / ld;
+  const int s = (int)(t % ld);
+  const int sb = s / SB, within = s % SB, lane = within / SPL, i = within % SPL;
+  const int qwords = ld / 64;
+  const uint64_t word = qmask[node * qwords + sb * SPL + i];
+  if (!((word >> lane) & 1ull)) return;
+  double x[3];
+  for (int c = 0; c < 3; ++c) {
+    const int64_t idx = (node * 3 + c) * ld + s;
+    if (u) x[c] = u[idx];
+    else x[c] = (double)uh[idx] - (uc ? (double)uc[idx] : 0.0);
+  }
+  const double* e = radial + node * 3;
+  q[t] = fma(e[2], x[2], fma(e[1], x[1], e[0] * x[0]));
 }
 
 __global__ __launch_bounds__(256) void k_combine_f32(int64_t n, const float* __restrict__ uh,
@@ -603,6 +660,17 @@ hipError_t launch_qoi_init(int32_t n_nodes, int32_t ld, const double* radial, co
   const int64_t n = (int64_t)n_nodes * ld;
   if (n == 0) return hipSuccess;
   k_qoi_init<<<grid_for(n, 256), 256, 0, st>>>(n_nodes, ld, radial, u_f64, uh, uc, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_qoi_resolve(int32_t n_nodes, int32_t ld, int sample_block, const double* radial,
+                              const double* u_f64, const float* uh, const float* uc, double* q,
+                              const uint64_t* qmask, hipStream_t st) {
+  const int64_t n = (int64_t)n_nodes * ld;
+  if (n == 0 || sample_block < 64) return hipSuccess;
+  const int spl = sample_block / 64;
+  k_qoi_resolve<<<grid_for(n, 256), 256, 0, st>>>(n_nodes, ld, sample_block, spl, radial, u_f64, uh, uc,
+                                                   q, qmask);
   return hipGetLastError();
 }
 
