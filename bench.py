@@ -113,6 +113,8 @@ def main():
     ap.add_argument("--also-f64", action="store_true", default=True)
     ap.add_argument("--no-also-f64", dest="also_f64", action="store_false")
     ap.add_argument("--no-cpu-baseline", dest="cpu", action="store_false", default=True)
+    ap.add_argument("--no-also-shared", dest="also_shared", action="store_false", default=True,
+                    help="skip the shared-stiffness (block-row product) timing")
     ap.add_argument("--sample-block", type=int, default=0, help="0 = library default")
     ap.add_argument("--sb-inner", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
@@ -148,8 +150,9 @@ def main():
     F = inputs.traction_load(mesh, cfg["p0"])
     log(f"inputs ready in {time.perf_counter() - t0:.1f} s: {mesh.n_nodes} nodes, {mesh.n_el} tri, S={cfg['S']}")
 
-    def run(apply_f32: bool, steps: int, warmup: int):
-        ens = ensfem.setup_case(mesh, eh, h, F, nu=cfg["nu"], shear_k=cfg["shear_k"], rho=cfg["rho"],
+    def run(apply_f32: bool, steps: int, warmup: int, shared: bool = False):
+        fields = np.repeat(eh[:, :1], eh.shape[1], axis=1) if shared else eh
+        ens = ensfem.setup_case(mesh, fields, h, F, nu=cfg["nu"], shear_k=cfg["shear_k"], rho=cfg["rho"],
                                 alpha=cfg["alpha"], apply_prec=ensfem.F32 if apply_f32 else ensfem.F64,
                                 sample_block=args.sample_block, sb_inner=args.sb_inner)
         dt = ens.cfl_dt(cfg["safety"])
@@ -178,6 +181,11 @@ def main():
         ms, dt, info = run(f32, args.steps, args.warmup)
         results["f32" if f32 else "f64"] = (ms, dt, info)
         log(f"apply={'f32' if f32 else 'f64'}: {ms / args.steps:.4f} ms/step")
+
+    if args.also_shared:
+        ms_sh, _, info_sh = run(args.apply == "f32", args.steps, args.warmup, shared=True)
+        assert info_sh["variant"] == ensfem.VARIANT_CSR_SHARED
+        log(f"shared stiffness, apply={args.apply}: {ms_sh / args.steps:.4f} ms/step")
 
     ms, dt, info = results[args.apply]
     S = cfg["S"]
@@ -209,6 +217,9 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": f"k_step ({variant})", "algorithmic_bytes_per_launch": b["total"]},
     }
+    if args.also_shared:
+        out["ms_per_step_shared_stiffness"] = ms_sh / args.steps
+        out["value_shared_stiffness"] = work / (ms_sh * 1e-3)
     for k, (ms2, _, _) in results.items():
         out[f"ms_per_step_{k}_apply"] = ms2 / args.steps
         out[f"value_{k}_apply"] = work / (ms2 * 1e-3)

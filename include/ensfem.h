@@ -60,7 +60,16 @@ enum { ENS_F64 = 0, ENS_F32 = 1 };
  *              u <- u + dt v (compensation term kept per dof)
  *   F32        velocity form in plain FP32 (shows what compensation buys) */
 enum { ENS_STATE_F64 = 0, ENS_STATE_F32_KAHAN = 1, ENS_STATE_F32 = 2 };
-/* apply kernel variant */
+/* apply kernel variant:
+ *   NODE_GATHER  per-sample stiffness: each node gathers its incident
+ *                elements' (E h)_{e,s} Khat_e rows (element-by-element,
+ *                assembly-free, Sec. 2.4)
+ *   CSR_SHARED   one stiffness for all samples ((E h)_{e,s} = (E h)_e):
+ *                K assembled once into 3x3 block rows, applied as a
+ *                sparse-matrix times ensemble-block product (the CSR
+ *                product with 9 n_s entries per block of Sec. 2.3)
+ *   AUTO         CSR_SHARED when every (E h) row is constant, else
+ *                NODE_GATHER (ens_info reports the one in use) */
 enum { ENS_VARIANT_AUTO = 0, ENS_VARIANT_NODE_GATHER = 1, ENS_VARIANT_CSR_SHARED = 3 };
 /* load time factor g(t):  STEP g = 1;  RAMP_SINE g = sin(pi t / (2 t_ramp))
  * for t < t_ramp, else 1 (sine ramp of Sec. 3.1.2);  PULSATILE = RAMP_SINE
@@ -119,7 +128,8 @@ int32_t ens_set_load(ens_ctx* ctx, const double* F, ens_schedule sched);
  * q_{i,s} = max_n e_r,i . u_{i,s}(t_n).  energy_every > 0 records the
  * discrete energy 1/2 v^T M v + 1/2 u_{n+1}^T K u_n per sample at steps
  * n with n % energy_every == 0 (the most recent 4096 records are kept).
- * ENS_VARIANT_CSR_SHARED needs shared stiffness (checked at bind). */
+ * ENS_VARIANT_CSR_SHARED needs shared stiffness (ENS_EUNSUPPORTED at bind
+ * otherwise). */
 int32_t ens_configure(ens_ctx* ctx, int32_t apply_prec, int32_t state_prec, int32_t variant,
                       int32_t qoi_mask, int32_t energy_every);
 

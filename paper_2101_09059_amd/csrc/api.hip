@@ -25,7 +25,8 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
   size_t xyz, tri, khat, area, lam, flags, adj_ptr, adj_el, adj_nb, adj_loc, k64, k32, fixed,
-      radial, F, eh64, eh32, h, minv64, minv32, u[2], uh[2], uc, v, q, qmask, epart, erec, gtab, base,
+      radial, F, eh64, eh32, h, minv64, minv32, u[2], uh[2], uc, v, q, qmask, bsr_ptr, bsr_col,
+      adj_slot, bsr64, bsr32, epart, erec, gtab, base,
       mean, var, aux, total;
 };
 
@@ -50,6 +51,9 @@ struct ens_ctx {
   std::vector<int32_t> adj_ptr, adj_el;
   std::vector<int2> adj_nb;
   std::vector<uint8_t> adj_loc;
+  // shared-stiffness block rows (off-diagonal neighbours per node)
+  std::vector<int32_t> bsr_ptr, bsr_col;
+  std::vector<int2> adj_slot;
   // material
   double nu = 0.49, shear_k = 5.0 / 6.0, rho = 1.0, alpha = 0.0;
   bool have_material = false;
@@ -133,6 +137,8 @@ int pick_sample_block(int S, int requested) {
 // nodes per workgroup for a sample block
 int nodes_per_block(int SB) { return kBlock / (SB >= 64 ? 64 : SB); }
 
+bool use_shared(const ens_ctx* c);
+
 Layout plan(const ens_ctx* c) {
   Layout L{};
   size_t off = 0;
@@ -171,6 +177,14 @@ Layout plan(const ens_ctx* c) {
     L.uh[1] = take(sizeof(float) * ndof * ld);
     if (c->state_prec == ENS_STATE_F32_KAHAN) L.uc = take(sizeof(float) * ndof * ld);
     L.v = take(sizeof(float) * ndof * ld);
+  }
+  if (use_shared(c)) {
+    const int64_t nb = (int64_t)c->bsr_col.size();
+    L.bsr_ptr = take(sizeof(int32_t) * (nn + 1));
+    L.bsr_col = take(sizeof(int32_t) * nb);
+    L.adj_slot = take(sizeof(int2) * nadj);
+    L.bsr64 = take(sizeof(double) * 9 * nb);
+    L.bsr32 = take(sizeof(float) * 9 * nb);
   }
   L.q = take(sizeof(double) * nn * ld);
   L.qmask = take(sizeof(uint64_t) * nn * ((ld + 63) / 64));
@@ -252,6 +266,35 @@ void build_adjacency(ens_ctx* c) {
       c->adj_nb[dst] = v;
     }
   }
+  // block rows for the shared-stiffness variant: sorted distinct neighbours
+  c->bsr_ptr.assign(nn + 1, 0);
+  c->bsr_col.clear();
+  c->adj_slot.resize(3 * ne);
+  std::vector<int32_t> cols;
+  for (int64_t i = 0; i < nn; ++i) {
+    cols.clear();
+    for (int32_t k = c->adj_ptr[i]; k < c->adj_ptr[i + 1]; ++k) {
+      const int2 v = c->adj_nb[k];
+      cols.push_back(v.x < 0 ? ~v.x : v.x);
+      cols.push_back(v.y);
+    }
+    std::sort(cols.begin(), cols.end());
+    cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+    const int32_t base = (int32_t)c->bsr_col.size();
+    c->bsr_col.insert(c->bsr_col.end(), cols.begin(), cols.end());
+    c->bsr_ptr[i + 1] = (int32_t)c->bsr_col.size();
+    for (int32_t k = c->adj_ptr[i]; k < c->adj_ptr[i + 1]; ++k) {
+      const int2 v = c->adj_nb[k];
+      const int32_t b = v.x < 0 ? ~v.x : v.x;
+      const int32_t sb = base + (int32_t)(std::lower_bound(cols.begin(), cols.end(), b) - cols.begin());
+      const int32_t sc = base + (int32_t)(std::lower_bound(cols.begin(), cols.end(), v.y) - cols.begin());
+      c->adj_slot[k] = make_int2(sb, sc);
+    }
+  }
+}
+
+bool use_shared(const ens_ctx* c) {
+  return c->variant == ENS_VARIANT_CSR_SHARED || (c->variant == ENS_VARIANT_AUTO && c->shared);
 }
 
 bool ready_for_workspace(const ens_ctx* c, std::string* why) {
@@ -273,6 +316,11 @@ StepArgs base_args(const ens_ctx* c, bool f32) {
   a.adj.nb = c->p<int2>(c->L.adj_nb);
   a.adj.k = f32 ? (const void*)c->p<float>(c->L.k32) : (const void*)c->p<double>(c->L.k64);
   a.eh = f32 ? (const void*)c->p<float>(c->L.eh32) : (const void*)c->p<double>(c->L.eh64);
+  if (use_shared(c)) {
+    a.bsr.ptr = c->p<int32_t>(c->L.bsr_ptr);
+    a.bsr.col = c->p<int32_t>(c->L.bsr_col);
+    a.bsr.val = f32 ? (const void*)c->p<float>(c->L.bsr32) : (const void*)c->p<double>(c->L.bsr64);
+  }
   a.minv = f32 ? (const void*)c->p<float>(c->L.minv32) : (const void*)c->p<double>(c->L.minv64);
   a.F = c->p<double>(c->L.F);
   a.fixed = c->p<uint8_t>(c->L.fixed);
@@ -326,6 +374,16 @@ int32_t upload_all(ens_ctx* ctx) {
   HIPC(launch_adjacency_blocks(3 * ne, ctx->p<int32_t>(L.adj_el), ctx->p<uint8_t>(L.adj_loc),
                                ctx->p<double>(L.khat), ctx->p<double>(L.k64), ctx->p<float>(L.k32), st));
   HIPC(launch_cast_f32(ne * ld, ctx->p<double>(L.eh64), ctx->p<float>(L.eh32), st));
+  if (use_shared(ctx)) {
+    const int64_t nb = (int64_t)ctx->bsr_col.size();
+    HIPC(hipMemcpy(ctx->p<void>(L.bsr_ptr), ctx->bsr_ptr.data(), sizeof(int32_t) * (nn + 1), hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(ctx->p<void>(L.bsr_col), ctx->bsr_col.data(), sizeof(int32_t) * nb, hipMemcpyHostToDevice));
+    HIPC(hipMemcpy(ctx->p<void>(L.adj_slot), ctx->adj_slot.data(), sizeof(int2) * 3 * ne, hipMemcpyHostToDevice));
+    HIPC(launch_bsr_assemble((int32_t)nn, (int32_t)ld, ctx->p<int32_t>(L.adj_ptr), ctx->p<int32_t>(L.adj_el),
+                             ctx->p<uint8_t>(L.adj_loc), ctx->p<int2>(L.adj_slot), ctx->p<int32_t>(L.bsr_ptr),
+                             ctx->p<double>(L.khat), ctx->p<double>(L.eh64), ctx->p<double>(L.bsr64), st));
+    HIPC(launch_cast_f32(9 * nb, ctx->p<double>(L.bsr64), ctx->p<float>(L.bsr32), st));
+  }
   HIPC(launch_lumped_mass((int32_t)nn, (int32_t)ld, ctx->p<int32_t>(L.adj_ptr), ctx->p<int32_t>(L.adj_el),
                           ctx->p<double>(L.area), ctx->p<double>(L.h), ctx->rho,
                           ctx->p<double>(L.minv64), ctx->p<float>(L.minv32), st));
@@ -378,7 +436,7 @@ int32_t ens_info(ens_ctx* ctx, ens_info_t* out) {
   out->sample_block = ctx->SB;
   out->apply_prec = ctx->apply_prec;
   out->state_prec = ctx->state_prec;
-  out->variant = ctx->variant;
+  out->variant = use_shared(ctx) ? ENS_VARIANT_CSR_SHARED : ENS_VARIANT_NODE_GATHER;
   out->shared_stiffness = ctx->shared ? 1 : 0;
   out->steps_done = ctx->steps;
   out->dt = ctx->dt;
@@ -513,11 +571,11 @@ int32_t ens_configure(ens_ctx* ctx, int32_t apply_prec, int32_t state_prec, int3
     return ctx->fail(ENS_EINVAL, "ens_configure: unknown state precision");
   if (state_prec != ENS_STATE_F64 && apply_prec != ENS_F32)
     return ctx->fail(ENS_EUNSUPPORTED, "ens_configure: FP32 states need the FP32 apply");
-  if (variant != ENS_VARIANT_AUTO && variant != ENS_VARIANT_NODE_GATHER)
-    return ctx->fail(ENS_EUNSUPPORTED, "ens_configure: variant not available");
+  if (variant != ENS_VARIANT_AUTO && variant != ENS_VARIANT_NODE_GATHER && variant != ENS_VARIANT_CSR_SHARED)
+    return ctx->fail(ENS_EINVAL, "ens_configure: unknown variant");
   if (qoi_mask & ~ENS_QOI_PEAK_RADIAL) return ctx->fail(ENS_EINVAL, "ens_configure: unknown QoI bit");
   if (energy_every < 0) return ctx->fail(ENS_EINVAL, "ens_configure: energy_every must be >= 0");
-  const bool relayout = state_prec != ctx->state_prec;
+  const bool relayout = state_prec != ctx->state_prec || variant != ctx->variant;
   ctx->apply_prec = apply_prec;
   ctx->state_prec = state_prec;
   ctx->variant = variant;
@@ -545,6 +603,8 @@ int32_t ens_bind_workspace(ens_ctx* ctx, void* dptr, size_t bytes) {
   GUARD_BEGIN
   std::string why;
   if (!ready_for_workspace(ctx, &why)) return ctx->fail(ENS_ESTATE, "ens_bind_workspace: " + why);
+  if (ctx->variant == ENS_VARIANT_CSR_SHARED && !ctx->shared)
+    return ctx->fail(ENS_EUNSUPPORTED, "ens_bind_workspace: the shared-stiffness variant needs (E h) constant over samples");
   const Layout L = plan(ctx);
   if (!dptr || (reinterpret_cast<uintptr_t>(dptr) % kAlign) != 0)
     return ctx->fail(ENS_EWORKSPACE, "ens_bind_workspace: null or unaligned (256 B) buffer");
@@ -645,7 +705,7 @@ int32_t run_starter(ens_ctx* ctx, double dt, hipStream_t st) {
       HIPC(hipMemsetAsync(R, 0, sizeof(double) * n, st));
     } else {
       StepArgs a = base_args(ctx, false);
-      HIPC(launch_apply(a, false, ctx->SB, ctx->p<double>(L.u[ctx->cur]), R, st));
+      HIPC(launch_apply(a, false, ctx->SB, use_shared(ctx), ctx->p<double>(L.u[ctx->cur]), R, st));
     }
     HIPC(launch_starter_f64((int32_t)ctx->n_nodes, ctx->ld, R, ctx->p<double>(L.minv64), ctx->p<double>(L.F),
                             ctx->p<uint8_t>(L.fixed), ctx->p<double>(L.u[ctx->cur]),
@@ -656,7 +716,7 @@ int32_t run_starter(ens_ctx* ctx, double dt, hipStream_t st) {
       HIPC(hipMemsetAsync(R, 0, sizeof(float) * n, st));
     } else {
       StepArgs a = base_args(ctx, true);
-      HIPC(launch_apply(a, true, ctx->SB, ctx->p<float>(L.uh[ctx->cur]), R, st));
+      HIPC(launch_apply(a, true, ctx->SB, use_shared(ctx), ctx->p<float>(L.uh[ctx->cur]), R, st));
     }
     HIPC(launch_starter_f32((int32_t)ctx->n_nodes, ctx->ld, R, ctx->p<float>(L.minv32), ctx->p<double>(L.F),
                             ctx->p<uint8_t>(L.fixed), ctx->p<float>(L.v), ctx->p<double>(L.gtab), dt,
@@ -731,7 +791,7 @@ int32_t ens_step(ens_ctx* ctx, int64_t n_steps, double dt, int32_t force, void* 
         a.uc = ctx->state_prec == ENS_STATE_F32_KAHAN ? ctx->p<float>(L.uc) : nullptr;
         a.v = ctx->p<float>(L.v);
       }
-      HIPC(launch_step(a, f32, ctx->state_prec, ctx->SB, qoi, energy, st));
+      HIPC(launch_step(a, f32, ctx->state_prec, ctx->SB, qoi, energy, use_shared(ctx), st));
       if (energy) {
         const int64_t rec = ctx->energy_records % kEnergyCap;
         HIPC(launch_energy_reduce(ctx->p<double>(L.epart), a.n_nb, ctx->ld, ctx->ld,
@@ -859,7 +919,8 @@ int32_t ens_apply(ens_ctx* ctx, int32_t prec, const void* U_dev, void* R_dev, vo
   if (!U_dev || !R_dev) return ctx->fail(ENS_EINVAL, "ens_apply: null device buffer");
   HIPC(hipSetDevice(ctx->device));
   StepArgs a = base_args(ctx, prec == ENS_F32);
-  HIPC(launch_apply(a, prec == ENS_F32, ctx->SB, U_dev, R_dev, static_cast<hipStream_t>(stream)));
+  HIPC(launch_apply(a, prec == ENS_F32, ctx->SB, use_shared(ctx), U_dev, R_dev,
+                    static_cast<hipStream_t>(stream)));
   return ENS_OK;
 }
 

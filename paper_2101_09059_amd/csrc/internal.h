@@ -32,6 +32,16 @@ struct Adjacency {
   const void* k;  // double[18] or float[18] per entry
 };
 
+// Shared-stiffness block rows (used when (E h)_{e,s} does not depend on s):
+// for node i, blocks ptr[i] .. ptr[i+1]-1 hold K_ij (3x3, row-major) for
+// every neighbour j != i, with the diagonal block implied by the rows'
+// translation null space: (K u)_i = sum_j K_ij (u_j - u_i).
+struct BlockRows {
+  const int32_t* ptr;
+  const int32_t* col;
+  const void* val;  // double[9] or float[9] per block
+};
+
 // State storage modes.
 enum StateMode { kStateF64 = 0, kStateF32Kahan = 1, kStateF32 = 2 };
 
@@ -42,6 +52,7 @@ struct StepArgs {
   int32_t n_sb;        // sample blocks
   int32_t sb_inner;    // workgroup order: sample block fastest (1) or node block fastest (0)
   Adjacency adj;
+  BlockRows bsr;
   const void* eh;      // (E h)_{e,s} in the apply precision, [n_el][ld]
   const void* minv;    // 1/m per node and sample, double (F64 apply) or float, [n_nodes][ld]
   const double* F;     // nodal load [n_nodes][3]
@@ -82,14 +93,18 @@ hipError_t launch_cfl_max(int64_t n_el, int32_t ld, int32_t S, const double* eh,
                           const double* lam, const double* area, double rho,
                           unsigned long long* out_bits, hipStream_t st);
 hipError_t launch_cast_f32(int64_t n, const double* src, float* dst, hipStream_t st);
+hipError_t launch_bsr_assemble(int32_t n_nodes, int32_t ld, const int32_t* adj_ptr,
+                               const int32_t* adj_el, const uint8_t* adj_loc, const int2* adj_slot,
+                               const int32_t* bsr_ptr, const double* khat, const double* eh,
+                               double* bsr64, hipStream_t st);
 
 // ---- time-stepping kernels (step.hip) -------------------------------------
 // One explicit step of the node-gather fused kernel.  apply_f32 selects
 // the apply precision; mode the state storage; qoi / energy the outputs.
 hipError_t launch_step(const StepArgs& a, bool apply_f32, int mode, int sample_block, bool qoi,
-                       bool energy, hipStream_t st);
-hipError_t launch_apply(const StepArgs& a, bool f32, int sample_block, const void* U, void* R,
-                        hipStream_t st);
+                       bool energy, bool shared, hipStream_t st);
+hipError_t launch_apply(const StepArgs& a, bool f32, int sample_block, bool shared, const void* U,
+                        void* R, hipStream_t st);
 hipError_t launch_schedule(double* gtab, int64_t* base, int32_t k, double dt, Schedule s,
                            hipStream_t st);
 hipError_t launch_advance(int64_t* base, int32_t k, hipStream_t st);

@@ -239,6 +239,36 @@ __global__ __launch_bounds__(256) void k_cfl_max(int64_t n_el, int32_t ld, int32
   if (threadIdx.x == 0) atomicMax(out_bits, (unsigned long long)__double_as_longlong(red[0]));
 }
 
+// Shared-stiffness block rows: K_ij = sum over the elements e containing
+// both i and j of (E h)_e Khat_e[i, j] (3x3), summed in adjacency order by
+// the thread that owns row i.  adj_slot[k] = (block of b, block of c).
+__global__ __launch_bounds__(256) void k_bsr_assemble(int32_t n_nodes, int32_t ld,
+                                                      const int32_t* __restrict__ adj_ptr,
+                                                      const int32_t* __restrict__ adj_el,
+                                                      const uint8_t* __restrict__ adj_loc,
+                                                      const int2* __restrict__ adj_slot,
+                                                      const int32_t* __restrict__ bsr_ptr,
+                                                      const double* __restrict__ khat,
+                                                      const double* __restrict__ eh,
+                                                      double* __restrict__ bsr) {
+  const int node = blockIdx.x * 256 + threadIdx.x;
+  if (node >= n_nodes) return;
+  for (int64_t k = (int64_t)bsr_ptr[node] * 9; k < (int64_t)bsr_ptr[node + 1] * 9; ++k) bsr[k] = 0.0;
+  for (int k = adj_ptr[node]; k < adj_ptr[node + 1]; ++k) {
+    const int64_t e = adj_el[k];
+    const int a = adj_loc[k];
+    const double w = eh[e * ld];
+    const int2 sl = adj_slot[k];
+    const double* K = khat + 81 * e;
+    for (int t = 0; t < 2; ++t) {
+      const int other = (a + 1 + t) % 3;
+      double* B = bsr + 9 * (int64_t)(t == 0 ? sl.x : sl.y);
+      for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) B[3 * r + c] += w * K[9 * (3 * a + r) + 3 * other + c];
+    }
+  }
+}
+
 __global__ __launch_bounds__(256) void k_cast_f32(int64_t n, const double* __restrict__ src,
                                                   float* __restrict__ dst) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -282,6 +312,16 @@ hipError_t launch_cfl_max(int64_t n_el, int32_t ld, int32_t S, const double* eh,
   const int64_t n = n_el * S;
   if (n == 0) return hipSuccess;
   k_cfl_max<<<grid_for(n, 256), 256, 0, st>>>(n_el, ld, S, eh, h, lam, area, rho, out_bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_bsr_assemble(int32_t n_nodes, int32_t ld, const int32_t* adj_ptr,
+                               const int32_t* adj_el, const uint8_t* adj_loc, const int2* adj_slot,
+                               const int32_t* bsr_ptr, const double* khat, const double* eh,
+                               double* bsr64, hipStream_t st) {
+  if (n_nodes == 0) return hipSuccess;
+  k_bsr_assemble<<<grid_for(n_nodes, 256), 256, 0, st>>>(n_nodes, ld, adj_ptr, adj_el, adj_loc, adj_slot,
+                                                          bsr_ptr, khat, eh, bsr64);
   return hipGetLastError();
 }
 

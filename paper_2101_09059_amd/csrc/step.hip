@@ -145,10 +145,41 @@ __device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_
   }
 }
 
+// Shared stiffness: R_i = sum_j K_ij (u_j - u_i) over the assembled
+// off-diagonal 3x3 blocks of row i.
+template <typename AT, typename ST, int SPL>
+__device__ __forceinline__ void gather_blocks(const StepArgs& p, int node, int64_t ld, int s0,
+                                              const ST* __restrict__ U, const ST (&ua)[3][SPL],
+                                              AT (&r)[3][SPL]) {
+  const int kb = p.bsr.ptr[node];
+  const int ke = p.bsr.ptr[node + 1];
+  const AT* __restrict__ V = static_cast<const AT*>(p.bsr.val);
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < SPL; ++i) r[c][i] = AT(0);
+#pragma unroll 2
+  for (int k = kb; k < ke; ++k) {
+    const int64_t rj = (int64_t)p.bsr.col[k] * 3;
+    const AT* __restrict__ B = V + (int64_t)k * 9;
+    ST uj[3][SPL];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (rj + c) * ld + s0, uj[c]);
+#pragma unroll
+    for (int i = 0; i < SPL; ++i) {
+      const AT d0 = (AT)(uj[0][i] - ua[0][i]);
+      const AT d1 = (AT)(uj[1][i] - ua[1][i]);
+      const AT d2 = (AT)(uj[2][i] - ua[2][i]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) r[c][i] = fma(B[3 * c + 2], d2, fma(B[3 * c + 1], d1, fma(B[3 * c], d0, r[c][i])));
+    }
+  }
+}
+
 // LPN lanes per node, SPL consecutive samples per lane: a workgroup covers
 // kBlock/LPN nodes times LPN*SPL samples.  With LPN = 64 a wave owns one
 // node, so adjacency and stiffness blocks are wave-uniform (scalar loads).
-template <typename AT, int MODE, int LPN, int SPL, bool QOI, bool ENERGY>
+template <typename AT, int MODE, int LPN, int SPL, bool QOI, bool ENERGY, bool SHARED>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
   constexpr int SB = LPN * SPL;
   constexpr int NPB = kBlock / LPN;
@@ -173,7 +204,8 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (row + c) * ld + s0, ua[c]);
     AT r[3][SPL];
-    gather_apply<AT, ST, SPL>(p, node, ld, s0, U, ua, r);
+    if constexpr (SHARED) gather_blocks<AT, ST, SPL>(p, node, ld, s0, U, ua, r);
+    else gather_apply<AT, ST, SPL>(p, node, ld, s0, U, ua, r);
 
     const double g = p.gtab[p.j];
     const unsigned fx = p.fixed[node];
@@ -323,7 +355,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
   }
 }
 
-template <typename AT, int LPN, int SPL>
+template <typename AT, int LPN, int SPL, bool SHARED>
 __global__ __launch_bounds__(kBlock) void k_apply(StepArgs p, const AT* __restrict__ U,
                                                   AT* __restrict__ R) {
   constexpr int SB = LPN * SPL;
@@ -340,7 +372,8 @@ __global__ __launch_bounds__(kBlock) void k_apply(StepArgs p, const AT* __restri
 #pragma unroll
   for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (row + c) * ld + s0, ua[c]);
   AT r[3][SPL];
-  gather_apply<AT, AT, SPL>(p, node, ld, s0, U, ua, r);
+  if constexpr (SHARED) gather_blocks<AT, AT, SPL>(p, node, ld, s0, U, ua, r);
+  else gather_apply<AT, AT, SPL>(p, node, ld, s0, U, ua, r);
 #pragma unroll
   for (int c = 0; c < 3; ++c) vstore<SPL, true>(R + (row + c) * ld + s0, r[c]);
 }
@@ -542,41 +575,47 @@ inline unsigned step_grid(const StepArgs& a) {
   return (unsigned)(((n + 7) / 8) * 8);
 }
 
-template <typename AT, int MODE, int LPN, int SPL>
+template <typename AT, int MODE, int LPN, int SPL, bool SH>
 hipError_t dispatch_flags(const StepArgs& a, bool qoi, bool energy, hipStream_t st) {
   const unsigned g = step_grid(a);
-  if (qoi && energy) k_step<AT, MODE, LPN, SPL, true, true><<<g, kBlock, 0, st>>>(a);
-  else if (qoi) k_step<AT, MODE, LPN, SPL, true, false><<<g, kBlock, 0, st>>>(a);
-  else if (energy) k_step<AT, MODE, LPN, SPL, false, true><<<g, kBlock, 0, st>>>(a);
-  else k_step<AT, MODE, LPN, SPL, false, false><<<g, kBlock, 0, st>>>(a);
+  if (qoi && energy) k_step<AT, MODE, LPN, SPL, true, true, SH><<<g, kBlock, 0, st>>>(a);
+  else if (qoi) k_step<AT, MODE, LPN, SPL, true, false, SH><<<g, kBlock, 0, st>>>(a);
+  else if (energy) k_step<AT, MODE, LPN, SPL, false, true, SH><<<g, kBlock, 0, st>>>(a);
+  else k_step<AT, MODE, LPN, SPL, false, false, SH><<<g, kBlock, 0, st>>>(a);
   return hipGetLastError();
 }
 
-template <typename AT, int MODE>
+template <typename AT, int MODE, bool SH>
 hipError_t dispatch_sb(const StepArgs& a, int sb, bool qoi, bool energy, hipStream_t st) {
   switch (sb) {
-    case 8: return dispatch_flags<AT, MODE, 8, 1>(a, qoi, energy, st);
-    case 16: return dispatch_flags<AT, MODE, 16, 1>(a, qoi, energy, st);
-    case 32: return dispatch_flags<AT, MODE, 32, 1>(a, qoi, energy, st);
-    case 64: return dispatch_flags<AT, MODE, 64, 1>(a, qoi, energy, st);
-    case 128: return dispatch_flags<AT, MODE, 64, 2>(a, qoi, energy, st);
-    case 256: return dispatch_flags<AT, MODE, 64, 4>(a, qoi, energy, st);
+    case 8: return dispatch_flags<AT, MODE, 8, 1, SH>(a, qoi, energy, st);
+    case 16: return dispatch_flags<AT, MODE, 16, 1, SH>(a, qoi, energy, st);
+    case 32: return dispatch_flags<AT, MODE, 32, 1, SH>(a, qoi, energy, st);
+    case 64: return dispatch_flags<AT, MODE, 64, 1, SH>(a, qoi, energy, st);
+    case 128: return dispatch_flags<AT, MODE, 64, 2, SH>(a, qoi, energy, st);
+    case 256: return dispatch_flags<AT, MODE, 64, 4, SH>(a, qoi, energy, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <typename AT>
+template <typename AT, int MODE>
+hipError_t dispatch_shared(const StepArgs& a, int sb, bool qoi, bool energy, bool shared, hipStream_t st) {
+  return shared ? dispatch_sb<AT, MODE, true>(a, sb, qoi, energy, st)
+                : dispatch_sb<AT, MODE, false>(a, sb, qoi, energy, st);
+}
+
+template <typename AT, bool SH>
 hipError_t dispatch_apply(const StepArgs& a, int sb, const void* U, void* R, hipStream_t st) {
   const unsigned g = step_grid(a);
   const AT* u = static_cast<const AT*>(U);
   AT* r = static_cast<AT*>(R);
   switch (sb) {
-    case 8: k_apply<AT, 8, 1><<<g, kBlock, 0, st>>>(a, u, r); break;
-    case 16: k_apply<AT, 16, 1><<<g, kBlock, 0, st>>>(a, u, r); break;
-    case 32: k_apply<AT, 32, 1><<<g, kBlock, 0, st>>>(a, u, r); break;
-    case 64: k_apply<AT, 64, 1><<<g, kBlock, 0, st>>>(a, u, r); break;
-    case 128: k_apply<AT, 64, 2><<<g, kBlock, 0, st>>>(a, u, r); break;
-    case 256: k_apply<AT, 64, 4><<<g, kBlock, 0, st>>>(a, u, r); break;
+    case 8: k_apply<AT, 8, 1, SH><<<g, kBlock, 0, st>>>(a, u, r); break;
+    case 16: k_apply<AT, 16, 1, SH><<<g, kBlock, 0, st>>>(a, u, r); break;
+    case 32: k_apply<AT, 32, 1, SH><<<g, kBlock, 0, st>>>(a, u, r); break;
+    case 64: k_apply<AT, 64, 1, SH><<<g, kBlock, 0, st>>>(a, u, r); break;
+    case 128: k_apply<AT, 64, 2, SH><<<g, kBlock, 0, st>>>(a, u, r); break;
+    case 256: k_apply<AT, 64, 4, SH><<<g, kBlock, 0, st>>>(a, u, r); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -585,25 +624,29 @@ hipError_t dispatch_apply(const StepArgs& a, int sb, const void* U, void* R, hip
 }  // namespace
 
 hipError_t launch_step(const StepArgs& a, bool apply_f32, int mode, int sample_block, bool qoi,
-                       bool energy, hipStream_t st) {
+                       bool energy, bool shared, hipStream_t st) {
   if (a.n_nb == 0 || a.n_sb == 0) return hipSuccess;
   if (!apply_f32) {
     if (mode != kStateF64) return hipErrorInvalidValue;
-    return dispatch_sb<double, kStateF64>(a, sample_block, qoi, energy, st);
+    return dispatch_shared<double, kStateF64>(a, sample_block, qoi, energy, shared, st);
   }
   switch (mode) {
-    case kStateF64: return dispatch_sb<float, kStateF64>(a, sample_block, qoi, energy, st);
-    case kStateF32Kahan: return dispatch_sb<float, kStateF32Kahan>(a, sample_block, qoi, energy, st);
-    case kStateF32: return dispatch_sb<float, kStateF32>(a, sample_block, qoi, energy, st);
+    case kStateF64: return dispatch_shared<float, kStateF64>(a, sample_block, qoi, energy, shared, st);
+    case kStateF32Kahan:
+      return dispatch_shared<float, kStateF32Kahan>(a, sample_block, qoi, energy, shared, st);
+    case kStateF32: return dispatch_shared<float, kStateF32>(a, sample_block, qoi, energy, shared, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_apply(const StepArgs& a, bool f32, int sample_block, const void* U, void* R,
-                        hipStream_t st) {
+hipError_t launch_apply(const StepArgs& a, bool f32, int sample_block, bool shared, const void* U,
+                        void* R, hipStream_t st) {
   if (a.n_nb == 0 || a.n_sb == 0) return hipSuccess;
-  return f32 ? dispatch_apply<float>(a, sample_block, U, R, st)
-             : dispatch_apply<double>(a, sample_block, U, R, st);
+  if (shared)
+    return f32 ? dispatch_apply<float, true>(a, sample_block, U, R, st)
+               : dispatch_apply<double, true>(a, sample_block, U, R, st);
+  return f32 ? dispatch_apply<float, false>(a, sample_block, U, R, st)
+             : dispatch_apply<double, false>(a, sample_block, U, R, st);
 }
 
 hipError_t launch_schedule(double* gtab, int64_t* base, int32_t k, double dt, Schedule s,

@@ -269,14 +269,14 @@ class Ensemble:
 def setup_case(mesh, eh, h, F, nu=0.49, shear_k=5.0 / 6.0, rho=1.0, alpha=50.0,
                kind=LOAD_STEP, t_ramp=0.0, amp=0.0, period=1.0, apply_prec=F64,
                state_prec=STATE_F64, qoi=True, energy_every=0, device=0,
-               sample_block=0, sb_inner=False) -> Ensemble:
+               sample_block=0, sb_inner=False, variant=VARIANT_AUTO) -> Ensemble:
     """Create, fill, configure and bind a context for one mesh and ensemble."""
     ens = Ensemble(device)
     ens.set_mesh(mesh.xyz, mesh.tri, mesh.fixed, mesh.radial)
     ens.set_material(nu, shear_k, rho, alpha)
     ens.set_ensemble(eh, h)
     ens.set_load(F, kind, t_ramp, amp, period)
-    ens.configure(apply_prec, state_prec, VARIANT_AUTO, qoi, energy_every)
+    ens.configure(apply_prec, state_prec, variant, qoi, energy_every)
     if sample_block or sb_inner:
         ens.set_tuning(sample_block, sb_inner)
     ens.bind_workspace()

@@ -319,3 +319,75 @@ def test_step_bitwise_independent_of_sample_block(state):
     for o in outs[1:]:
         for a, b in zip(outs[0], o):
             assert np.array_equal(a, b)
+
+
+def _shared_case(nt, nz, S, seed):
+    cs = small_case(nt, nz, S, seed=seed)
+    cs.eh = np.repeat(cs.eh[:, :1], S, axis=1).copy()
+    from oracle import cfl as _cfl
+    cs.dt = _cfl.stable_dt(cs.khat, cs.area, cs.eh, cs.h, 1.0, 0.9)
+    return cs
+
+
+@pytest.mark.parametrize("prec", [ensfem.F64, ensfem.F32])
+@pytest.mark.parametrize("S", [5, 128, 200])
+def test_shared_stiffness_block_product(prec, S):
+    """Shared (E h): K assembled once as 3x3 block rows, applied to the
+    ensemble block; equals the oracle's K U and the element-by-element path."""
+    say(f"case: shared-stiffness product S={S} prec={prec}")
+    cs = _shared_case(29, 15, S, seed=S)
+    ens = _ctx(cs)
+    assert ens.info()["shared_stiffness"] == 1 and ens.info()["variant"] == ensfem.VARIANT_CSR_SHARED
+    ld = ens.info()["S_pad"]
+    dt = torch.float64 if prec == ensfem.F64 else torch.float32
+    rng = np.random.default_rng(S + 1)
+    Ud = torch.zeros((cs.mesh.n_dof, ld), dtype=dt, device="cuda")
+    Ud[:, :S] = torch.from_numpy(rng.standard_normal((cs.mesh.n_dof, S))).to(dt)
+    Rd = torch.empty_like(Ud)
+    ens.apply(Ud, Rd, prec)
+    eg = _ctx(cs, variant=ensfem.VARIANT_NODE_GATHER)
+    Rg = torch.empty_like(Ud)
+    eg.apply(Ud, Rg, prec)
+    torch.cuda.synchronize()
+    R = Rd[:, :S].double().cpu().numpy()
+    ref = oracle_apply(cs, Ud[:, :S].double().cpu().numpy())
+    tol = 1e-13 if prec == ensfem.F64 else 1e-5
+    err = np.linalg.norm(R - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert err.max() <= tol
+    Rgn = Rg[:, :S].double().cpu().numpy()
+    assert (np.linalg.norm(R - Rgn, axis=0) / np.linalg.norm(Rgn, axis=0)).max() <= tol
+    ens.close()
+    eg.close()
+
+
+@pytest.mark.parametrize("mode,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_shared_stiffness_time_stepping(mode, tol):
+    cs = _shared_case(24, 14, 16, seed=9)
+    kw = {} if mode == "f64" else dict(apply_prec=ensfem.F32)
+    say(f"case: shared-stiffness stepping {mode}")
+    ens = _ctx(cs, kind=ensfem.LOAD_RAMP_SINE, t_ramp=0.01, **kw)
+    assert ens.info()["variant"] == ensfem.VARIANT_CSR_SHARED
+    ens.init_state()
+    n = 2000
+    ens.step(n, cs.dt)
+    u, q = ens.read_state(), ens.read_qoi()
+    ens.close()
+    g = lambda t: stepper.load_factor("sine", t, 0.01)
+    ref = stepper.run_ensemble(cs.mesh.tri, cs.khat, cs.area, cs.eh, cs.h, 1.0, cs.F, cs.mesh.fixed,
+                               cs.mesh.radial, cs.dt, n, 50.0, g)
+    assert rel_l2(u, ref["u"]) <= tol
+    assert rel_l2(q, ref["q"]) <= tol
+
+
+def test_shared_variant_rejected_for_sample_dependent_stiffness():
+    cs = small_case(12, 6, 4, seed=2)
+    ens = ensfem.Ensemble(0)
+    ens.set_mesh(cs.mesh.xyz, cs.mesh.tri, cs.mesh.fixed, cs.mesh.radial)
+    ens.set_material(0.49, 5 / 6, 1.0, 50.0)
+    ens.set_ensemble(cs.eh, cs.h)
+    ens.set_load(cs.F)
+    ens.configure(variant=ensfem.VARIANT_CSR_SHARED)
+    with pytest.raises(ensfem.EnsfemError) as ei:
+        ens.bind_workspace()
+    assert ei.value.code == ensfem.ENS_EUNSUPPORTED
+    ens.close()
