@@ -151,8 +151,9 @@ int32_t ens_cfl_dt(ens_ctx* ctx, double safety, double* dt_out);
 int32_t ens_init_state(ens_ctx* ctx, const double* u0, const double* v0);
 
 /* Enqueue n_steps explicit steps of size dt on `stream` (hipStream_t).  dt
- * is fixed by the first call after ens_init_state; later calls must pass the
- * same value (ENS_EINVAL otherwise).  ENS_EUNSTABLE if dt exceeds the
+ * is fixed by the first call after ens_init_state (which also forms the
+ * starter, even with n_steps = 0); later calls must pass the same value
+ * (ENS_EINVAL otherwise).  ENS_EUNSTABLE if dt exceeds the
  * stability bound (2 / omega_hat) unless `force` is nonzero.  ENS_ESTATE if
  * mesh, ensemble, load, state or workspace is missing. */
 int32_t ens_step(ens_ctx* ctx, int64_t n_steps, double dt, int32_t force, void* stream);
@@ -187,6 +188,42 @@ int32_t ens_set_tuning(ens_ctx* ctx, int32_t sample_block, int32_t sb_inner);
  * QoI).  ens_save with host == NULL writes the size to *bytes. */
 int32_t ens_save(ens_ctx* ctx, void* host, size_t* bytes);
 int32_t ens_load(ens_ctx* ctx, const void* host, size_t bytes);
+
+/* ---- Batching: many meshes per launch ---------------------------------
+ * A batch steps several contexts together (one persistent launch per time
+ * step whose workgroups walk a list of (mesh, node tile, sample block)
+ * tiles; the step loop is captured in a hipGraph and replayed).  Each
+ * context keeps its own mesh, fields, load, dt and state and stays usable
+ * on its own between batch calls.  Requirements (ENS_EINVAL otherwise, the
+ * message on the offending context): bound workspaces on one device, the
+ * same apply / state precision and QoI setting, node-gather variant, no
+ * energy records, padded width S_pad a multiple of 64.  The batch owns
+ * small device tables (tiles, per-mesh arguments) and a stream of its own;
+ * ens_batch_step orders itself after prior work on `stream` and makes
+ * `stream` wait for it. */
+typedef struct ens_batch ens_batch;
+typedef struct {
+  int32_t n_meshes, n_tiles;
+  int32_t samples_per_lane; /* 64 lanes x this many samples per tile      */
+  int32_t tile_nodes;       /* nodes per tile                            */
+  int32_t grid;             /* persistent workgroups per launch          */
+  int32_t graph_steps;      /* steps per captured graph                  */
+  double tuned_ms_per_step; /* best autotuner trial, 0 before autotune   */
+} ens_batch_info_t;
+
+int32_t ens_batch_create(ens_ctx** ctxs, int32_t n, ens_batch** out);
+int32_t ens_batch_destroy(ens_batch* b);
+const char* ens_batch_last_error(const ens_batch* b);
+int32_t ens_batch_info(ens_batch* b, ens_batch_info_t* out);
+/* n_steps steps of every mesh.  Every context must have its state set and
+ * dt fixed (ens_init_state, then ens_step(ctx, 0, dt, ...)).  Results are
+ * bitwise those of stepping each context alone. */
+int32_t ens_batch_step(ens_batch* b, int64_t n_steps, void* stream);
+/* Times trial_steps steps for each candidate tiling (samples per lane 1 or
+ * 2, 4/16/64 nodes per tile, 2/4/8 workgroups per compute unit) and keeps
+ * the fastest.  The trial steps ADVANCE every context's state: re-init the
+ * states afterwards to restart from the initial condition. */
+int32_t ens_batch_autotune(ens_batch* b, int32_t trial_steps);
 
 #ifdef __cplusplus
 }

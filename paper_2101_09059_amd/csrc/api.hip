@@ -83,6 +83,7 @@ struct ens_ctx {
   int64_t energy_records = 0;
   std::vector<int64_t> energy_steps;
   hipStream_t last_stream = nullptr;
+  uint64_t gen = 0;  // bumped by every change a captured step graph depends on
 
   template <class T>
   T* p(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -333,6 +334,22 @@ StepArgs base_args(const ens_ctx* c, bool f32) {
   return a;
 }
 
+// State buffers of the step whose current displacement is buffer
+// cur ^ flip.
+void set_state_ptrs(const ens_ctx* c, StepArgs& a, int flip) {
+  const int cur = c->cur ^ flip;
+  if (c->state_prec == ENS_STATE_F64) {
+    a.u_cur = c->p<double>(c->L.u[cur]);
+    a.u_prev = c->p<double>(c->L.u[1 - cur]);
+    a.u_next = c->p<double>(c->L.u[1 - cur]);
+  } else {
+    a.uh_cur = c->p<float>(c->L.uh[cur]);
+    a.uh_next = c->p<float>(c->L.uh[1 - cur]);
+    a.uc = c->state_prec == ENS_STATE_F32_KAHAN ? c->p<float>(c->L.uc) : nullptr;
+    a.v = c->p<float>(c->L.v);
+  }
+}
+
 // pad [rows][S] host data to [rows][ld], pads copy column 0
 void pad_rows(const double* src, int64_t rows, int S, int ld, std::vector<double>& dst) {
   dst.resize((size_t)rows * ld);
@@ -447,6 +464,7 @@ int32_t ens_info(ens_ctx* ctx, ens_info_t* out) {
 int32_t ens_set_mesh(ens_ctx* ctx, int64_t n_nodes, const double* xyz, int64_t n_el,
                      const int32_t* tri, const uint8_t* fixed_dof, const double* radial) {
   if (!ctx) return ENS_EINVAL;
+  ctx->gen++;
   GUARD_BEGIN
   if (n_nodes < 3 || n_el < 1 || !xyz || !tri || !fixed_dof || !radial)
     return ctx->fail(ENS_EINVAL, "ens_set_mesh: need n_nodes >= 3, n_el >= 1 and non-null arrays");
@@ -497,6 +515,7 @@ int32_t ens_set_mesh(ens_ctx* ctx, int64_t n_nodes, const double* xyz, int64_t n
 
 int32_t ens_set_material(ens_ctx* ctx, double nu, double shear_k, double rho, double alpha) {
   if (!ctx) return ENS_EINVAL;
+  ctx->gen++;
   if (!(nu >= 0.0 && nu < 0.5) || !(shear_k >= 0.0) || !(rho > 0.0) || !(alpha >= 0.0) ||
       !std::isfinite(shear_k) || !std::isfinite(rho) || !std::isfinite(alpha))
     return ctx->fail(ENS_EINVAL, "ens_set_material: need 0 <= nu < 0.5, k >= 0, rho > 0, alpha >= 0");
@@ -512,6 +531,7 @@ int32_t ens_set_material(ens_ctx* ctx, double nu, double shear_k, double rho, do
 
 int32_t ens_set_ensemble(ens_ctx* ctx, int32_t S, const double* eh, const double* h) {
   if (!ctx) return ENS_EINVAL;
+  ctx->gen++;
   GUARD_BEGIN
   if (!ctx->have_mesh) return ctx->fail(ENS_ESTATE, "ens_set_ensemble: set the mesh first");
   if (S < 1 || !eh || !h) return ctx->fail(ENS_EINVAL, "ens_set_ensemble: need S >= 1 and non-null arrays");
@@ -539,6 +559,7 @@ int32_t ens_set_ensemble(ens_ctx* ctx, int32_t S, const double* eh, const double
 
 int32_t ens_set_load(ens_ctx* ctx, const double* F, ens_schedule sched) {
   if (!ctx) return ENS_EINVAL;
+  ctx->gen++;
   GUARD_BEGIN
   if (!ctx->have_mesh) return ctx->fail(ENS_ESTATE, "ens_set_load: set the mesh first");
   if (!F) return ctx->fail(ENS_EINVAL, "ens_set_load: null load");
@@ -565,6 +586,7 @@ int32_t ens_set_load(ens_ctx* ctx, const double* F, ens_schedule sched) {
 int32_t ens_configure(ens_ctx* ctx, int32_t apply_prec, int32_t state_prec, int32_t variant,
                       int32_t qoi_mask, int32_t energy_every) {
   if (!ctx) return ENS_EINVAL;
+  ctx->gen++;
   if (apply_prec != ENS_F64 && apply_prec != ENS_F32)
     return ctx->fail(ENS_EINVAL, "ens_configure: apply_prec must be ENS_F64 or ENS_F32");
   if (state_prec < ENS_STATE_F64 || state_prec > ENS_STATE_F32)
@@ -600,6 +622,7 @@ int32_t ens_workspace_size(ens_ctx* ctx, size_t* bytes) {
 
 int32_t ens_bind_workspace(ens_ctx* ctx, void* dptr, size_t bytes) {
   if (!ctx) return ENS_EINVAL;
+  ctx->gen++;
   GUARD_BEGIN
   std::string why;
   if (!ready_for_workspace(ctx, &why)) return ctx->fail(ENS_ESTATE, "ens_bind_workspace: " + why);
@@ -634,6 +657,7 @@ int32_t ens_cfl_dt(ens_ctx* ctx, double safety, double* dt_out) {
 
 int32_t ens_init_state(ens_ctx* ctx, const double* u0, const double* v0) {
   if (!ctx) return ENS_EINVAL;
+  ctx->gen++;
   GUARD_BEGIN
   if (!ctx->bound) return ctx->fail(ENS_EWORKSPACE, "ens_init_state: bind a workspace first");
   const Layout& L = ctx->L;
@@ -767,30 +791,23 @@ int32_t ens_step(ens_ctx* ctx, int64_t n_steps, double dt, int32_t force, void* 
   StepArgs a = base_args(ctx, f32);
   a.dt = dt;
   a.a = 0.5 * ctx->alpha * dt;
+  if (!ctx->started) {  // Taylor starter at t = 0, fixes dt
+    HIPC(launch_schedule(ctx->p<double>(L.gtab), ctx->p<int64_t>(L.base), 1, dt, ctx->sched, st));
+    const int32_t rc = run_starter(ctx, dt, st);
+    if (rc != ENS_OK) return rc;
+    ctx->started = true;
+    ctx->dt = dt;
+    ctx->gen++;
+  }
   int64_t left = n_steps;
   while (left > 0) {
     const int k = (int)std::min<int64_t>(left, kChunk);
     HIPC(launch_schedule(ctx->p<double>(L.gtab), ctx->p<int64_t>(L.base), k, dt, ctx->sched, st));
-    if (!ctx->started) {
-      const int32_t rc = run_starter(ctx, dt, st);
-      if (rc != ENS_OK) return rc;
-      ctx->started = true;
-      ctx->dt = dt;
-    }
     for (int j = 0; j < k; ++j) {
       const int64_t n = ctx->steps + j;
       const bool energy = ctx->energy_every > 0 && (n % ctx->energy_every) == 0;
       a.j = j;
-      if (ctx->state_prec == ENS_STATE_F64) {
-        a.u_cur = ctx->p<double>(L.u[ctx->cur]);
-        a.u_prev = ctx->p<double>(L.u[1 - ctx->cur]);
-        a.u_next = ctx->p<double>(L.u[1 - ctx->cur]);
-      } else {
-        a.uh_cur = ctx->p<float>(L.uh[ctx->cur]);
-        a.uh_next = ctx->p<float>(L.uh[1 - ctx->cur]);
-        a.uc = ctx->state_prec == ENS_STATE_F32_KAHAN ? ctx->p<float>(L.uc) : nullptr;
-        a.v = ctx->p<float>(L.v);
-      }
+      set_state_ptrs(ctx, a, 0);
       HIPC(launch_step(a, f32, ctx->state_prec, ctx->SB, qoi, energy, use_shared(ctx), st));
       if (energy) {
         const int64_t rec = ctx->energy_records % kEnergyCap;
@@ -982,6 +999,7 @@ int32_t ens_save(ens_ctx* ctx, void* host, size_t* bytes) {
 
 int32_t ens_load(ens_ctx* ctx, const void* host, size_t bytes) {
   if (!ctx || !host) return ENS_EINVAL;
+  ctx->gen++;
   GUARD_BEGIN
   if (!ctx->bound) return ctx->fail(ENS_EWORKSPACE, "ens_load: bind a workspace first");
   if (bytes < sizeof(CkptHeader)) return ctx->fail(ENS_EINVAL, "ens_load: truncated checkpoint");
@@ -1030,6 +1048,7 @@ int32_t ens_load(ens_ctx* ctx, const void* host, size_t bytes) {
 
 int32_t ens_set_tuning(ens_ctx* ctx, int32_t sample_block, int32_t sb_inner) {
   if (!ctx) return ENS_EINVAL;
+  ctx->gen++;
   if (sample_block != 0 && sample_block != 8 && sample_block != 16 && sample_block != 32 && sample_block != 64 &&
       sample_block != 128 && sample_block != 256)
     return ctx->fail(ENS_EINVAL, "ens_set_tuning: sample block must be 0 (auto), 8, 16, 32, 64, 128 or 256");
@@ -1052,6 +1071,364 @@ int32_t ens_set_tuning(ens_ctx* ctx, int32_t sample_block, int32_t sb_inner) {
     }
   }
   return ENS_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batching: several contexts stepped by one persistent launch per step, the
+// step loop captured in a hipGraph, tiling chosen by a timing autotuner.
+// ---------------------------------------------------------------------------
+
+struct ens_batch {
+  std::vector<ens_ctx*> ctx;
+  int device = 0;
+  bool apply_f32 = false, qoi = true;
+  int mode = 0;
+  // tuning
+  int spl = 1, tile_nodes = 16, grid = 1024;
+  double tuned_ms = 0.0;
+  // device tables (small, owned)
+  BatchTile* d_tiles = nullptr;
+  int32_t n_tiles = 0;
+  size_t tiles_cap = 0;
+  StepArgs* d_desc = nullptr;
+  std::vector<int> desc_cur;
+  std::vector<uint64_t> desc_gen;
+  // captured chunk of graph_k steps
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_k = 64;
+  std::vector<uint64_t> graph_gen;
+  int graph_sig[3] = {0, 0, 0};
+  hipStream_t st = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  std::string err;
+  int32_t fail(int32_t code, const std::string& m) {
+    err = m;
+    return code;
+  }
+};
+
+namespace {
+
+#define BHIPC(expr)                                                                              \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess)                                                                        \
+      return b->fail(ENS_EDEVICE, std::string("HIP error: ") + hipGetErrorString(e_) + " at " #expr); \
+  } while (0)
+
+void drop_graph(ens_batch* b) {
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+// Tiles of `tile_nodes` consecutive nodes times one sample block of 64*spl
+// samples, meshes interleaved so the persistent workgroups see a mix.
+int32_t build_tiles(ens_batch* b) {
+  std::vector<std::vector<BatchTile>> per(b->ctx.size());
+  size_t total = 0;
+  const int sbw = 64 * b->spl;
+  for (size_t m = 0; m < b->ctx.size(); ++m) {
+    const ens_ctx* c = b->ctx[m];
+    const int nsb = c->ld / sbw;
+    for (int sb = 0; sb < nsb; ++sb)
+      for (int64_t n0 = 0; n0 < c->n_nodes; n0 += b->tile_nodes)
+        per[m].push_back(BatchTile{(int32_t)m, (int32_t)n0,
+                                   (int32_t)std::min<int64_t>(b->tile_nodes, c->n_nodes - n0), sb});
+    total += per[m].size();
+  }
+  std::vector<BatchTile> tiles;
+  tiles.reserve(total);
+  // proportional interleave: take from each mesh in order of its progress
+  std::vector<size_t> at(per.size(), 0);
+  while (tiles.size() < total) {
+    size_t best = 0;
+    double best_f = 2.0;
+    for (size_t m = 0; m < per.size(); ++m) {
+      if (at[m] >= per[m].size()) continue;
+      const double f = (double)at[m] / (double)per[m].size();
+      if (f < best_f) { best_f = f; best = m; }
+    }
+    tiles.push_back(per[best][at[best]++]);
+  }
+  if (tiles.size() > b->tiles_cap) {
+    if (b->d_tiles) BHIPC(hipFree(b->d_tiles));
+    b->d_tiles = nullptr;
+    BHIPC(hipMalloc(&b->d_tiles, sizeof(BatchTile) * tiles.size()));
+    b->tiles_cap = tiles.size();
+  }
+  BHIPC(hipMemcpy(b->d_tiles, tiles.data(), sizeof(BatchTile) * tiles.size(), hipMemcpyHostToDevice));
+  b->n_tiles = (int32_t)tiles.size();
+  drop_graph(b);
+  return ENS_OK;
+}
+
+// Per-mesh step arguments for both parities, relative to each context's
+// current buffer.
+int32_t build_desc(ens_batch* b) {
+  std::vector<StepArgs> d(2 * b->ctx.size());
+  for (size_t m = 0; m < b->ctx.size(); ++m) {
+    ens_ctx* c = b->ctx[m];
+    for (int par = 0; par < 2; ++par) {
+      StepArgs a = base_args(c, b->apply_f32);
+      a.dt = c->dt;
+      a.a = 0.5 * c->alpha * c->dt;
+      set_state_ptrs(c, a, par);
+      d[2 * m + par] = a;
+    }
+    b->desc_cur[m] = c->cur;
+    b->desc_gen[m] = c->gen;
+  }
+  BHIPC(hipMemcpyAsync(b->d_desc, d.data(), sizeof(StepArgs) * d.size(), hipMemcpyHostToDevice, b->st));
+  BHIPC(hipStreamSynchronize(b->st));
+  return ENS_OK;
+}
+
+int32_t check_ready(ens_batch* b) {
+  for (size_t m = 0; m < b->ctx.size(); ++m) {
+    const ens_ctx* c = b->ctx[m];
+    if (!c->bound || !c->state_init || !c->started || !c->have_load)
+      return b->fail(ENS_ESTATE, "batch mesh " + std::to_string(m) +
+                                     ": bind, init the state and fix dt (ens_step with 0 steps) first");
+  }
+  return ENS_OK;
+}
+
+// Enqueue k steps of every mesh on b->st: per chunk of at most kChunk steps
+// the load-factor tables, one launch per step, then the step counters.
+// kChunk is even, so step j of a chunk has the parity of j.
+static_assert(kChunk % 2 == 0, "chunks must keep the state parity");
+int32_t enqueue_steps(ens_batch* b, int64_t k_total) {
+  for (int64_t done = 0; done < k_total;) {
+    const int k = (int)std::min<int64_t>(k_total - done, kChunk);
+    for (ens_ctx* c : b->ctx)
+      BHIPC(launch_schedule(c->p<double>(c->L.gtab), c->p<int64_t>(c->L.base), k, c->dt, c->sched, b->st));
+    for (int j = 0; j < k; ++j)
+      BHIPC(launch_batch_step(b->d_tiles, b->n_tiles, b->d_desc, j, b->apply_f32, b->mode, b->spl, b->qoi,
+                              b->grid, b->st));
+    for (ens_ctx* c : b->ctx) BHIPC(launch_advance(c->p<int64_t>(c->L.base), k, b->st));
+    done += k;
+  }
+  return ENS_OK;
+}
+
+void after_steps(ens_batch* b, int64_t n) {
+  for (ens_ctx* c : b->ctx) {
+    c->steps += n;
+    if (n & 1) c->cur ^= 1;
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t ens_batch_create(ens_ctx** ctxs, int32_t n, ens_batch** out) {
+  if (!ctxs || n < 1 || !out) return ENS_EINVAL;
+  *out = nullptr;
+  ens_batch* b = new (std::nothrow) ens_batch();
+  if (!b) return ENS_EINVAL;
+  b->ctx.assign(ctxs, ctxs + n);
+  const ens_ctx* c0 = ctxs[0];
+  bool all128 = true;
+  for (int i = 0; i < n; ++i) {
+    const ens_ctx* c = ctxs[i];
+    std::string why;
+    if (!c) why = "null context";
+    else if (!c->bound) why = "workspace not bound";
+    else if (c->device != c0->device) why = "contexts on different devices";
+    else if (c->apply_prec != c0->apply_prec || c->state_prec != c0->state_prec)
+      why = "all meshes need the same apply and state precision";
+    else if ((c->qoi_mask != 0) != (c0->qoi_mask != 0)) why = "all meshes need the same QoI setting";
+    else if (c->energy_every != 0) why = "energy records are not available in batched stepping";
+    else if (use_shared(c)) why = "batched stepping uses the element-by-element variant only";
+    else if (c->ld % 64 != 0) why = "padded width must be a multiple of 64 (ens_set_tuning(ctx, 64, 0) before binding)";
+    for (int j = 0; j < i && why.empty(); ++j)
+      if (ctxs[j] == c) why = "context listed twice";
+    if (!why.empty()) {
+      delete b;
+      if (c) const_cast<ens_ctx*>(c)->err = "ens_batch_create: mesh " + std::to_string(i) + ": " + why;
+      return ENS_EINVAL;
+    }
+    if (c->ld % 128 != 0) all128 = false;
+  }
+  b->device = c0->device;
+  b->apply_f32 = c0->apply_prec == ENS_F32;
+  b->mode = c0->state_prec;
+  b->qoi = c0->qoi_mask != 0;
+  b->spl = all128 ? 2 : 1;
+  b->desc_cur.assign(n, -1);
+  b->desc_gen.assign(n, ~0ull);
+  int cus = 256;
+  hipDeviceProp_t prop;
+  if (hipSetDevice(b->device) != hipSuccess || hipGetDeviceProperties(&prop, b->device) != hipSuccess ||
+      hipStreamCreate(&b->st) != hipSuccess || hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess ||
+      hipMalloc(&b->d_desc, sizeof(StepArgs) * 2 * n) != hipSuccess) {
+    delete b;
+    return ENS_EDEVICE;
+  }
+  cus = prop.multiProcessorCount;
+  b->grid = 4 * cus;
+  if (build_tiles(b) != ENS_OK) {
+    delete b;
+    return ENS_EDEVICE;
+  }
+  *out = b;
+  return ENS_OK;
+}
+
+int32_t ens_batch_destroy(ens_batch* b) {
+  if (!b) return ENS_EINVAL;
+  hipSetDevice(b->device);
+  hipDeviceSynchronize();
+  drop_graph(b);
+  if (b->d_tiles) hipFree(b->d_tiles);
+  if (b->d_desc) hipFree(b->d_desc);
+  if (b->ev_in) hipEventDestroy(b->ev_in);
+  if (b->ev_out) hipEventDestroy(b->ev_out);
+  if (b->st) hipStreamDestroy(b->st);
+  delete b;
+  return ENS_OK;
+}
+
+const char* ens_batch_last_error(const ens_batch* b) { return b ? b->err.c_str() : "null batch"; }
+
+int32_t ens_batch_info(ens_batch* b, ens_batch_info_t* out) {
+  if (!b || !out) return ENS_EINVAL;
+  out->n_meshes = (int32_t)b->ctx.size();
+  out->n_tiles = b->n_tiles;
+  out->samples_per_lane = b->spl;
+  out->tile_nodes = b->tile_nodes;
+  out->grid = b->grid;
+  out->graph_steps = b->graph_k;
+  out->tuned_ms_per_step = b->tuned_ms;
+  return ENS_OK;
+}
+
+int32_t ens_batch_step(ens_batch* b, int64_t n_steps, void* stream) {
+  if (!b) return ENS_EINVAL;
+  try {
+    if (n_steps < 0) return b->fail(ENS_EINVAL, "ens_batch_step: n_steps must be >= 0");
+    int32_t rc = check_ready(b);
+    if (rc != ENS_OK) return rc;
+    BHIPC(hipSetDevice(b->device));
+    hipStream_t user = static_cast<hipStream_t>(stream);
+    BHIPC(hipEventRecord(b->ev_in, user));
+    BHIPC(hipStreamWaitEvent(b->st, b->ev_in, 0));
+    bool stale = false;
+    for (size_t m = 0; m < b->ctx.size(); ++m)
+      if (b->desc_cur[m] != b->ctx[m]->cur || b->desc_gen[m] != b->ctx[m]->gen) stale = true;
+    if (stale) {
+      rc = build_desc(b);
+      if (rc != ENS_OK) return rc;
+    }
+    std::vector<uint64_t> gen(b->ctx.size());
+    for (size_t m = 0; m < b->ctx.size(); ++m) gen[m] = b->ctx[m]->gen;
+    const int sig[3] = {b->spl, b->tile_nodes, b->grid};
+    if (b->exec && (gen != b->graph_gen || std::memcmp(sig, b->graph_sig, sizeof sig) != 0)) drop_graph(b);
+    int64_t left = n_steps;
+    if (left >= b->graph_k) {
+      if (!b->exec) {
+        BHIPC(hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal));
+        rc = enqueue_steps(b, b->graph_k);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->st, &g);
+        if (rc != ENS_OK) return rc;
+        if (e != hipSuccess) return b->fail(ENS_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e));
+        b->graph = g;
+        BHIPC(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+        b->graph_gen = gen;
+        std::memcpy(b->graph_sig, sig, sizeof sig);
+      }
+      while (left >= b->graph_k) {  // graph_k is even: parities are unchanged per replay
+        BHIPC(hipGraphLaunch(b->exec, b->st));
+        after_steps(b, b->graph_k);
+        left -= b->graph_k;
+      }
+    }
+    if (left > 0) {
+      rc = enqueue_steps(b, (int)left);
+      if (rc != ENS_OK) return rc;
+      after_steps(b, left);
+    }
+    BHIPC(hipEventRecord(b->ev_out, b->st));
+    BHIPC(hipStreamWaitEvent(user, b->ev_out, 0));
+    for (ens_ctx* c : b->ctx) c->last_stream = user;
+    return ENS_OK;
+  } catch (...) {
+    return b->fail(ENS_EINVAL, "ens_batch_step: host failure");
+  }
+}
+
+int32_t ens_batch_autotune(ens_batch* b, int32_t trial_steps) {
+  if (!b) return ENS_EINVAL;
+  try {
+    if (trial_steps < 1) return b->fail(ENS_EINVAL, "ens_batch_autotune: trial_steps must be >= 1");
+    int32_t rc = check_ready(b);
+    if (rc != ENS_OK) return rc;
+    BHIPC(hipSetDevice(b->device));
+    hipDeviceProp_t prop;
+    BHIPC(hipGetDeviceProperties(&prop, b->device));
+    const int cus = prop.multiProcessorCount;
+    bool all128 = true;
+    for (const ens_ctx* c : b->ctx)
+      if (c->ld % 128 != 0) all128 = false;
+    hipEvent_t e0, e1;
+    BHIPC(hipEventCreate(&e0));
+    BHIPC(hipEventCreate(&e1));
+    double best = 1e300;
+    int bs = b->spl, bt = b->tile_nodes, bg = b->grid;
+    for (int spl : {1, 2}) {
+      if (spl == 2 && !all128) continue;
+      for (int tn : {4, 16, 64}) {
+        for (int gm : {2, 4, 8}) {
+          b->spl = spl;
+          b->tile_nodes = tn;
+          b->grid = gm * cus;
+          rc = build_tiles(b);
+          if (rc == ENS_OK) rc = build_desc(b);
+          if (rc != ENS_OK) break;
+          rc = enqueue_steps(b, 2);  // warm-up, even: parities unchanged
+          if (rc != ENS_OK) break;
+          after_steps(b, 2);
+          BHIPC(hipEventRecord(e0, b->st));
+          rc = enqueue_steps(b, trial_steps);
+          if (rc != ENS_OK) break;
+          BHIPC(hipEventRecord(e1, b->st));
+          BHIPC(hipEventSynchronize(e1));
+          after_steps(b, trial_steps);
+          float ms = 0.f;
+          BHIPC(hipEventElapsedTime(&ms, e0, e1));
+          if (ms / trial_steps < best) {
+            best = ms / trial_steps;
+            bs = spl;
+            bt = tn;
+            bg = gm * cus;
+          }
+          if (trial_steps & 1) build_desc(b);
+        }
+        if (rc != ENS_OK) break;
+      }
+      if (rc != ENS_OK) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc != ENS_OK) return rc;
+    b->spl = bs;
+    b->tile_nodes = bt;
+    b->grid = bg;
+    b->tuned_ms = best;
+    rc = build_tiles(b);
+    if (rc != ENS_OK) return rc;
+    return build_desc(b);
+  } catch (...) {
+    return b->fail(ENS_EINVAL, "ens_batch_autotune: host failure");
+  }
 }
 
 }  // extern "C"

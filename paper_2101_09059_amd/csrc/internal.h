@@ -70,14 +70,22 @@ struct StepArgs {
   double* q;           // running peak radial displacement [n_nodes][ld]
   // At-max bits (wave-per-node kernels): bit set <=> the running peak equals
   // the current radial displacement, which is then not stored in q.
-  // Per node ld/64 words; word sb*SPL + i, bit = lane of sample
-  // sb*SB + lane*SPL + i.
+  // Per node ceil(ld/64) words; sample s in word s/64, bit s%64.
   uint64_t* qmask;
   int32_t qwords;
   const double* gtab;  // load factors of the current chunk
   int32_t j;           // index into gtab
   double dt, a;        // step, alpha dt / 2
   double* energy_part; // [n_nb][ld] per node-block energy partial sums
+};
+
+// One work item of the batched step: `count` nodes from `node0` of mesh
+// `mesh`, sample block `sblock` (64 lanes x SPL samples).
+struct BatchTile {
+  int32_t mesh;
+  int32_t node0;
+  int32_t count;
+  int32_t sblock;
 };
 
 // ---- set-up kernels (setup.hip) -------------------------------------------
@@ -120,6 +128,8 @@ hipError_t launch_starter_f32(int32_t n_nodes, int32_t ld, const float* R, const
 hipError_t launch_split_f32(int64_t n, const double* u0, float* uh, float* uc, hipStream_t st);
 hipError_t launch_qoi_init(int32_t n_nodes, int32_t ld, const double* radial, const double* u_f64,
                            const float* uh, const float* uc, double* q, hipStream_t st);
+hipError_t launch_batch_step(const BatchTile* tiles, int32_t n_tiles, const StepArgs* desc, int32_t j,
+                             bool apply_f32, int mode, int spl, bool qoi, int grid, hipStream_t st);
 hipError_t launch_qoi_resolve(int32_t n_nodes, int32_t ld, int sample_block, const double* radial,
                               const double* u_f64, const float* uh, const float* uc, double* q,
                               const uint64_t* qmask, hipStream_t st);

@@ -176,12 +176,204 @@ __device__ __forceinline__ void gather_blocks(const StepArgs& p, int node, int64
   }
 }
 
+// At-max bits use a sample-indexed layout, independent of the lane mapping:
+// per node ld/64 words, sample s in word s/64, bit s%64.  With SPL samples
+// per lane, lane l holds samples SPL*l + i of its block: word
+// (SPL*l + i)/64, bit SPL*(l % (64/SPL)) + i.
+template <int SPL>
+__device__ __forceinline__ uint64_t spread_bits(uint64_t x) {
+  if constexpr (SPL == 1) {
+    return x;
+  } else if constexpr (SPL == 2) {  // bit k of a 32-bit value -> bit 2k
+    x &= 0xffffffffull;
+    x = (x | (x << 16)) & 0x0000ffff0000ffffull;
+    x = (x | (x << 8)) & 0x00ff00ff00ff00ffull;
+    x = (x | (x << 4)) & 0x0f0f0f0f0f0f0f0full;
+    x = (x | (x << 2)) & 0x3333333333333333ull;
+    x = (x | (x << 1)) & 0x5555555555555555ull;
+    return x;
+  } else {  // SPL == 4: bit k of a 16-bit value -> bit 4k
+    x &= 0xffffull;
+    x = (x | (x << 24)) & 0x000000ff000000ffull;
+    x = (x | (x << 12)) & 0x000f000f000f000full;
+    x = (x | (x << 6)) & 0x0303030303030303ull;
+    x = (x | (x << 3)) & 0x1111111111111111ull;
+    return x;
+  }
+}
+
+// Work of one wave-or-lane-group on one node and SPL samples per lane:
+// stiffness apply, central-difference update, QoI and energy terms.
+// `lane` in [0, LPN); samples sbk*LPN*SPL + lane*SPL + i.
+template <typename AT, int MODE, int LPN, int SPL, bool QOI, bool ENERGY, bool SHARED>
+__device__ __forceinline__ void step_node(const StepArgs& p, int node, int sbk, int lane,
+                                          double (&e_loc)[SPL]) {
+  constexpr int SB = LPN * SPL;
+  const int s0 = sbk * SB + lane * SPL;
+  const int64_t ld = p.ld;
+  using ST = typename std::conditional<MODE == kStateF64, double, float>::type;
+  const ST* __restrict__ U = nullptr;
+  if constexpr (MODE == kStateF64) U = p.u_cur; else U = p.uh_cur;
+  const int64_t row = (int64_t)node * 3;
+  ST ua[3][SPL];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (row + c) * ld + s0, ua[c]);
+  AT r[3][SPL];
+  if constexpr (SHARED) gather_blocks<AT, ST, SPL>(p, node, ld, s0, U, ua, r);
+  else gather_apply<AT, ST, SPL>(p, node, ld, s0, U, ua, r);
+
+  const double g = p.gtab[p.j];
+  const unsigned fx = p.fixed[node];
+  const int64_t ms = (int64_t)node * ld + s0;
+  double un[3][SPL];
+  double uo[3][SPL];  // u_n as the QoI sees it
+  if constexpr (MODE == kStateF64) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int i = 0; i < SPL; ++i) uo[c][i] = ua[c][i];
+    double minv[SPL];
+    if constexpr (std::is_same<AT, double>::value) {
+      vload<SPL, true>(static_cast<const double*>(p.minv) + ms, minv);
+    } else {
+      float mf[SPL];
+      vload<SPL, true>(static_cast<const float*>(p.minv) + ms, mf);
+#pragma unroll
+      for (int i = 0; i < SPL; ++i) minv[i] = (double)mf[i];
+    }
+    const double dt2 = p.dt * p.dt;
+    const double inv1pa = 1.0 / (1.0 + p.a);
+    const double oma = 1.0 - p.a;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t idx = (row + c) * ld + s0;
+      double up[SPL];
+      vload<SPL, true>(p.u_prev + idx, up);
+      const double fc = g * p.F[row + c];
+#pragma unroll
+      for (int i = 0; i < SPL; ++i) {
+        const double acc = (dt2 * minv[i]) * (fc - (double)r[c][i]);
+        double v = fma(-oma, up[i], fma(2.0, ua[c][i], acc)) * inv1pa;
+        if (fx & (1u << c)) v = 0.0;
+        un[c][i] = v;
+      }
+      vstore<SPL, true>(p.u_next + idx, un[c]);
+    }
+    if constexpr (ENERGY) {
+#pragma unroll
+      for (int i = 0; i < SPL; ++i) {
+        const double m = 1.0 / minv[i];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const double vel = (un[c][i] - ua[c][i]) / p.dt;
+          e_loc[i] += 0.5 * m * vel * vel + 0.5 * un[c][i] * (double)r[c][i];
+        }
+      }
+    }
+  } else {
+    float minv[SPL];
+    vload<SPL, true>(static_cast<const float*>(p.minv) + ms, minv);
+    const float dtf = (float)p.dt;
+    const float inv1pa = (float)(1.0 / (1.0 + p.a));
+    const float oma = (float)(1.0 - p.a);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const int64_t idx = (row + c) * ld + s0;
+      const float fc = (float)(g * p.F[row + c]);
+      float vel[SPL], cc[SPL], uh[SPL];
+      vload<SPL, true>(p.v + idx, vel);
+      if constexpr (MODE == kStateF32Kahan) vload<SPL, true>(p.uc + idx, cc);
+#pragma unroll
+      for (int i = 0; i < SPL; ++i) {
+        if constexpr (MODE == kStateF32Kahan) uo[c][i] = (double)ua[c][i] - (double)cc[i];
+        else uo[c][i] = (double)ua[c][i];
+        const float acc = minv[i] * (fc - (float)r[c][i]);
+        vel[i] = fmaf(dtf, acc, oma * vel[i]) * inv1pa;
+        uh[i] = ua[c][i];
+        if constexpr (MODE == kStateF32Kahan) {
+          const float y = fmaf(dtf, vel[i], -cc[i]);
+          const float t = uh[i] + y;
+          cc[i] = (t - uh[i]) - y;
+          uh[i] = t;
+        } else {
+          cc[i] = 0.0f;
+          uh[i] = fmaf(dtf, vel[i], uh[i]);
+        }
+        if (fx & (1u << c)) {
+          uh[i] = 0.0f;
+          cc[i] = 0.0f;
+          vel[i] = 0.0f;
+        }
+        un[c][i] = (double)uh[i] - (double)cc[i];
+        if constexpr (ENERGY) {
+          e_loc[i] += 0.5 / (double)minv[i] * (double)vel[i] * (double)vel[i] +
+                      0.5 * un[c][i] * (double)r[c][i];
+        }
+      }
+      vstore<SPL, true>(p.uh_next + idx, uh);
+      if constexpr (MODE == kStateF32Kahan) vstore<SPL, true>(p.uc + idx, cc);
+      vstore<SPL, true>(p.v + idx, vel);
+    }
+  }
+  if constexpr (QOI) {
+    const double e0 = p.radial[row + 0], e1 = p.radial[row + 1], e2 = p.radial[row + 2];
+    if constexpr (LPN == 64) {
+      // q is only touched where the radial displacement turns: a rise that
+      // continues from the running peak keeps the at-max bit, a fall from it
+      // writes the peak, a rise below it compares with the stored peak.
+      constexpr int LPW = 64 / SPL;  // lanes per mask word
+      uint64_t* __restrict__ mw = p.qmask + (int64_t)node * p.qwords + sbk * SPL;
+      uint64_t words[SPL];
+#pragma unroll
+      for (int w = 0; w < SPL; ++w) words[w] = mw[w];
+      uint64_t mine = words[0];
+#pragma unroll
+      for (int w = 1; w < SPL; ++w)
+        if (lane / LPW == w) mine = words[w];
+      uint64_t ballots[SPL];
+#pragma unroll
+      for (int i = 0; i < SPL; ++i) {
+        const bool at = (mine >> (SPL * (lane % LPW) + i)) & 1ull;
+        const double rc = fma(e2, uo[2][i], fma(e1, uo[1][i], e0 * uo[0][i]));
+        const double rn = fma(e2, un[2][i], fma(e1, un[1][i], e0 * un[0][i]));
+        bool nbit = false;
+        if (at) {
+          nbit = rn >= rc;
+          if (!nbit) __builtin_nontemporal_store(rc, p.q + ms + i);
+        } else if (rn > rc) {
+          nbit = rn > __builtin_nontemporal_load(p.q + ms + i);
+        }
+        ballots[i] = __ballot(nbit);
+      }
+#pragma unroll
+      for (int w = 0; w < SPL; ++w) {
+        uint64_t nw = 0;
+#pragma unroll
+        for (int i = 0; i < SPL; ++i) nw |= spread_bits<SPL>(ballots[i] >> (w * LPW)) << i;
+        if (nw != words[w] && lane == 0) mw[w] = nw;
+      }
+    } else {
+      double qo[SPL];
+      vload<SPL, true>(p.q + ms, qo);
+      bool upd = false;
+#pragma unroll
+      for (int i = 0; i < SPL; ++i) {
+        const double qv = fma(e2, un[2][i], fma(e1, un[1][i], e0 * un[0][i]));
+        if (qv > qo[i]) {
+          qo[i] = qv;
+          upd = true;
+        }
+      }
+      if (upd) vstore<SPL, true>(p.q + ms, qo);
+    }
+  }
+}
+
 // LPN lanes per node, SPL consecutive samples per lane: a workgroup covers
 // kBlock/LPN nodes times LPN*SPL samples.  With LPN = 64 a wave owns one
 // node, so adjacency and stiffness blocks are wave-uniform (scalar loads).
 template <typename AT, int MODE, int LPN, int SPL, bool QOI, bool ENERGY, bool SHARED>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
-  constexpr int SB = LPN * SPL;
   constexpr int NPB = kBlock / LPN;
   int nb, sbk;
   if (!wg_coords(p, nb, sbk)) return;  // uniform over the workgroup
@@ -189,168 +381,48 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
   const int lane = threadIdx.x % LPN;
   int node = nb * NPB + ln;
   if (LPN >= 64) node = __builtin_amdgcn_readfirstlane(node);
-  const int s0 = sbk * SB + lane * SPL;
-  const int64_t ld = p.ld;
-  const bool active = node < p.n_nodes;
   double e_loc[SPL];
 #pragma unroll
   for (int i = 0; i < SPL; ++i) e_loc[i] = 0.0;
-  if (active) {
-    using ST = typename std::conditional<MODE == kStateF64, double, float>::type;
-    const ST* __restrict__ U = nullptr;
-    if constexpr (MODE == kStateF64) U = p.u_cur; else U = p.uh_cur;
-    const int64_t row = (int64_t)node * 3;
-    ST ua[3][SPL];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (row + c) * ld + s0, ua[c]);
-    AT r[3][SPL];
-    if constexpr (SHARED) gather_blocks<AT, ST, SPL>(p, node, ld, s0, U, ua, r);
-    else gather_apply<AT, ST, SPL>(p, node, ld, s0, U, ua, r);
-
-    const double g = p.gtab[p.j];
-    const unsigned fx = p.fixed[node];
-    const int64_t ms = (int64_t)node * ld + s0;
-    double un[3][SPL];
-    double uo[3][SPL];  // u_n as the QoI sees it
-    if constexpr (MODE == kStateF64) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int i = 0; i < SPL; ++i) uo[c][i] = ua[c][i];
-      double minv[SPL];
-      if constexpr (std::is_same<AT, double>::value) {
-        vload<SPL, true>(static_cast<const double*>(p.minv) + ms, minv);
-      } else {
-        float mf[SPL];
-        vload<SPL, true>(static_cast<const float*>(p.minv) + ms, mf);
-#pragma unroll
-        for (int i = 0; i < SPL; ++i) minv[i] = (double)mf[i];
-      }
-      const double dt2 = p.dt * p.dt;
-      const double inv1pa = 1.0 / (1.0 + p.a);
-      const double oma = 1.0 - p.a;
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int64_t idx = (row + c) * ld + s0;
-        double up[SPL];
-        vload<SPL, true>(p.u_prev + idx, up);
-        const double fc = g * p.F[row + c];
-#pragma unroll
-        for (int i = 0; i < SPL; ++i) {
-          const double acc = (dt2 * minv[i]) * (fc - (double)r[c][i]);
-          double v = fma(-oma, up[i], fma(2.0, ua[c][i], acc)) * inv1pa;
-          if (fx & (1u << c)) v = 0.0;
-          un[c][i] = v;
-        }
-        vstore<SPL, true>(p.u_next + idx, un[c]);
-      }
-      if constexpr (ENERGY) {
-#pragma unroll
-        for (int i = 0; i < SPL; ++i) {
-          const double m = 1.0 / minv[i];
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            const double vel = (un[c][i] - ua[c][i]) / p.dt;
-            e_loc[i] += 0.5 * m * vel * vel + 0.5 * un[c][i] * (double)r[c][i];
-          }
-        }
-      }
-    } else {
-      float minv[SPL];
-      vload<SPL, true>(static_cast<const float*>(p.minv) + ms, minv);
-      const float dtf = (float)p.dt;
-      const float inv1pa = (float)(1.0 / (1.0 + p.a));
-      const float oma = (float)(1.0 - p.a);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const int64_t idx = (row + c) * ld + s0;
-        const float fc = (float)(g * p.F[row + c]);
-        float vel[SPL], cc[SPL], uh[SPL];
-        vload<SPL, true>(p.v + idx, vel);
-        if constexpr (MODE == kStateF32Kahan) vload<SPL, true>(p.uc + idx, cc);
-#pragma unroll
-        for (int i = 0; i < SPL; ++i) {
-          if constexpr (MODE == kStateF32Kahan) uo[c][i] = (double)ua[c][i] - (double)cc[i];
-          else uo[c][i] = (double)ua[c][i];
-          const float acc = minv[i] * (fc - (float)r[c][i]);
-          vel[i] = fmaf(dtf, acc, oma * vel[i]) * inv1pa;
-          uh[i] = ua[c][i];
-          if constexpr (MODE == kStateF32Kahan) {
-            const float y = fmaf(dtf, vel[i], -cc[i]);
-            const float t = uh[i] + y;
-            cc[i] = (t - uh[i]) - y;
-            uh[i] = t;
-          } else {
-            cc[i] = 0.0f;
-            uh[i] = fmaf(dtf, vel[i], uh[i]);
-          }
-          if (fx & (1u << c)) {
-            uh[i] = 0.0f;
-            cc[i] = 0.0f;
-            vel[i] = 0.0f;
-          }
-          un[c][i] = (double)uh[i] - (double)cc[i];
-          if constexpr (ENERGY) {
-            e_loc[i] += 0.5 / (double)minv[i] * (double)vel[i] * (double)vel[i] +
-                        0.5 * un[c][i] * (double)r[c][i];
-          }
-        }
-        vstore<SPL, true>(p.uh_next + idx, uh);
-        if constexpr (MODE == kStateF32Kahan) vstore<SPL, true>(p.uc + idx, cc);
-        vstore<SPL, true>(p.v + idx, vel);
-      }
-    }
-    if constexpr (QOI) {
-      const double e0 = p.radial[row + 0], e1 = p.radial[row + 1], e2 = p.radial[row + 2];
-      if constexpr (LPN == 64) {
-        // q is only touched when the radial displacement turns: a rise that
-        // continues from the running peak keeps the at-max bit, a fall from
-        // it writes the peak, a rise below it compares with the stored peak.
-        uint64_t* __restrict__ mw = p.qmask + (int64_t)node * p.qwords + sbk * SPL;
-#pragma unroll
-        for (int i = 0; i < SPL; ++i) {
-          const uint64_t word = mw[i];
-          const bool at = (word >> lane) & 1ull;
-          const double rc = fma(e2, uo[2][i], fma(e1, uo[1][i], e0 * uo[0][i]));
-          const double rn = fma(e2, un[2][i], fma(e1, un[1][i], e0 * un[0][i]));
-          bool nbit = false;
-          if (at) {
-            nbit = rn >= rc;
-            if (!nbit) __builtin_nontemporal_store(rc, p.q + ms + i);
-          } else if (rn > rc) {
-            nbit = rn > __builtin_nontemporal_load(p.q + ms + i);
-          }
-          const uint64_t nword = __ballot(nbit);
-          if (nword != word && lane == 0) mw[i] = nword;
-        }
-      } else {
-        double qo[SPL];
-        vload<SPL, true>(p.q + ms, qo);
-        bool upd = false;
-#pragma unroll
-        for (int i = 0; i < SPL; ++i) {
-          const double qv = fma(e2, un[2][i], fma(e1, un[1][i], e0 * un[0][i]));
-          if (qv > qo[i]) {
-            qo[i] = qv;
-            upd = true;
-          }
-        }
-        if (upd) vstore<SPL, true>(p.q + ms, qo);
-      }
-    }
-  }
+  if (node < p.n_nodes) step_node<AT, MODE, LPN, SPL, QOI, ENERGY, SHARED>(p, node, sbk, lane, e_loc);
   if constexpr (ENERGY) {
     __shared__ double red[kBlock * SPL];
 #pragma unroll
     for (int i = 0; i < SPL; ++i) red[threadIdx.x * SPL + i] = e_loc[i];
     __syncthreads();
     if (ln == 0) {
+      const int s0 = sbk * LPN * SPL + lane * SPL;
 #pragma unroll
       for (int i = 0; i < SPL; ++i) {
         double sum = 0.0;
         for (int n = 0; n < NPB; ++n) sum += red[(n * LPN + lane) * SPL + i];
-        p.energy_part[(int64_t)nb * ld + s0 + i] = sum;
+        p.energy_part[(int64_t)nb * p.ld + s0 + i] = sum;
       }
+    }
+  }
+}
+
+// Batched step: one launch steps every mesh of a batch.  Persistent
+// workgroups walk a static list of tiles (mesh, first node, node count,
+// sample block); each wave takes every 4th node of the tile with 64 lanes x
+// SPL samples.  Per-mesh arguments come from a device table indexed by the
+// mesh and by the parity of the step (which state buffer is current).
+template <typename AT, int MODE, int SPL, bool QOI>
+__global__ __launch_bounds__(kBlock) void k_batch_step(const BatchTile* __restrict__ tiles,
+                                                       int32_t n_tiles,
+                                                       const StepArgs* __restrict__ desc,
+                                                       int32_t j) {
+  const int wave = threadIdx.x / 64;
+  const int lane = threadIdx.x % 64;
+  double e_loc[SPL];
+  for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+    const BatchTile tile = tiles[t];
+    const StepArgs& p0 = desc[2 * tile.mesh + (j & 1)];
+    StepArgs p = p0;
+    p.j = j;
+    for (int n = wave; n < tile.count; n += kBlock / 64) {
+      const int node = __builtin_amdgcn_readfirstlane(tile.node0 + n);
+      step_node<AT, MODE, 64, SPL, QOI, false, false>(p, node, tile.sblock, lane, e_loc);
     }
   }
 }
@@ -498,7 +570,7 @@ __global__ __launch_bounds__(256) void k_qoi_init(int32_t n_nodes, int32_t ld,
 
 // Fold the at-max bits into q: where a bit is set, store the current radial
 // displacement (same operation order as the step kernel).  Idempotent.
-__global__ __launch_bounds__(256) void k_qoi_resolve(int32_t n_nodes, int32_t ld, int SB, int SPL,
+__global__ __launch_bounds__(256) void k_qoi_resolve(int32_t n_nodes, int32_t ld,
                                                      const double* __restrict__ radial,
                                                      const double* __restrict__ u,
                                                      const float* __restrict__ uh,
@@ -509,10 +581,9 @@ __global__ __launch_bounds__(256) void k_qoi_resolve(int32_t n_nodes, int32_t ld
   if (t >= (int64_t)n_nodes * ld) return;
   const int64_t node = t / ld;
   const int s = (int)(t % ld);
-  const int sb = s / SB, within = s % SB, lane = within / SPL, i = within % SPL;
-  const int qwords = ld / 64;
-  const uint64_t word = qmask[node * qwords + sb * SPL + i];
-  if (!((word >> lane) & 1ull)) return;
+  const int qwords = (ld + 63) / 64;
+  const uint64_t word = qmask[node * qwords + s / 64];
+  if (!((word >> (s % 64)) & 1ull)) return;
   double x[3];
   for (int c = 0; c < 3; ++c) {
     const int64_t idx = (node * 3 + c) * ld + s;
@@ -649,6 +720,35 @@ hipError_t launch_apply(const StepArgs& a, bool f32, int sample_block, bool shar
              : dispatch_apply<double, false>(a, sample_block, U, R, st);
 }
 
+hipError_t launch_batch_step(const BatchTile* tiles, int32_t n_tiles, const StepArgs* desc, int32_t j,
+                             bool apply_f32, int mode, int spl, bool qoi, int grid, hipStream_t st) {
+  if (n_tiles == 0) return hipSuccess;
+#define ENSFEM_BATCH(AT, MODE, SPL)                                                                    \
+  do {                                                                                                 \
+    if (qoi) k_batch_step<AT, MODE, SPL, true><<<grid, kBlock, 0, st>>>(tiles, n_tiles, desc, j);      \
+    else k_batch_step<AT, MODE, SPL, false><<<grid, kBlock, 0, st>>>(tiles, n_tiles, desc, j);         \
+    return hipGetLastError();                                                                          \
+  } while (0)
+  if (!apply_f32) {
+    if (mode != kStateF64) return hipErrorInvalidValue;
+    if (spl == 1) ENSFEM_BATCH(double, kStateF64, 1);
+    if (spl == 2) ENSFEM_BATCH(double, kStateF64, 2);
+    return hipErrorInvalidValue;
+  }
+  if (mode == kStateF64) {
+    if (spl == 1) ENSFEM_BATCH(float, kStateF64, 1);
+    if (spl == 2) ENSFEM_BATCH(float, kStateF64, 2);
+  } else if (mode == kStateF32Kahan) {
+    if (spl == 1) ENSFEM_BATCH(float, kStateF32Kahan, 1);
+    if (spl == 2) ENSFEM_BATCH(float, kStateF32Kahan, 2);
+  } else if (mode == kStateF32) {
+    if (spl == 1) ENSFEM_BATCH(float, kStateF32, 1);
+    if (spl == 2) ENSFEM_BATCH(float, kStateF32, 2);
+  }
+#undef ENSFEM_BATCH
+  return hipErrorInvalidValue;
+}
+
 hipError_t launch_schedule(double* gtab, int64_t* base, int32_t k, double dt, Schedule s,
                            hipStream_t st) {
   k_schedule<<<1, 256, 0, st>>>(gtab, base, k, dt, s);
@@ -711,9 +811,7 @@ hipError_t launch_qoi_resolve(int32_t n_nodes, int32_t ld, int sample_block, con
                               const uint64_t* qmask, hipStream_t st) {
   const int64_t n = (int64_t)n_nodes * ld;
   if (n == 0 || sample_block < 64) return hipSuccess;
-  const int spl = sample_block / 64;
-  k_qoi_resolve<<<grid_for(n, 256), 256, 0, st>>>(n_nodes, ld, sample_block, spl, radial, u_f64, uh, uc,
-                                                   q, qmask);
+  k_qoi_resolve<<<grid_for(n, 256), 256, 0, st>>>(n_nodes, ld, radial, u_f64, uh, uc, q, qmask);
   return hipGetLastError();
 }
 

@@ -52,6 +52,13 @@ class Info(ctypes.Structure):
                 ("workspace_bytes", ctypes.c_size_t)]
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("n_meshes", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
+                ("samples_per_lane", ctypes.c_int32), ("tile_nodes", ctypes.c_int32),
+                ("grid", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
+                ("tuned_ms_per_step", ctypes.c_double)]
+
+
 _lib = None
 
 _P = ctypes.c_void_p
@@ -80,6 +87,12 @@ _SIGS = {
     "ens_apply": (_I32, [_P, _I32, _P, _P, _P]),
     "ens_save": (_I32, [_P, _P, ctypes.POINTER(_SZ)]),
     "ens_load": (_I32, [_P, _P, _SZ]),
+    "ens_batch_create": (_I32, [ctypes.POINTER(_P), _I32, ctypes.POINTER(_P)]),
+    "ens_batch_destroy": (_I32, [_P]),
+    "ens_batch_last_error": (ctypes.c_char_p, [_P]),
+    "ens_batch_info": (_I32, [_P, ctypes.POINTER(BatchInfo)]),
+    "ens_batch_step": (_I32, [_P, _I64, _P]),
+    "ens_batch_autotune": (_I32, [_P, _I32]),
 }
 
 
@@ -264,6 +277,48 @@ class Ensemble:
     def load(self, blob: bytes):
         buf = ctypes.create_string_buffer(blob, len(blob))
         self._check(self._lib.ens_load(self._h, ctypes.addressof(buf), len(blob)))
+
+
+class Batch:
+    """Several Ensemble contexts stepped together (one launch per step)."""
+
+    def __init__(self, members):
+        self._lib = load_library()
+        self.members = list(members)
+        arr = (_P * len(self.members))(*[m._h for m in self.members])
+        h = _P()
+        rc = self._lib.ens_batch_create(arr, len(self.members), ctypes.byref(h))
+        if rc != ENS_OK:
+            msgs = [m._lib.ens_last_error(m._h).decode() for m in self.members]
+            raise EnsfemError(rc, "ens_batch_create failed: " + "; ".join(x for x in msgs if x))
+        self._h = h
+
+    def _check(self, rc: int):
+        if rc != ENS_OK:
+            msg = self._lib.ens_batch_last_error(self._h)
+            raise EnsfemError(rc, msg.decode() if msg else "")
+
+    def step(self, n_steps: int, stream=None):
+        self._check(self._lib.ens_batch_step(self._h, int(n_steps), _stream_handle(stream)))
+
+    def autotune(self, trial_steps: int = 10):
+        self._check(self._lib.ens_batch_autotune(self._h, int(trial_steps)))
+
+    def info(self) -> dict:
+        inf = BatchInfo()
+        self._check(self._lib.ens_batch_info(self._h, ctypes.byref(inf)))
+        return {k: getattr(inf, k) for k, _ in BatchInfo._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ens_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def setup_case(mesh, eh, h, F, nu=0.49, shear_k=5.0 / 6.0, rho=1.0, alpha=50.0,
