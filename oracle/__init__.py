@@ -17,7 +17,10 @@ What it computes, following the paper (arXiv 2101.09059, Li & Schiavazzi):
   * cfl.py      -- stable step from the largest element eigenvalue;
   * matern.py   -- Matern covariance and dense-Cholesky field samples on
                    element centroids (Sec. 2.1);
-  * stats.py    -- per-node ensemble mean and variance.
+  * stats.py    -- per-node ensemble mean and variance;
+  * mlp.py      -- the learned form's GELU network, forward / backward / Adam;
+  * control_variate.py -- multifidelity control-variate mean / variance
+                   and its fallback rule.
 
 Every function is pinned by the CPU tests (closed forms, invariants,
 textbook special cases); see each module header for its pins.
