@@ -204,9 +204,10 @@ int32_t ens_load(ens_ctx* ctx, const void* host, size_t bytes);
 typedef struct ens_batch ens_batch;
 typedef struct {
   int32_t n_meshes, n_tiles;
-  int32_t samples_per_lane; /* 64 lanes x this many samples per tile      */
+  int32_t samples_per_lane; /* 64 lanes x up to this many samples per tile */
   int32_t tile_nodes;       /* nodes per tile                            */
-  int32_t grid;             /* persistent workgroups per launch          */
+  int32_t grid;             /* persistent workgroups per launch, 0 = one
+                               workgroup per tile                        */
   int32_t graph_steps;      /* steps per captured graph                  */
   double tuned_ms_per_step; /* best autotuner trial, 0 before autotune   */
 } ens_batch_info_t;
@@ -220,8 +221,8 @@ int32_t ens_batch_info(ens_batch* b, ens_batch_info_t* out);
  * bitwise those of stepping each context alone. */
 int32_t ens_batch_step(ens_batch* b, int64_t n_steps, void* stream);
 /* Times trial_steps steps for each candidate tiling (samples per lane 1 or
- * 2, 4/16/64 nodes per tile, 2/4/8 workgroups per compute unit) and keeps
- * the fastest.  The trial steps ADVANCE every context's state: re-init the
+ * 2, 4/8/16 nodes per tile, 4 or 8 persistent workgroups per compute unit
+ * or one workgroup per tile) and keeps the fastest.  The trial steps ADVANCE every context's state: re-init the
  * states afterwards to restart from the initial condition. */
 int32_t ens_batch_autotune(ens_batch* b, int32_t trial_steps);
 

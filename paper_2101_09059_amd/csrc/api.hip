@@ -312,25 +312,25 @@ StepArgs base_args(const ens_ctx* c, bool f32) {
   a.n_nb = (int32_t)((c->n_nodes + npb - 1) / npb);
   a.n_sb = c->ld / c->SB;
   a.sb_inner = c->sb_inner;
-  a.adj.ptr = c->p<int32_t>(c->L.adj_ptr);
-  a.adj.el = c->p<int32_t>(c->L.adj_el);
-  a.adj.nb = c->p<int2>(c->L.adj_nb);
-  a.adj.k = f32 ? (const void*)c->p<float>(c->L.k32) : (const void*)c->p<double>(c->L.k64);
-  a.eh = f32 ? (const void*)c->p<float>(c->L.eh32) : (const void*)c->p<double>(c->L.eh64);
+  a.adj.ptr = gptr(c->p<int32_t>(c->L.adj_ptr));
+  a.adj.el = gptr(c->p<int32_t>(c->L.adj_el));
+  a.adj.nb = gptr(c->p<int2>(c->L.adj_nb));
+  a.adj.k = gptr(f32 ? (const void*)c->p<float>(c->L.k32) : (const void*)c->p<double>(c->L.k64));
+  a.eh = gptr(f32 ? (const void*)c->p<float>(c->L.eh32) : (const void*)c->p<double>(c->L.eh64));
   if (use_shared(c)) {
-    a.bsr.ptr = c->p<int32_t>(c->L.bsr_ptr);
-    a.bsr.col = c->p<int32_t>(c->L.bsr_col);
-    a.bsr.val = f32 ? (const void*)c->p<float>(c->L.bsr32) : (const void*)c->p<double>(c->L.bsr64);
+    a.bsr.ptr = gptr(c->p<int32_t>(c->L.bsr_ptr));
+    a.bsr.col = gptr(c->p<int32_t>(c->L.bsr_col));
+    a.bsr.val = gptr(f32 ? (const void*)c->p<float>(c->L.bsr32) : (const void*)c->p<double>(c->L.bsr64));
   }
-  a.minv = f32 ? (const void*)c->p<float>(c->L.minv32) : (const void*)c->p<double>(c->L.minv64);
-  a.F = c->p<double>(c->L.F);
-  a.fixed = c->p<uint8_t>(c->L.fixed);
-  a.radial = c->p<double>(c->L.radial);
-  a.q = c->p<double>(c->L.q);
-  a.qmask = c->p<uint64_t>(c->L.qmask);
+  a.minv = gptr(f32 ? (const void*)c->p<float>(c->L.minv32) : (const void*)c->p<double>(c->L.minv64));
+  a.F = gptr(c->p<double>(c->L.F));
+  a.fixed = gptr(c->p<uint8_t>(c->L.fixed));
+  a.radial = gptr(c->p<double>(c->L.radial));
+  a.q = gptr(c->p<double>(c->L.q));
+  a.qmask = gptr(c->p<uint64_t>(c->L.qmask));
   a.qwords = (c->ld + 63) / 64;
-  a.gtab = c->p<double>(c->L.gtab);
-  a.energy_part = c->p<double>(c->L.epart);
+  a.gtab = gptr(c->p<double>(c->L.gtab));
+  a.energy_part = gptr(c->p<double>(c->L.epart));
   return a;
 }
 
@@ -339,14 +339,14 @@ StepArgs base_args(const ens_ctx* c, bool f32) {
 void set_state_ptrs(const ens_ctx* c, StepArgs& a, int flip) {
   const int cur = c->cur ^ flip;
   if (c->state_prec == ENS_STATE_F64) {
-    a.u_cur = c->p<double>(c->L.u[cur]);
-    a.u_prev = c->p<double>(c->L.u[1 - cur]);
-    a.u_next = c->p<double>(c->L.u[1 - cur]);
+    a.u_cur = gptr(c->p<double>(c->L.u[cur]));
+    a.u_prev = gptr(c->p<double>(c->L.u[1 - cur]));
+    a.u_next = gptr(c->p<double>(c->L.u[1 - cur]));
   } else {
-    a.uh_cur = c->p<float>(c->L.uh[cur]);
-    a.uh_next = c->p<float>(c->L.uh[1 - cur]);
-    a.uc = c->state_prec == ENS_STATE_F32_KAHAN ? c->p<float>(c->L.uc) : nullptr;
-    a.v = c->p<float>(c->L.v);
+    a.uh_cur = gptr(c->p<float>(c->L.uh[cur]));
+    a.uh_next = gptr(c->p<float>(c->L.uh[1 - cur]));
+    a.uc = gptr(c->state_prec == ENS_STATE_F32_KAHAN ? c->p<float>(c->L.uc) : nullptr);
+    a.v = gptr(c->p<float>(c->L.v));
   }
 }
 
@@ -1090,7 +1090,8 @@ struct ens_batch {
   double tuned_ms = 0.0;
   // device tables (small, owned)
   BatchTile* d_tiles = nullptr;
-  int32_t n_tiles = 0;
+  int32_t n_tiles = 0, n_wide = 0;  // tiles [0, n_wide) have 2 samples per lane
+  bool one_per_tile = false;        // grid = one workgroup per tile
   size_t tiles_cap = 0;
   StepArgs* d_desc = nullptr;
   std::vector<int> desc_cur;
@@ -1126,35 +1127,24 @@ void drop_graph(ens_batch* b) {
   b->graph = nullptr;
 }
 
-// Tiles of `tile_nodes` consecutive nodes times one sample block of 64*spl
-// samples, meshes interleaved so the persistent workgroups see a mix.
+// Tiles of `tile_nodes` consecutive nodes times one sample block, mesh by
+// mesh, node-fastest.  With spl = 2 a mesh's samples go in blocks of 128
+// (2 per lane) plus a last block of 64 when S_pad is an odd multiple of 64.
 int32_t build_tiles(ens_batch* b) {
-  std::vector<std::vector<BatchTile>> per(b->ctx.size());
-  size_t total = 0;
-  const int sbw = 64 * b->spl;
+  std::vector<BatchTile> wide, narrow;  // 2 samples per lane, then 1
   for (size_t m = 0; m < b->ctx.size(); ++m) {
     const ens_ctx* c = b->ctx[m];
-    const int nsb = c->ld / sbw;
-    for (int sb = 0; sb < nsb; ++sb)
+    for (int s0 = 0; s0 < c->ld;) {
+      const int spl = (b->spl == 2 && s0 + 128 <= c->ld) ? 2 : 1;
       for (int64_t n0 = 0; n0 < c->n_nodes; n0 += b->tile_nodes)
-        per[m].push_back(BatchTile{(int32_t)m, (int32_t)n0,
-                                   (int32_t)std::min<int64_t>(b->tile_nodes, c->n_nodes - n0), sb});
-    total += per[m].size();
-  }
-  std::vector<BatchTile> tiles;
-  tiles.reserve(total);
-  // proportional interleave: take from each mesh in order of its progress
-  std::vector<size_t> at(per.size(), 0);
-  while (tiles.size() < total) {
-    size_t best = 0;
-    double best_f = 2.0;
-    for (size_t m = 0; m < per.size(); ++m) {
-      if (at[m] >= per[m].size()) continue;
-      const double f = (double)at[m] / (double)per[m].size();
-      if (f < best_f) { best_f = f; best = m; }
+        (spl == 2 ? wide : narrow)
+            .push_back(BatchTile{(int32_t)m, (int32_t)n0, (int32_t)std::min<int64_t>(b->tile_nodes, c->n_nodes - n0), s0});
+      s0 += 64 * spl;
     }
-    tiles.push_back(per[best][at[best]++]);
   }
+  b->n_wide = (int32_t)wide.size();
+  std::vector<BatchTile> tiles(wide);
+  tiles.insert(tiles.end(), narrow.begin(), narrow.end());
   if (tiles.size() > b->tiles_cap) {
     if (b->d_tiles) BHIPC(hipFree(b->d_tiles));
     b->d_tiles = nullptr;
@@ -1208,8 +1198,13 @@ int32_t enqueue_steps(ens_batch* b, int64_t k_total) {
     for (ens_ctx* c : b->ctx)
       BHIPC(launch_schedule(c->p<double>(c->L.gtab), c->p<int64_t>(c->L.base), k, c->dt, c->sched, b->st));
     for (int j = 0; j < k; ++j)
-      BHIPC(launch_batch_step(b->d_tiles, b->n_tiles, b->d_desc, j, b->apply_f32, b->mode, b->spl, b->qoi,
-                              b->grid, b->st));
+      for (int cls = 0; cls < 2; ++cls) {
+        const int32_t first = cls == 0 ? 0 : b->n_wide;
+        const int32_t count = cls == 0 ? b->n_wide : b->n_tiles - b->n_wide;
+        const int grid = b->one_per_tile ? (int)((count + 7) / 8 * 8) : b->grid;
+        BHIPC(launch_batch_step(b->d_tiles + first, count, cls == 0 ? 2 : 1, b->d_desc, j, b->apply_f32,
+                                b->mode, b->qoi, grid, b->st));
+      }
     for (ens_ctx* c : b->ctx) BHIPC(launch_advance(c->p<int64_t>(c->L.base), k, b->st));
     done += k;
   }
@@ -1260,7 +1255,8 @@ int32_t ens_batch_create(ens_ctx** ctxs, int32_t n, ens_batch** out) {
   b->apply_f32 = c0->apply_prec == ENS_F32;
   b->mode = c0->state_prec;
   b->qoi = c0->qoi_mask != 0;
-  b->spl = all128 ? 2 : 1;
+  b->spl = 2;
+  (void)all128;
   b->desc_cur.assign(n, -1);
   b->desc_gen.assign(n, ~0ull);
   int cus = 256;
@@ -1273,7 +1269,7 @@ int32_t ens_batch_create(ens_ctx** ctxs, int32_t n, ens_batch** out) {
     return ENS_EDEVICE;
   }
   cus = prop.multiProcessorCount;
-  b->grid = 4 * cus;
+  b->grid = 8 * cus;
   if (build_tiles(b) != ENS_OK) {
     delete b;
     return ENS_EDEVICE;
@@ -1304,7 +1300,7 @@ int32_t ens_batch_info(ens_batch* b, ens_batch_info_t* out) {
   out->n_tiles = b->n_tiles;
   out->samples_per_lane = b->spl;
   out->tile_nodes = b->tile_nodes;
-  out->grid = b->grid;
+  out->grid = b->one_per_tile ? 0 : b->grid;
   out->graph_steps = b->graph_k;
   out->tuned_ms_per_step = b->tuned_ms;
   return ENS_OK;
@@ -1329,7 +1325,7 @@ int32_t ens_batch_step(ens_batch* b, int64_t n_steps, void* stream) {
     }
     std::vector<uint64_t> gen(b->ctx.size());
     for (size_t m = 0; m < b->ctx.size(); ++m) gen[m] = b->ctx[m]->gen;
-    const int sig[3] = {b->spl, b->tile_nodes, b->grid};
+    const int sig[3] = {b->spl, b->tile_nodes, b->one_per_tile ? -1 : b->grid};
     if (b->exec && (gen != b->graph_gen || std::memcmp(sig, b->graph_sig, sizeof sig) != 0)) drop_graph(b);
     int64_t left = n_steps;
     if (left >= b->graph_k) {
@@ -1375,21 +1371,19 @@ int32_t ens_batch_autotune(ens_batch* b, int32_t trial_steps) {
     hipDeviceProp_t prop;
     BHIPC(hipGetDeviceProperties(&prop, b->device));
     const int cus = prop.multiProcessorCount;
-    bool all128 = true;
-    for (const ens_ctx* c : b->ctx)
-      if (c->ld % 128 != 0) all128 = false;
     hipEvent_t e0, e1;
     BHIPC(hipEventCreate(&e0));
     BHIPC(hipEventCreate(&e1));
     double best = 1e300;
     int bs = b->spl, bt = b->tile_nodes, bg = b->grid;
+    int bone = b->one_per_tile ? 1 : 0;
     for (int spl : {1, 2}) {
-      if (spl == 2 && !all128) continue;
-      for (int tn : {4, 16, 64}) {
-        for (int gm : {2, 4, 8}) {
+      for (int tn : {4, 8, 16}) {
+        for (int gm : {0, 4, 8}) {  // 0: one workgroup per tile
           b->spl = spl;
           b->tile_nodes = tn;
-          b->grid = gm * cus;
+          b->one_per_tile = gm == 0;
+          b->grid = (gm ? gm : 8) * cus;
           rc = build_tiles(b);
           if (rc == ENS_OK) rc = build_desc(b);
           if (rc != ENS_OK) break;
@@ -1408,7 +1402,8 @@ int32_t ens_batch_autotune(ens_batch* b, int32_t trial_steps) {
             best = ms / trial_steps;
             bs = spl;
             bt = tn;
-            bg = gm * cus;
+            bg = b->grid;
+            bone = gm == 0 ? 1 : 0;
           }
           if (trial_steps & 1) build_desc(b);
         }
@@ -1422,6 +1417,7 @@ int32_t ens_batch_autotune(ens_batch* b, int32_t trial_steps) {
     b->spl = bs;
     b->tile_nodes = bt;
     b->grid = bg;
+    b->one_per_tile = bone != 0;
     b->tuned_ms = best;
     rc = build_tiles(b);
     if (rc != ENS_OK) return rc;

@@ -14,6 +14,16 @@ namespace ensfem {
 constexpr int kBlock = 256;       // threads per workgroup for the ensemble kernels
 constexpr int kEnergyCap = 4096;  // energy records kept (ring)
 
+// Device arrays referenced from argument structs are global memory; the
+// qualifier keeps that knowledge when a struct is read from a device table
+// (plain pointers loaded from memory are generic to the compiler).
+#define ENS_GLOBAL __attribute__((address_space(1)))
+
+template <class T>
+__host__ __device__ inline ENS_GLOBAL T* gptr(T* p) {
+  return (ENS_GLOBAL T*)p;
+}
+
 // Load-schedule kinds (mirror the public enum).
 struct Schedule {
   int kind;
@@ -26,10 +36,10 @@ struct Schedule {
 // Entries walk around the node; nb.x < 0 (stored as ~b) marks an entry whose
 // b is the previous entry's c.
 struct Adjacency {
-  const int32_t* ptr;
-  const int32_t* el;
-  const int2* nb;
-  const void* k;  // double[18] or float[18] per entry
+  ENS_GLOBAL const int32_t* ptr;
+  ENS_GLOBAL const int32_t* el;
+  ENS_GLOBAL const int2* nb;
+  ENS_GLOBAL const void* k;  // double[18] or float[18] per entry
 };
 
 // Shared-stiffness block rows (used when (E h)_{e,s} does not depend on s):
@@ -37,9 +47,9 @@ struct Adjacency {
 // every neighbour j != i, with the diagonal block implied by the rows'
 // translation null space: (K u)_i = sum_j K_ij (u_j - u_i).
 struct BlockRows {
-  const int32_t* ptr;
-  const int32_t* col;
-  const void* val;  // double[9] or float[9] per block
+  ENS_GLOBAL const int32_t* ptr;
+  ENS_GLOBAL const int32_t* col;
+  ENS_GLOBAL const void* val;  // double[9] or float[9] per block
 };
 
 // State storage modes.
@@ -53,39 +63,39 @@ struct StepArgs {
   int32_t sb_inner;    // workgroup order: sample block fastest (1) or node block fastest (0)
   Adjacency adj;
   BlockRows bsr;
-  const void* eh;      // (E h)_{e,s} in the apply precision, [n_el][ld]
-  const void* minv;    // 1/m per node and sample, double (F64 apply) or float, [n_nodes][ld]
-  const double* F;     // nodal load [n_nodes][3]
-  const uint8_t* fixed;   // clamped-dof bits per node
-  const double* radial;   // [n_nodes][3]
+  ENS_GLOBAL const void* eh;      // (E h)_{e,s} in the apply precision, [n_el][ld]
+  ENS_GLOBAL const void* minv;    // 1/m per node and sample, double (F64 apply) or float, [n_nodes][ld]
+  ENS_GLOBAL const double* F;     // nodal load [n_nodes][3]
+  ENS_GLOBAL const uint8_t* fixed;   // clamped-dof bits per node
+  ENS_GLOBAL const double* radial;   // [n_nodes][3]
   // FP64 two-level state
-  const double* u_cur;
-  const double* u_prev;
-  double* u_next;
+  ENS_GLOBAL const double* u_cur;
+  ENS_GLOBAL const double* u_prev;
+  ENS_GLOBAL double* u_next;
   // FP32 velocity-form state
-  const float* uh_cur;
-  float* uh_next;
-  float* uc;           // Kahan compensation (in place)
-  float* v;            // velocity v_{n-1/2} -> v_{n+1/2} (in place)
-  double* q;           // running peak radial displacement [n_nodes][ld]
+  ENS_GLOBAL const float* uh_cur;
+  ENS_GLOBAL float* uh_next;
+  ENS_GLOBAL float* uc;           // Kahan compensation (in place)
+  ENS_GLOBAL float* v;            // velocity v_{n-1/2} -> v_{n+1/2} (in place)
+  ENS_GLOBAL double* q;           // running peak radial displacement [n_nodes][ld]
   // At-max bits (wave-per-node kernels): bit set <=> the running peak equals
   // the current radial displacement, which is then not stored in q.
   // Per node ceil(ld/64) words; sample s in word s/64, bit s%64.
-  uint64_t* qmask;
+  ENS_GLOBAL uint64_t* qmask;
   int32_t qwords;
-  const double* gtab;  // load factors of the current chunk
+  ENS_GLOBAL const double* gtab;  // load factors of the current chunk
   int32_t j;           // index into gtab
   double dt, a;        // step, alpha dt / 2
-  double* energy_part; // [n_nb][ld] per node-block energy partial sums
+  ENS_GLOBAL double* energy_part; // [n_nb][ld] per node-block energy partial sums
 };
 
 // One work item of the batched step: `count` nodes from `node0` of mesh
-// `mesh`, sample block `sblock` (64 lanes x SPL samples).
+// `mesh`, samples sample0 .. sample0 + 64*spl - 1 (spl fixed per launch).
 struct BatchTile {
   int32_t mesh;
   int32_t node0;
   int32_t count;
-  int32_t sblock;
+  int32_t sample0;
 };
 
 // ---- set-up kernels (setup.hip) -------------------------------------------
@@ -128,8 +138,8 @@ hipError_t launch_starter_f32(int32_t n_nodes, int32_t ld, const float* R, const
 hipError_t launch_split_f32(int64_t n, const double* u0, float* uh, float* uc, hipStream_t st);
 hipError_t launch_qoi_init(int32_t n_nodes, int32_t ld, const double* radial, const double* u_f64,
                            const float* uh, const float* uc, double* q, hipStream_t st);
-hipError_t launch_batch_step(const BatchTile* tiles, int32_t n_tiles, const StepArgs* desc, int32_t j,
-                             bool apply_f32, int mode, int spl, bool qoi, int grid, hipStream_t st);
+hipError_t launch_batch_step(const BatchTile* tiles, int32_t n_tiles, int spl, const StepArgs* desc, int32_t j,
+                             bool apply_f32, int mode, bool qoi, int grid, hipStream_t st);
 hipError_t launch_qoi_resolve(int32_t n_nodes, int32_t ld, int sample_block, const double* radial,
                               const double* u_f64, const float* uh, const float* uc, double* q,
                               const uint64_t* qmask, hipStream_t st);

@@ -1,0 +1,781 @@
+// Learned form: a fully connected GELU network that maps the leading
+// Karhunen-Loeve coefficients of log E and log h to the per-node peak radial
+// displacement, trained and evaluated with BF16 matrix-core (MFMA) kernels
+// accumulating in FP32, plus the multifidelity control-variate combination.
+//
+// Storage: W_l [out][in] FP32 master copy + BF16 copy, biases FP32, Adam
+// moments FP32; activations BF16 between layers, pre-activations FP32.
+//
+// GEMM: C[M x N] = sum_k A(m, k) B(k, n), 128 x 128 block tile, 32-deep
+// K steps staged through LDS (both operands stored K-contiguous there),
+// 4 waves of 64 x 64, each a 4 x 4 grid of 16x16x32 BF16 MFMAs.  The
+// operands may be K-contiguous or M/N-contiguous in global memory.
+// Epilogues: bias + GELU (forward hidden), bias (forward output), FP32
+// store with split-K partials (backward data / gradient check), per-column
+// sums of y and y^2 (moments over many draws without storing them), fused
+// Adam update (backward weights).  All reductions run in a fixed order.
+#include "ensfem.h"
+#include "ensfem_surrogate.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 128, BN = 128, BK = 32, LDS_STRIDE = BK + 8;
+
+enum Epi { EPI_F32 = 0, EPI_BIAS_GELU = 1, EPI_BIAS_F32 = 2, EPI_MOMENTS = 3, EPI_ADAM = 4 };
+
+struct GemmArgs {
+  int M, N, K;
+  const __bf16* A;
+  int64_t a_sm, a_sk;  // A(m, k) = A[m * a_sm + k * a_sk]
+  const __bf16* B;
+  int64_t b_sk, b_sn;  // B(k, n) = B[k * b_sk + n * b_sn]
+  int k_chunk;         // K range per blockIdx.z
+  bool vec_ok;         // 16-byte operand loads are aligned
+  // epilogue operands
+  float* C32;
+  int64_t ldc;
+  int64_t split_stride;  // elements between split-K partial outputs
+  const float* bias;
+  float* Z32;
+  __bf16* H16;
+  float* P1;
+  float* P2;  // [gridDim.y][N] per-row-block column sums
+  float* W32;
+  float* M1;
+  float* M2;
+  __bf16* W16;
+  float lr, b1, b2, eps, c1, c2;
+};
+
+__device__ __forceinline__ float gelu_f(float x) {
+  return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f));
+}
+
+__device__ __forceinline__ float gelu_grad_f(float x) {
+  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+
+// Stage a BM x BK (or BN x BK) tile of an operand into LDS [row][k].
+// KC: the operand is contiguous along k in global memory.
+template <bool KC>
+__device__ __forceinline__ void stage_tile(__bf16 (*S)[LDS_STRIDE], const __bf16* __restrict__ P,
+                                           int64_t s_row, int64_t s_k, int row0, int k0, int rows,
+                                           int kend, bool vec_ok) {
+  const int t = threadIdx.x;
+  if constexpr (KC) {
+    // 128 rows x 4 chunks of 8 k
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int c = t + 256 * it;
+      const int r = c >> 2, kc = (c & 3) * 8;
+      const int gr = row0 + r, gk = k0 + kc;
+      bf16x8 v;
+      if (gr < rows && gk + 8 <= kend && vec_ok) {
+        v = *reinterpret_cast<const bf16x8*>(P + (int64_t)gr * s_row + gk);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          v[e] = (gr < rows && gk + e < kend) ? P[(int64_t)gr * s_row + (int64_t)(gk + e) * s_k] : (__bf16)0.0f;
+      }
+      *reinterpret_cast<bf16x8*>(&S[r][kc]) = v;
+    }
+  } else {
+    // 32 k x 16 chunks of 8 rows, transposed into [row][k]
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int c = t + 256 * it;
+      const int kk = c >> 4, rc = (c & 15) * 8;
+      const int gk = k0 + kk, gr = row0 + rc;
+      bf16x8 v;
+      if (gk < kend && gr + 8 <= rows && vec_ok) {
+        v = *reinterpret_cast<const bf16x8*>(P + (int64_t)gk * s_k + gr);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          v[e] = (gk < kend && gr + e < rows) ? P[(int64_t)(gr + e) * s_row + (int64_t)gk * s_k] : (__bf16)0.0f;
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) S[rc + e][kk] = v[e];
+    }
+  }
+}
+
+template <bool AK, bool BKC, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+  __shared__ __bf16 As[BM][LDS_STRIDE];
+  __shared__ __bf16 Bs[BN][LDS_STRIDE];
+  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  const int kbeg = blockIdx.z * g.k_chunk;
+  const int kend = min(g.K, kbeg + g.k_chunk);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int wm = w >> 1, wn = w & 1;
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    stage_tile<AK>(As, g.A, g.a_sm, g.a_sk, m0, k0, g.M, kend, g.vec_ok);
+    stage_tile<BKC>(Bs, g.B, g.b_sn, g.b_sk, n0, k0, g.N, kend, g.vec_ok);
+    __syncthreads();
+    bf16x8 a[4], b[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[wm * 64 + i * 16 + (l & 15)][8 * (l >> 4)]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bs[wn * 64 + j * 16 + (l & 15)][8 * (l >> 4)]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+  // lane l of a 16x16 output tile holds rows 4*(l/16) + r, column l % 16
+  if constexpr (EPI == EPI_MOMENTS) {
+    __shared__ float red1[2][BN], red2[2][BN];
+    float s1[4], s2[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + wn * 64 + j * 16 + (l & 15);
+      const float bn = (n < g.N) ? g.bias[n] : 0.f;
+      float a1 = 0.f, a2 = 0.f;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm * 64 + i * 16 + 4 * (l >> 4) + r;
+          if (m < g.M) {
+            const float y = acc[i][j][r] + bn;
+            a1 += y;
+            a2 = fmaf(y, y, a2);
+          }
+        }
+      // fixed butterfly over the 4 lane groups holding this column
+      a1 += __shfl_xor(a1, 16, 64);
+      a2 += __shfl_xor(a2, 16, 64);
+      a1 += __shfl_xor(a1, 32, 64);
+      a2 += __shfl_xor(a2, 32, 64);
+      s1[j] = a1;
+      s2[j] = a2;
+    }
+    if (l < 16) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        red1[wm][wn * 64 + j * 16 + l] = s1[j];
+        red2[wm][wn * 64 + j * 16 + l] = s2[j];
+      }
+    }
+    __syncthreads();
+    if (threadIdx.x < BN) {
+      const int n = n0 + threadIdx.x;
+      if (n < g.N) {
+        g.P1[(int64_t)blockIdx.y * g.N + n] = red1[0][threadIdx.x] + red1[1][threadIdx.x];
+        g.P2[(int64_t)blockIdx.y * g.N + n] = red2[0][threadIdx.x] + red2[1][threadIdx.x];
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = m0 + wm * 64 + i * 16 + 4 * (l >> 4) + r;
+          const int n = n0 + wn * 64 + j * 16 + (l & 15);
+          if (m >= g.M || n >= g.N) continue;
+          const float v = acc[i][j][r];
+          const int64_t idx = (int64_t)m * g.ldc + n;
+          if constexpr (EPI == EPI_F32) {
+            g.C32[blockIdx.z * g.split_stride + idx] = v;
+          } else if constexpr (EPI == EPI_BIAS_GELU) {
+            const float z = v + g.bias[n];
+            g.Z32[idx] = z;
+            g.H16[idx] = (__bf16)gelu_f(z);
+          } else if constexpr (EPI == EPI_BIAS_F32) {
+            g.C32[idx] = v + g.bias[n];
+          } else if constexpr (EPI == EPI_ADAM) {
+            const float m1 = fmaf(g.b1, g.M1[idx], (1.f - g.b1) * v);
+            const float m2 = fmaf(g.b2, g.M2[idx], (1.f - g.b2) * v * v);
+            const float wv = g.W32[idx] - g.lr * (m1 * g.c1) / (sqrtf(m2 * g.c2) + g.eps);
+            g.M1[idx] = m1;
+            g.M2[idx] = m2;
+            g.W32[idx] = wv;
+            g.W16[idx] = (__bf16)wv;
+          }
+        }
+  }
+}
+
+__global__ void k_to_bf16(int64_t n, const float* __restrict__ x, __bf16* __restrict__ y) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < n) y[t] = (__bf16)x[t];
+}
+
+// sum of split-K partials in split order
+__global__ void k_split_reduce(int64_t n, int splits, int64_t stride, const float* __restrict__ P,
+                               float* __restrict__ out) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n) return;
+  float s = 0.f;
+  for (int z = 0; z < splits; ++z) s += P[z * stride + t];
+  out[t] = s;
+}
+
+// dZ = dH * GELU'(Z): FP32 copy (bias gradient) and BF16 copy (GEMMs)
+__global__ void k_gelu_bwd(int64_t n, const float* __restrict__ dH, const float* __restrict__ Z,
+                           float* __restrict__ dZ32, __bf16* __restrict__ dZ16) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n) return;
+  const float d = dH[t] * gelu_grad_f(Z[t]);
+  dZ32[t] = d;
+  dZ16[t] = (__bf16)d;
+}
+
+// MSE: dY = 2 (Y - T) / (B n) in BF16 and FP32; per-block partial loss sums.
+__global__ void k_mse(int64_t n, float scale, const float* __restrict__ Y, const float* __restrict__ T,
+                      __bf16* __restrict__ dY16, float* __restrict__ dY32, double* __restrict__ part) {
+  __shared__ double red[256];
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  double e2 = 0.0;
+  if (t < n) {
+    const float d = Y[t] - T[t];
+    dY16[t] = (__bf16)(2.f * scale * d);
+    if (dY32) dY32[t] = 2.f * scale * d;
+    e2 = (double)d * (double)d;
+  }
+  red[threadIdx.x] = e2;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_loss_final(int nparts, const double* __restrict__ part, double scale,
+                             float* __restrict__ loss) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < nparts; ++i) s += part[i];
+  *loss = (float)(s * scale);
+}
+
+// column sums of a [rows][cols] FP32 matrix, one thread per column
+__global__ void k_colsum(int rows, int cols, const float* __restrict__ X, float* __restrict__ out) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= cols) return;
+  float s = 0.f;
+  for (int r = 0; r < rows; ++r) s += X[(int64_t)r * cols + c];
+  out[c] = s;
+}
+
+__global__ void k_adam_vec(int n, const float* __restrict__ g, float* __restrict__ w, float* __restrict__ m1,
+                           float* __restrict__ m2, float lr, float b1, float b2, float eps, float c1, float c2) {
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= n) return;
+  const float a = fmaf(b1, m1[t], (1.f - b1) * g[t]);
+  const float b = fmaf(b2, m2[t], (1.f - b2) * g[t] * g[t]);
+  m1[t] = a;
+  m2[t] = b;
+  w[t] = w[t] - lr * (a * c1) / (sqrtf(b * c2) + eps);
+}
+
+// moments partials [rb][N] -> running FP64 totals, row blocks in order
+__global__ void k_moment_accumulate(int rb, int N, const float* __restrict__ P1, const float* __restrict__ P2,
+                                    double* __restrict__ S1, double* __restrict__ S2) {
+  const int n = blockIdx.x * 256 + threadIdx.x;
+  if (n >= N) return;
+  double a = 0.0, b = 0.0;
+  for (int r = 0; r < rb; ++r) {
+    a += (double)P1[(int64_t)r * N + n];
+    b += (double)P2[(int64_t)r * N + n];
+  }
+  S1[n] += a;
+  S2[n] += b;
+}
+
+// Control-variate combination per node (FP64), see sur_cv_moments.
+__global__ void k_cv(int64_t n, int N, const double* __restrict__ qH, const double* __restrict__ qL,
+                     const double* __restrict__ sL, const double* __restrict__ sL2, double M,
+                     double* __restrict__ mean, double* __restrict__ var, double* __restrict__ rho) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const double* h = qH + i * N;
+  const double* q = qL + i * N;
+  // two estimators: the values (first moment) and their squares (second)
+  double est[2];
+  double rho1 = 0.0;
+  for (int p = 0; p < 2; ++p) {
+    double hm = 0.0, lm = 0.0;
+    for (int s = 0; s < N; ++s) {
+      const double a = p ? h[s] * h[s] : h[s];
+      const double b = p ? q[s] * q[s] : q[s];
+      hm += a;
+      lm += b;
+    }
+    hm /= N;
+    lm /= N;
+    double cov = 0.0, vl = 0.0, vh = 0.0;
+    for (int s = 0; s < N; ++s) {
+      const double a = (p ? h[s] * h[s] : h[s]) - hm;
+      const double b = (p ? q[s] * q[s] : q[s]) - lm;
+      cov += a * b;
+      vl += b * b;
+      vh += a * a;
+    }
+    cov /= (N - 1);
+    vl /= (N - 1);
+    vh /= (N - 1);
+    const double beta = vl > 0.0 ? cov / vl : 0.0;
+    const double lM = (p ? sL2[i] : sL[i]) / M;
+    est[p] = hm - beta * (lm - lM);
+    if (p == 0) rho1 = (vl > 0.0 && vh > 0.0) ? cov / sqrt(vl * vh) : 0.0;
+  }
+  mean[i] = est[0];
+  var[i] = est[1] - est[0] * est[0];
+  rho[i] = rho1;
+}
+
+inline unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace
+
+struct sur_net {
+  int device = 0;
+  int n_in = 0, width = 0, n_hidden = 0, n_out = 0, max_batch = 0;
+  std::string err;
+  // layer geometry
+  std::vector<int> fan_in, fan_out;
+  std::vector<size_t> w_off, b_off;  // offsets into the parameter vector (floats)
+  size_t n_params = 0;
+  // workspace
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t o_p32 = 0, o_m1 = 0, o_m2 = 0, o_w16 = 0, o_h0 = 0, o_z = 0, o_h = 0, o_y = 0, o_dy16 = 0,
+         o_dh = 0, o_dz32 = 0, o_dz16 = 0, o_split = 0, o_db = 0, o_p1 = 0, o_p2 = 0, o_s1 = 0, o_s2 = 0,
+         o_lpart = 0, o_loss = 0, total = 0;
+  int splits_max = 64;
+  bool bound = false, have_params = false;
+  int64_t t = 0;  // Adam steps taken
+  int32_t fail(int32_t c, const std::string& m) {
+    err = m;
+    return c;
+  }
+  template <class T>
+  T* p(size_t off) const { return reinterpret_cast<T*>(ws + off); }
+  float* W32(int l) const { return p<float>(o_p32) + w_off[l]; }
+  float* B32(int l) const { return p<float>(o_p32) + b_off[l]; }
+  __bf16* W16(int l) const { return p<__bf16>(o_w16) + w_off[l]; }
+  float* Z(int l) const { return p<float>(o_z) + (size_t)l * max_batch * width; }      // l = 0..n_hidden-1
+  __bf16* H(int l) const {  // l = 0: input, l >= 1 hidden outputs
+    return l == 0 ? p<__bf16>(o_h0) : p<__bf16>(o_h) + (size_t)(l - 1) * max_batch * width;
+  }
+};
+
+#define SHIPC(expr)                                                                              \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess)                                                                        \
+      return s->fail(ENS_EDEVICE, std::string("HIP error: ") + hipGetErrorString(e_) + " at " #expr); \
+  } while (0)
+
+namespace {
+
+size_t al(size_t x) { return (x + 255) & ~size_t(255); }
+
+void plan(sur_net* s) {
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t o = off;
+    off = al(off + b);
+    return o;
+  };
+  const size_t B = s->max_batch, W = s->width;
+  s->o_p32 = take(4 * s->n_params);
+  s->o_m1 = take(4 * s->n_params);
+  s->o_m2 = take(4 * s->n_params);
+  s->o_w16 = take(2 * s->n_params);
+  s->o_h0 = take(2 * B * s->n_in);
+  s->o_z = take(4 * B * W * s->n_hidden);
+  s->o_h = take(2 * B * W * s->n_hidden);
+  s->o_y = take(4 * B * s->n_out);
+  s->o_dy16 = take(2 * B * s->n_out);
+  s->o_dh = take(4 * B * W);
+  s->o_dz32 = take(4 * B * std::max<size_t>(W, s->n_out));
+  s->o_dz16 = take(2 * B * W);
+  s->o_split = take(4 * (size_t)s->splits_max * B * W);
+  s->o_db = take(4 * std::max<size_t>(W, s->n_out));
+  const size_t rb = (B + BM - 1) / BM;
+  s->o_p1 = take(4 * rb * s->n_out);
+  s->o_p2 = take(4 * rb * s->n_out);
+  s->o_s1 = take(8 * (size_t)s->n_out);
+  s->o_s2 = take(8 * (size_t)s->n_out);
+  s->o_lpart = take(8 * (size_t)blocks((int64_t)B * s->n_out));
+  s->o_loss = take(4);
+  s->total = off;
+}
+
+template <bool AK, bool BKC, int EPI>
+hipError_t gemm(GemmArgs g, int splits, hipStream_t st) {
+  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, splits);
+  k_gemm<AK, BKC, EPI><<<grid, 256, 0, st>>>(g);
+  return hipGetLastError();
+}
+
+GemmArgs base_gemm(int M, int N, int K) {
+  GemmArgs g;
+  std::memset(&g, 0, sizeof g);
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.k_chunk = K;
+  return g;
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+// Forward through the hidden layers for `batch` rows of X (FP32 [batch][n_in]).
+int32_t forward_hidden(sur_net* s, const float* X, int batch, hipStream_t st) {
+  SHIPC((k_to_bf16<<<blocks((int64_t)batch * s->n_in), 256, 0, st>>>((int64_t)batch * s->n_in, X, s->H(0)),
+         hipGetLastError()));
+  for (int l = 0; l < s->n_hidden; ++l) {
+    const int in = s->fan_in[l], out = s->fan_out[l];
+    GemmArgs g = base_gemm(batch, out, in);
+    g.A = s->H(l);
+    g.a_sm = in;
+    g.a_sk = 1;
+    g.B = s->W16(l);
+    g.b_sk = 1;
+    g.b_sn = in;
+    g.vec_ok = (in % 8 == 0) && aligned16(g.A) && aligned16(g.B);
+    g.ldc = out;
+    g.bias = s->B32(l);
+    g.Z32 = s->Z(l);
+    g.H16 = s->H(l + 1);
+    SHIPC((gemm<true, true, EPI_BIAS_GELU>(g, 1, st)));
+  }
+  return ENS_OK;
+}
+
+GemmArgs output_gemm(sur_net* s, int batch) {
+  const int L = s->n_hidden, in = s->fan_in[L], out = s->fan_out[L];
+  GemmArgs g = base_gemm(batch, out, in);
+  g.A = s->H(L);
+  g.a_sm = in;
+  g.a_sk = 1;
+  g.B = s->W16(L);
+  g.b_sk = 1;
+  g.b_sn = in;
+  g.vec_ok = (in % 8 == 0) && aligned16(g.A) && aligned16(g.B);
+  g.ldc = out;
+  g.bias = s->B32(L);
+  return g;
+}
+
+int split_count(const sur_net* s, int M, int N, int K) {
+  const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  int sp = std::max(1, 512 / std::max(1, tiles));
+  sp = std::min(sp, s->splits_max);
+  sp = std::min(sp, std::max(1, K / (4 * BK)));
+  return sp;
+}
+
+// dH = dZ_next (bf16 [batch][out]) * W (bf16 [out][in]) -> FP32 [batch][in]
+int32_t backward_data(sur_net* s, int layer, const __bf16* dZ, int batch, float* dH, hipStream_t st) {
+  const int in = s->fan_in[layer], out = s->fan_out[layer];
+  const int sp = split_count(s, batch, in, out);
+  GemmArgs g = base_gemm(batch, in, out);
+  g.A = dZ;
+  g.a_sm = out;
+  g.a_sk = 1;
+  g.B = s->W16(layer);
+  g.b_sk = in;
+  g.b_sn = 1;
+  g.vec_ok = (out % 8 == 0) && (in % 8 == 0) && aligned16(g.A) && aligned16(g.B);
+  g.k_chunk = ((out + sp - 1) / sp + BK - 1) / BK * BK;
+  const int splits = (out + g.k_chunk - 1) / g.k_chunk;
+  g.ldc = in;
+  g.split_stride = (int64_t)batch * in;
+  g.C32 = s->p<float>(s->o_split);
+  SHIPC((gemm<true, false, EPI_F32>(g, splits, st)));
+  const int64_t n = (int64_t)batch * in;
+  SHIPC((k_split_reduce<<<blocks(n), 256, 0, st>>>(n, splits, g.split_stride, g.C32, dH), hipGetLastError()));
+  return ENS_OK;
+}
+
+// weight gradient dW = dZ^T H (dZ bf16 [batch][out], H bf16 [batch][in]),
+// either stored (grad != null) or applied by Adam
+int32_t backward_weight(sur_net* s, int layer, const __bf16* dZ, const __bf16* Hin, int batch, float* grad,
+                        float lr, float c1, float c2, hipStream_t st) {
+  const int in = s->fan_in[layer], out = s->fan_out[layer];
+  GemmArgs g = base_gemm(out, in, batch);
+  g.A = dZ;
+  g.a_sm = 1;
+  g.a_sk = out;
+  g.B = Hin;
+  g.b_sk = in;
+  g.b_sn = 1;
+  g.vec_ok = (out % 8 == 0) && (in % 8 == 0) && aligned16(g.A) && aligned16(g.B);
+  g.ldc = in;
+  if (grad) {
+    g.C32 = grad;
+    SHIPC((gemm<false, false, EPI_F32>(g, 1, st)));
+  } else {
+    g.W32 = s->W32(layer);
+    g.M1 = s->p<float>(s->o_m1) + s->w_off[layer];
+    g.M2 = s->p<float>(s->o_m2) + s->w_off[layer];
+    g.W16 = s->W16(layer);
+    g.lr = lr;
+    g.b1 = 0.9f;
+    g.b2 = 0.999f;
+    g.eps = 1e-8f;
+    g.c1 = c1;
+    g.c2 = c2;
+    SHIPC((gemm<false, false, EPI_ADAM>(g, 1, st)));
+  }
+  return ENS_OK;
+}
+
+// Full backward pass after a forward pass that left Y in o_y.  grad != null:
+// store the gradient vector (layout of the parameters); else Adam step.
+int32_t backward(sur_net* s, const float* T, int batch, float* grad, float* loss_dev, float lr,
+                 hipStream_t st) {
+  const int L = s->n_hidden;
+  const int64_t ny = (int64_t)batch * s->n_out;
+  const unsigned nb = blocks(ny);
+  float* dY32 = s->p<float>(s->o_dz32);  // FP32 dY reuses the dZ32 buffer (sized for n_out)
+  SHIPC((k_mse<<<nb, 256, 0, st>>>(ny, 1.0f / (float)ny, s->p<float>(s->o_y), T, s->p<__bf16>(s->o_dy16), dY32,
+                                   s->p<double>(s->o_lpart)),
+         hipGetLastError()));
+  SHIPC((k_loss_final<<<1, 64, 0, st>>>((int)nb, s->p<double>(s->o_lpart), 1.0 / (double)ny,
+                                        loss_dev ? loss_dev : s->p<float>(s->o_loss)),
+         hipGetLastError()));
+  const double t = (double)(s->t + 1);
+  const float c1 = (float)(1.0 / (1.0 - std::pow(0.9, t)));
+  const float c2 = (float)(1.0 / (1.0 - std::pow(0.999, t)));
+  const __bf16* dZ = s->p<__bf16>(s->o_dy16);
+  const float* dZf = dY32;
+  for (int l = L; l >= 0; --l) {
+    const int in = s->fan_in[l], out = s->fan_out[l];
+    // bias gradient
+    float* db = grad ? grad + s->b_off[l] : s->p<float>(s->o_db);
+    SHIPC((k_colsum<<<blocks(out), 256, 0, st>>>(batch, out, dZf, db), hipGetLastError()));
+    if (!grad) {
+      float* m1 = s->p<float>(s->o_m1) + s->b_off[l];
+      float* m2 = s->p<float>(s->o_m2) + s->b_off[l];
+      SHIPC((k_adam_vec<<<blocks(out), 256, 0, st>>>(out, db, s->B32(l), m1, m2, lr, 0.9f, 0.999f, 1e-8f, c1, c2),
+             hipGetLastError()));
+    }
+    // data gradient for the layer below (uses the weights before their update)
+    if (l > 0) {
+      float* dH = s->p<float>(s->o_dh);
+      int32_t rc = backward_data(s, l, dZ, batch, dH, st);
+      if (rc != ENS_OK) return rc;
+      const int64_t n = (int64_t)batch * in;
+      // the weight update below still reads dZ of this layer: write the next
+      // dZ into the other half of the buffers
+      rc = backward_weight(s, l, dZ, s->H(l), batch, grad ? grad + s->w_off[l] : nullptr, lr, c1, c2, st);
+      if (rc != ENS_OK) return rc;
+      SHIPC((k_gelu_bwd<<<blocks(n), 256, 0, st>>>(n, dH, s->Z(l - 1), s->p<float>(s->o_dz32),
+                                                   s->p<__bf16>(s->o_dz16)),
+             hipGetLastError()));
+      dZ = s->p<__bf16>(s->o_dz16);
+      dZf = s->p<float>(s->o_dz32);
+    } else {
+      const int32_t rc = backward_weight(s, 0, dZ, s->H(0), batch, grad ? grad + s->w_off[0] : nullptr, lr, c1,
+                                         c2, st);
+      if (rc != ENS_OK) return rc;
+    }
+  }
+  if (!grad) s->t += 1;
+  return ENS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t sur_create(int32_t device, int32_t n_in, int32_t width, int32_t n_hidden, int32_t n_out,
+                   int32_t max_batch, sur_net** out) {
+  if (!out) return ENS_EINVAL;
+  *out = nullptr;
+  if (n_in < 1 || width < 1 || n_hidden < 1 || n_out < 1 || max_batch < 1) return ENS_EINVAL;
+  int nd = 0;
+  if (hipGetDeviceCount(&nd) != hipSuccess || device < 0 || device >= nd) return ENS_EDEVICE;
+  sur_net* s = new (std::nothrow) sur_net();
+  if (!s) return ENS_EINVAL;
+  s->device = device;
+  s->n_in = n_in;
+  s->width = width;
+  s->n_hidden = n_hidden;
+  s->n_out = n_out;
+  s->max_batch = max_batch;
+  size_t off = 0;
+  for (int l = 0; l <= n_hidden; ++l) {
+    const int in = l == 0 ? n_in : width;
+    const int o = l == n_hidden ? n_out : width;
+    s->fan_in.push_back(in);
+    s->fan_out.push_back(o);
+    s->w_off.push_back(off);
+    off += (size_t)in * o;
+    s->b_off.push_back(off);
+    off += o;
+  }
+  s->n_params = off;
+  plan(s);
+  *out = s;
+  return ENS_OK;
+}
+
+int32_t sur_destroy(sur_net* s) {
+  if (!s) return ENS_EINVAL;
+  if (s->bound) {
+    hipSetDevice(s->device);
+    hipDeviceSynchronize();
+  }
+  delete s;
+  return ENS_OK;
+}
+
+const char* sur_last_error(const sur_net* s) { return s ? s->err.c_str() : "null network"; }
+
+int32_t sur_info(sur_net* s, int64_t* n_params, size_t* workspace_bytes) {
+  if (!s) return ENS_EINVAL;
+  if (n_params) *n_params = (int64_t)s->n_params;
+  if (workspace_bytes) *workspace_bytes = s->total;
+  return ENS_OK;
+}
+
+int32_t sur_bind_workspace(sur_net* s, void* dptr, size_t bytes) {
+  if (!s) return ENS_EINVAL;
+  if (!dptr || (reinterpret_cast<uintptr_t>(dptr) & 255) != 0)
+    return s->fail(ENS_EWORKSPACE, "sur_bind_workspace: null or unaligned (256 B) buffer");
+  if (bytes < s->total)
+    return s->fail(ENS_EWORKSPACE, "sur_bind_workspace: need " + std::to_string(s->total) + " bytes");
+  s->ws = static_cast<char*>(dptr);
+  s->ws_bytes = bytes;
+  s->bound = true;
+  s->have_params = false;
+  return ENS_OK;
+}
+
+int32_t sur_set_params(sur_net* s, const float* host) {
+  if (!s || !host) return ENS_EINVAL;
+  if (!s->bound) return s->fail(ENS_EWORKSPACE, "sur_set_params: bind a workspace first");
+  for (size_t i = 0; i < s->n_params; ++i)
+    if (!std::isfinite(host[i])) return s->fail(ENS_EINVAL, "sur_set_params: non-finite parameter");
+  SHIPC(hipSetDevice(s->device));
+  SHIPC(hipMemcpy(s->p<float>(s->o_p32), host, 4 * s->n_params, hipMemcpyHostToDevice));
+  SHIPC(hipMemset(s->p<float>(s->o_m1), 0, 4 * s->n_params));
+  SHIPC(hipMemset(s->p<float>(s->o_m2), 0, 4 * s->n_params));
+  SHIPC((k_to_bf16<<<blocks((int64_t)s->n_params), 256>>>((int64_t)s->n_params, s->p<float>(s->o_p32),
+                                                          s->p<__bf16>(s->o_w16)),
+         hipGetLastError()));
+  SHIPC(hipDeviceSynchronize());
+  s->t = 0;
+  s->have_params = true;
+  return ENS_OK;
+}
+
+int32_t sur_get_params(sur_net* s, float* host) {
+  if (!s || !host) return ENS_EINVAL;
+  if (!s->have_params) return s->fail(ENS_ESTATE, "sur_get_params: no parameters");
+  SHIPC(hipSetDevice(s->device));
+  SHIPC(hipDeviceSynchronize());
+  SHIPC(hipMemcpy(host, s->p<float>(s->o_p32), 4 * s->n_params, hipMemcpyDeviceToHost));
+  return ENS_OK;
+}
+
+int32_t sur_forward(sur_net* s, const float* X, int32_t batch, float* Y, void* stream) {
+  if (!s || !X || !Y) return ENS_EINVAL;
+  if (!s->have_params) return s->fail(ENS_ESTATE, "sur_forward: set the parameters first");
+  if (batch < 1 || batch > s->max_batch) return s->fail(ENS_EINVAL, "sur_forward: batch out of range");
+  SHIPC(hipSetDevice(s->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int32_t rc = forward_hidden(s, X, batch, st);
+  if (rc != ENS_OK) return rc;
+  GemmArgs g = output_gemm(s, batch);
+  g.C32 = Y;
+  SHIPC((gemm<true, true, EPI_BIAS_F32>(g, 1, st)));
+  return ENS_OK;
+}
+
+int32_t sur_gradients(sur_net* s, const float* X, const float* T, int32_t batch, float* grad, float* loss,
+                      void* stream) {
+  if (!s || !X || !T || !grad) return ENS_EINVAL;
+  if (!s->have_params) return s->fail(ENS_ESTATE, "sur_gradients: set the parameters first");
+  if (batch < 1 || batch > s->max_batch) return s->fail(ENS_EINVAL, "sur_gradients: batch out of range");
+  SHIPC(hipSetDevice(s->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int32_t rc = forward_hidden(s, X, batch, st);
+  if (rc != ENS_OK) return rc;
+  GemmArgs g = output_gemm(s, batch);
+  g.C32 = s->p<float>(s->o_y);
+  SHIPC((gemm<true, true, EPI_BIAS_F32>(g, 1, st)));
+  return backward(s, T, batch, grad, loss, 0.f, st);
+}
+
+int32_t sur_train_step(sur_net* s, const float* X, const float* T, int32_t batch, float lr, float* loss,
+                       void* stream) {
+  if (!s || !X || !T) return ENS_EINVAL;
+  if (!s->have_params) return s->fail(ENS_ESTATE, "sur_train_step: set the parameters first");
+  if (batch < 1 || batch > s->max_batch) return s->fail(ENS_EINVAL, "sur_train_step: batch out of range");
+  if (!(lr >= 0.f)) return s->fail(ENS_EINVAL, "sur_train_step: lr must be >= 0");
+  SHIPC(hipSetDevice(s->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int32_t rc = forward_hidden(s, X, batch, st);
+  if (rc != ENS_OK) return rc;
+  GemmArgs g = output_gemm(s, batch);
+  g.C32 = s->p<float>(s->o_y);
+  SHIPC((gemm<true, true, EPI_BIAS_F32>(g, 1, st)));
+  return backward(s, T, batch, nullptr, loss, lr, st);
+}
+
+int32_t sur_moments(sur_net* s, const float* X, int64_t M, double* sum_host, double* sumsq_host,
+                    void* stream) {
+  if (!s || !X || !sum_host || !sumsq_host || M < 1) return ENS_EINVAL;
+  if (!s->have_params) return s->fail(ENS_ESTATE, "sur_moments: set the parameters first");
+  SHIPC(hipSetDevice(s->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  double* S1 = s->p<double>(s->o_s1);
+  double* S2 = s->p<double>(s->o_s2);
+  SHIPC(hipMemsetAsync(S1, 0, 8 * (size_t)s->n_out, st));
+  SHIPC(hipMemsetAsync(S2, 0, 8 * (size_t)s->n_out, st));
+  for (int64_t r0 = 0; r0 < M; r0 += s->max_batch) {
+    const int batch = (int)std::min<int64_t>(s->max_batch, M - r0);
+    int32_t rc = forward_hidden(s, X + r0 * s->n_in, batch, st);
+    if (rc != ENS_OK) return rc;
+    GemmArgs g = output_gemm(s, batch);
+    g.P1 = s->p<float>(s->o_p1);
+    g.P2 = s->p<float>(s->o_p2);
+    SHIPC((gemm<true, true, EPI_MOMENTS>(g, 1, st)));
+    const int rb = (batch + BM - 1) / BM;
+    SHIPC((k_moment_accumulate<<<blocks(s->n_out), 256, 0, st>>>(rb, s->n_out, g.P1, g.P2, S1, S2),
+           hipGetLastError()));
+  }
+  SHIPC(hipStreamSynchronize(st));
+  SHIPC(hipMemcpy(sum_host, S1, 8 * (size_t)s->n_out, hipMemcpyDeviceToHost));
+  SHIPC(hipMemcpy(sumsq_host, S2, 8 * (size_t)s->n_out, hipMemcpyDeviceToHost));
+  return ENS_OK;
+}
+
+int32_t sur_cv_moments(const double* qH, const double* qL, int64_t n, int32_t N, const double* sumL,
+                       const double* sumsqL, int64_t M, double* mean, double* var, double* rho, void* stream) {
+  if (!qH || !qL || !sumL || !sumsqL || !mean || !var || !rho || n < 1 || N < 2 || M < 1) return ENS_EINVAL;
+  k_cv<<<blocks(n), 256, 0, static_cast<hipStream_t>(stream)>>>(n, N, qH, qL, sumL, sumsqL, (double)M, mean,
+                                                                var, rho);
+  return hipGetLastError() == hipSuccess ? ENS_OK : ENS_EDEVICE;
+}
+
+}  // extern "C"

@@ -43,6 +43,36 @@ __device__ __forceinline__ bool wg_coords(const StepArgs& p, int& nb, int& sb) {
   return nb < p.n_nb && sb < p.n_sb;
 }
 
+// Generic view of a global-memory pointer held in an argument struct.
+template <typename T>
+__device__ __forceinline__ T* gen(ENS_GLOBAL T* ptr) {
+  return (T*)ptr;
+}
+
+// Move a wave-uniform value into a scalar register.  Where the compiler
+// already loads it through the scalar unit this folds away; where it had to
+// use a vector load (arrays reached through a device table may alias the
+// kernel's stores, so the scalar cache cannot be used) it frees the VGPRs.
+template <typename T>
+__device__ __forceinline__ T uni(T v) {
+  if constexpr (sizeof(T) == 4) {
+    return __builtin_bit_cast(T, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+  } else if constexpr (sizeof(T) == 8) {
+    const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(u & 0xffffffffu));
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(u >> 32));
+    return __builtin_bit_cast(T, ((unsigned long long)hi << 32) | lo);
+  } else {
+    return v;
+  }
+}
+
+template <bool U, typename T>
+__device__ __forceinline__ T maybe_uni(T v) {
+  if constexpr (U) return uni(v);
+  else return v;
+}
+
 // N consecutive samples per lane: one vector memory access per row.
 template <typename T, int N> struct VecOf;
 template <typename T> struct VecOf<T, 1> { typedef T type; };
@@ -93,14 +123,14 @@ __device__ __forceinline__ AT row6(const AT* __restrict__ k, AT d0, AT d1, AT d2
 }
 
 // R for one node and SPL consecutive samples starting at s0.
-template <typename AT, typename ST, int SPL>
+template <typename AT, typename ST, int SPL, bool UNI>
 __device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_t ld, int s0,
                                              const ST* __restrict__ U, const ST (&ua)[3][SPL],
                                              AT (&r)[3][SPL]) {
-  const int kb = p.adj.ptr[node];
-  const int ke = p.adj.ptr[node + 1];
-  const AT* __restrict__ KB = static_cast<const AT*>(p.adj.k);
-  const AT* __restrict__ EH = static_cast<const AT*>(p.eh);
+  const int kb = maybe_uni<UNI>(gen(p.adj.ptr)[node]);
+  const int ke = maybe_uni<UNI>(gen(p.adj.ptr)[node + 1]);
+  const AT* __restrict__ KB = static_cast<const AT*>(gen(p.adj.k));
+  const AT* __restrict__ EH = static_cast<const AT*>(gen(p.eh));
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -108,9 +138,12 @@ __device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_
   ST ub[3][SPL], uc[3][SPL];
 #pragma unroll 2
   for (int k = kb; k < ke; ++k) {
-    const int64_t e = p.adj.el[k];
-    const int2 bc = p.adj.nb[k];
-    const AT* __restrict__ kk = KB + (int64_t)k * 18;
+    const int64_t e = maybe_uni<UNI>(gen(p.adj.el)[k]);
+    const int2 bc0 = gen(p.adj.nb)[k];
+    const int2 bc = make_int2(maybe_uni<UNI>(bc0.x), maybe_uni<UNI>(bc0.y));
+    AT kk[18];
+#pragma unroll
+    for (int i = 0; i < 18; ++i) kk[i] = maybe_uni<UNI>(KB[(int64_t)k * 18 + i]);
     AT eh[SPL];
     vload<SPL, false>(EH + e * ld + s0, eh);
     // bc.x < 0: this element's first neighbour is the previous one's second
@@ -147,21 +180,23 @@ __device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_
 
 // Shared stiffness: R_i = sum_j K_ij (u_j - u_i) over the assembled
 // off-diagonal 3x3 blocks of row i.
-template <typename AT, typename ST, int SPL>
+template <typename AT, typename ST, int SPL, bool UNI>
 __device__ __forceinline__ void gather_blocks(const StepArgs& p, int node, int64_t ld, int s0,
                                               const ST* __restrict__ U, const ST (&ua)[3][SPL],
                                               AT (&r)[3][SPL]) {
-  const int kb = p.bsr.ptr[node];
-  const int ke = p.bsr.ptr[node + 1];
-  const AT* __restrict__ V = static_cast<const AT*>(p.bsr.val);
+  const int kb = maybe_uni<UNI>(gen(p.bsr.ptr)[node]);
+  const int ke = maybe_uni<UNI>(gen(p.bsr.ptr)[node + 1]);
+  const AT* __restrict__ V = static_cast<const AT*>(gen(p.bsr.val));
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int i = 0; i < SPL; ++i) r[c][i] = AT(0);
 #pragma unroll 2
   for (int k = kb; k < ke; ++k) {
-    const int64_t rj = (int64_t)p.bsr.col[k] * 3;
-    const AT* __restrict__ B = V + (int64_t)k * 9;
+    const int64_t rj = (int64_t)maybe_uni<UNI>(gen(p.bsr.col)[k]) * 3;
+    AT B[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) B[i] = maybe_uni<UNI>(V[(int64_t)k * 9 + i]);
     ST uj[3][SPL];
 #pragma unroll
     for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (rj + c) * ld + s0, uj[c]);
@@ -204,26 +239,27 @@ __device__ __forceinline__ uint64_t spread_bits(uint64_t x) {
 
 // Work of one wave-or-lane-group on one node and SPL samples per lane:
 // stiffness apply, central-difference update, QoI and energy terms.
-// `lane` in [0, LPN); samples sbk*LPN*SPL + lane*SPL + i.
+// `lane` in [0, LPN); samples base + lane*SPL + i (base a multiple of
+// LPN*SPL, and of 64 when LPN = 64).
 template <typename AT, int MODE, int LPN, int SPL, bool QOI, bool ENERGY, bool SHARED>
-__device__ __forceinline__ void step_node(const StepArgs& p, int node, int sbk, int lane,
+__device__ __forceinline__ void step_node(const StepArgs& p, int j, int node, int base, int lane,
                                           double (&e_loc)[SPL]) {
-  constexpr int SB = LPN * SPL;
-  const int s0 = sbk * SB + lane * SPL;
+  const int s0 = base + lane * SPL;
   const int64_t ld = p.ld;
   using ST = typename std::conditional<MODE == kStateF64, double, float>::type;
   const ST* __restrict__ U = nullptr;
-  if constexpr (MODE == kStateF64) U = p.u_cur; else U = p.uh_cur;
+  if constexpr (MODE == kStateF64) U = gen(p.u_cur); else U = gen(p.uh_cur);
   const int64_t row = (int64_t)node * 3;
   ST ua[3][SPL];
 #pragma unroll
   for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (row + c) * ld + s0, ua[c]);
   AT r[3][SPL];
-  if constexpr (SHARED) gather_blocks<AT, ST, SPL>(p, node, ld, s0, U, ua, r);
-  else gather_apply<AT, ST, SPL>(p, node, ld, s0, U, ua, r);
+  constexpr bool UNI = LPN == 64;
+  if constexpr (SHARED) gather_blocks<AT, ST, SPL, UNI>(p, node, ld, s0, U, ua, r);
+  else gather_apply<AT, ST, SPL, UNI>(p, node, ld, s0, U, ua, r);
 
-  const double g = p.gtab[p.j];
-  const unsigned fx = p.fixed[node];
+  const double g = maybe_uni<UNI>(gen(p.gtab)[j]);
+  const unsigned fx = maybe_uni<UNI>((unsigned)gen(p.fixed)[node]);
   const int64_t ms = (int64_t)node * ld + s0;
   double un[3][SPL];
   double uo[3][SPL];  // u_n as the QoI sees it
@@ -234,10 +270,10 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int node, int sbk, 
       for (int i = 0; i < SPL; ++i) uo[c][i] = ua[c][i];
     double minv[SPL];
     if constexpr (std::is_same<AT, double>::value) {
-      vload<SPL, true>(static_cast<const double*>(p.minv) + ms, minv);
+      vload<SPL, true>(static_cast<const double*>(gen(p.minv)) + ms, minv);
     } else {
       float mf[SPL];
-      vload<SPL, true>(static_cast<const float*>(p.minv) + ms, mf);
+      vload<SPL, true>(static_cast<const float*>(gen(p.minv)) + ms, mf);
 #pragma unroll
       for (int i = 0; i < SPL; ++i) minv[i] = (double)mf[i];
     }
@@ -248,8 +284,8 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int node, int sbk, 
     for (int c = 0; c < 3; ++c) {
       const int64_t idx = (row + c) * ld + s0;
       double up[SPL];
-      vload<SPL, true>(p.u_prev + idx, up);
-      const double fc = g * p.F[row + c];
+      vload<SPL, true>(gen(p.u_prev) + idx, up);
+      const double fc = g * maybe_uni<UNI>(gen(p.F)[row + c]);
 #pragma unroll
       for (int i = 0; i < SPL; ++i) {
         const double acc = (dt2 * minv[i]) * (fc - (double)r[c][i]);
@@ -257,7 +293,7 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int node, int sbk, 
         if (fx & (1u << c)) v = 0.0;
         un[c][i] = v;
       }
-      vstore<SPL, true>(p.u_next + idx, un[c]);
+      vstore<SPL, true>(gen(p.u_next) + idx, un[c]);
     }
     if constexpr (ENERGY) {
 #pragma unroll
@@ -272,17 +308,17 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int node, int sbk, 
     }
   } else {
     float minv[SPL];
-    vload<SPL, true>(static_cast<const float*>(p.minv) + ms, minv);
+    vload<SPL, true>(static_cast<const float*>(gen(p.minv)) + ms, minv);
     const float dtf = (float)p.dt;
     const float inv1pa = (float)(1.0 / (1.0 + p.a));
     const float oma = (float)(1.0 - p.a);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int64_t idx = (row + c) * ld + s0;
-      const float fc = (float)(g * p.F[row + c]);
+      const float fc = (float)(g * maybe_uni<UNI>(gen(p.F)[row + c]));
       float vel[SPL], cc[SPL], uh[SPL];
-      vload<SPL, true>(p.v + idx, vel);
-      if constexpr (MODE == kStateF32Kahan) vload<SPL, true>(p.uc + idx, cc);
+      vload<SPL, true>(gen(p.v) + idx, vel);
+      if constexpr (MODE == kStateF32Kahan) vload<SPL, true>(gen(p.uc) + idx, cc);
 #pragma unroll
       for (int i = 0; i < SPL; ++i) {
         if constexpr (MODE == kStateF32Kahan) uo[c][i] = (double)ua[c][i] - (double)cc[i];
@@ -310,22 +346,24 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int node, int sbk, 
                       0.5 * un[c][i] * (double)r[c][i];
         }
       }
-      vstore<SPL, true>(p.uh_next + idx, uh);
-      if constexpr (MODE == kStateF32Kahan) vstore<SPL, true>(p.uc + idx, cc);
-      vstore<SPL, true>(p.v + idx, vel);
+      vstore<SPL, true>(gen(p.uh_next) + idx, uh);
+      if constexpr (MODE == kStateF32Kahan) vstore<SPL, true>(gen(p.uc) + idx, cc);
+      vstore<SPL, true>(gen(p.v) + idx, vel);
     }
   }
   if constexpr (QOI) {
-    const double e0 = p.radial[row + 0], e1 = p.radial[row + 1], e2 = p.radial[row + 2];
+    const double e0 = maybe_uni<UNI>(gen(p.radial)[row + 0]);
+    const double e1 = maybe_uni<UNI>(gen(p.radial)[row + 1]);
+    const double e2 = maybe_uni<UNI>(gen(p.radial)[row + 2]);
     if constexpr (LPN == 64) {
       // q is only touched where the radial displacement turns: a rise that
       // continues from the running peak keeps the at-max bit, a fall from it
       // writes the peak, a rise below it compares with the stored peak.
       constexpr int LPW = 64 / SPL;  // lanes per mask word
-      uint64_t* __restrict__ mw = p.qmask + (int64_t)node * p.qwords + sbk * SPL;
+      uint64_t* __restrict__ mw = gen(p.qmask) + (int64_t)node * p.qwords + base / 64;
       uint64_t words[SPL];
 #pragma unroll
-      for (int w = 0; w < SPL; ++w) words[w] = mw[w];
+      for (int w = 0; w < SPL; ++w) words[w] = uni(mw[w]);
       uint64_t mine = words[0];
 #pragma unroll
       for (int w = 1; w < SPL; ++w)
@@ -339,9 +377,9 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int node, int sbk, 
         bool nbit = false;
         if (at) {
           nbit = rn >= rc;
-          if (!nbit) __builtin_nontemporal_store(rc, p.q + ms + i);
+          if (!nbit) __builtin_nontemporal_store(rc, gen(p.q) + ms + i);
         } else if (rn > rc) {
-          nbit = rn > __builtin_nontemporal_load(p.q + ms + i);
+          nbit = rn > __builtin_nontemporal_load(gen(p.q) + ms + i);
         }
         ballots[i] = __ballot(nbit);
       }
@@ -354,7 +392,7 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int node, int sbk, 
       }
     } else {
       double qo[SPL];
-      vload<SPL, true>(p.q + ms, qo);
+      vload<SPL, true>(gen(p.q) + ms, qo);
       bool upd = false;
 #pragma unroll
       for (int i = 0; i < SPL; ++i) {
@@ -364,7 +402,7 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int node, int sbk, 
           upd = true;
         }
       }
-      if (upd) vstore<SPL, true>(p.q + ms, qo);
+      if (upd) vstore<SPL, true>(gen(p.q) + ms, qo);
     }
   }
 }
@@ -384,7 +422,8 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
   double e_loc[SPL];
 #pragma unroll
   for (int i = 0; i < SPL; ++i) e_loc[i] = 0.0;
-  if (node < p.n_nodes) step_node<AT, MODE, LPN, SPL, QOI, ENERGY, SHARED>(p, node, sbk, lane, e_loc);
+  if (node < p.n_nodes)
+    step_node<AT, MODE, LPN, SPL, QOI, ENERGY, SHARED>(p, p.j, node, sbk * LPN * SPL, lane, e_loc);
   if constexpr (ENERGY) {
     __shared__ double red[kBlock * SPL];
 #pragma unroll
@@ -396,33 +435,44 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
       for (int i = 0; i < SPL; ++i) {
         double sum = 0.0;
         for (int n = 0; n < NPB; ++n) sum += red[(n * LPN + lane) * SPL + i];
-        p.energy_part[(int64_t)nb * p.ld + s0 + i] = sum;
+        gen(p.energy_part)[(int64_t)nb * p.ld + s0 + i] = sum;
       }
     }
   }
 }
 
-// Batched step: one launch steps every mesh of a batch.  Persistent
-// workgroups walk a static list of tiles (mesh, first node, node count,
-// sample block); each wave takes every 4th node of the tile with 64 lanes x
-// SPL samples.  Per-mesh arguments come from a device table indexed by the
-// mesh and by the parity of the step (which state buffer is current).
+// Batched step: one launch steps every mesh of a batch (per lane width:
+// tiles with 2 samples per lane and, where a padded width leaves a last
+// block of 64, tiles with 1, each class one launch).  Persistent
+// workgroups walk a list of tiles (mesh, first node, node count, first
+// sample) ordered mesh by mesh and node-fastest; each XCD takes a
+// contiguous eighth of the list and its workgroups sweep it in order, so
+// tiles that share neighbours run close in time on one L2.  Each wave takes
+// every 4th node of a tile with 64 lanes x SPL samples.
+// Per-mesh arguments come from a device table indexed by mesh and by the
+// parity of the step (which state buffer is current).
 template <typename AT, int MODE, int SPL, bool QOI>
-__global__ __launch_bounds__(kBlock) void k_batch_step(const BatchTile* __restrict__ tiles,
-                                                       int32_t n_tiles,
-                                                       const StepArgs* __restrict__ desc,
-                                                       int32_t j) {
+__global__ __launch_bounds__(kBlock) void k_batch_step(const BatchTile* __restrict__ tiles, int32_t n_tiles,
+                                                       const StepArgs* __restrict__ desc, int32_t j) {
   const int wave = threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
+  const int per = gridDim.x >> 3;
+  const int x = blockIdx.x & 7, rank = blockIdx.x >> 3;
+  const int beg = (int)(((int64_t)n_tiles * x) >> 3);
+  const int end = (int)(((int64_t)n_tiles * (x + 1)) >> 3);
   double e_loc[SPL];
-  for (int t = blockIdx.x; t < n_tiles; t += gridDim.x) {
-    const BatchTile tile = tiles[t];
-    const StepArgs& p0 = desc[2 * tile.mesh + (j & 1)];
-    StepArgs p = p0;
-    p.j = j;
-    for (int n = wave; n < tile.count; n += kBlock / 64) {
-      const int node = __builtin_amdgcn_readfirstlane(tile.node0 + n);
-      step_node<AT, MODE, 64, SPL, QOI, false, false>(p, node, tile.sblock, lane, e_loc);
+#pragma nounroll
+  for (int t = beg + rank; t < end; t += per) {
+    // tile and mesh arguments are uniform: keep them in scalar registers
+    const int mesh = __builtin_amdgcn_readfirstlane(tiles[t].mesh);
+    const int node0 = __builtin_amdgcn_readfirstlane(tiles[t].node0);
+    const int count = __builtin_amdgcn_readfirstlane(tiles[t].count);
+    const int sample0 = __builtin_amdgcn_readfirstlane(tiles[t].sample0);
+    const StepArgs& p = desc[2 * mesh + (j & 1)];
+#pragma nounroll
+    for (int n = wave; n < count; n += kBlock / 64) {
+      const int node = __builtin_amdgcn_readfirstlane(node0 + n);
+      step_node<AT, MODE, 64, SPL, QOI, false, false>(p, j, node, sample0, lane, e_loc);
     }
   }
 }
@@ -444,8 +494,8 @@ __global__ __launch_bounds__(kBlock) void k_apply(StepArgs p, const AT* __restri
 #pragma unroll
   for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (row + c) * ld + s0, ua[c]);
   AT r[3][SPL];
-  if constexpr (SHARED) gather_blocks<AT, AT, SPL>(p, node, ld, s0, U, ua, r);
-  else gather_apply<AT, AT, SPL>(p, node, ld, s0, U, ua, r);
+  if constexpr (SHARED) gather_blocks<AT, AT, SPL, (LPN == 64)>(p, node, ld, s0, U, ua, r);
+  else gather_apply<AT, AT, SPL, (LPN == 64)>(p, node, ld, s0, U, ua, r);
 #pragma unroll
   for (int c = 0; c < 3; ++c) vstore<SPL, true>(R + (row + c) * ld + s0, r[c]);
 }
@@ -720,31 +770,28 @@ hipError_t launch_apply(const StepArgs& a, bool f32, int sample_block, bool shar
              : dispatch_apply<double, false>(a, sample_block, U, R, st);
 }
 
-hipError_t launch_batch_step(const BatchTile* tiles, int32_t n_tiles, const StepArgs* desc, int32_t j,
-                             bool apply_f32, int mode, int spl, bool qoi, int grid, hipStream_t st) {
+hipError_t launch_batch_step(const BatchTile* tiles, int32_t n_tiles, int spl, const StepArgs* desc, int32_t j,
+                             bool apply_f32, int mode, bool qoi, int grid, hipStream_t st) {
   if (n_tiles == 0) return hipSuccess;
-#define ENSFEM_BATCH(AT, MODE, SPL)                                                                    \
-  do {                                                                                                 \
-    if (qoi) k_batch_step<AT, MODE, SPL, true><<<grid, kBlock, 0, st>>>(tiles, n_tiles, desc, j);      \
-    else k_batch_step<AT, MODE, SPL, false><<<grid, kBlock, 0, st>>>(tiles, n_tiles, desc, j);         \
-    return hipGetLastError();                                                                          \
+  if (grid % 8 != 0 || (spl != 1 && spl != 2)) return hipErrorInvalidValue;
+#define ENSFEM_BATCH(AT, MODE)                                                                           \
+  do {                                                                                                   \
+    if (spl == 2) {                                                                                      \
+      if (qoi) k_batch_step<AT, MODE, 2, true><<<grid, kBlock, 0, st>>>(tiles, n_tiles, desc, j);        \
+      else k_batch_step<AT, MODE, 2, false><<<grid, kBlock, 0, st>>>(tiles, n_tiles, desc, j);           \
+    } else {                                                                                             \
+      if (qoi) k_batch_step<AT, MODE, 1, true><<<grid, kBlock, 0, st>>>(tiles, n_tiles, desc, j);        \
+      else k_batch_step<AT, MODE, 1, false><<<grid, kBlock, 0, st>>>(tiles, n_tiles, desc, j);           \
+    }                                                                                                    \
+    return hipGetLastError();                                                                            \
   } while (0)
   if (!apply_f32) {
     if (mode != kStateF64) return hipErrorInvalidValue;
-    if (spl == 1) ENSFEM_BATCH(double, kStateF64, 1);
-    if (spl == 2) ENSFEM_BATCH(double, kStateF64, 2);
-    return hipErrorInvalidValue;
+    ENSFEM_BATCH(double, kStateF64);
   }
-  if (mode == kStateF64) {
-    if (spl == 1) ENSFEM_BATCH(float, kStateF64, 1);
-    if (spl == 2) ENSFEM_BATCH(float, kStateF64, 2);
-  } else if (mode == kStateF32Kahan) {
-    if (spl == 1) ENSFEM_BATCH(float, kStateF32Kahan, 1);
-    if (spl == 2) ENSFEM_BATCH(float, kStateF32Kahan, 2);
-  } else if (mode == kStateF32) {
-    if (spl == 1) ENSFEM_BATCH(float, kStateF32, 1);
-    if (spl == 2) ENSFEM_BATCH(float, kStateF32, 2);
-  }
+  if (mode == kStateF64) ENSFEM_BATCH(float, kStateF64);
+  if (mode == kStateF32Kahan) ENSFEM_BATCH(float, kStateF32Kahan);
+  if (mode == kStateF32) ENSFEM_BATCH(float, kStateF32);
 #undef ENSFEM_BATCH
   return hipErrorInvalidValue;
 }

@@ -18,6 +18,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libensfem.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "ensfem.h")
+HEADERS = [HEADER, os.path.join(os.path.dirname(HERE), "include", "ensfem_surrogate.h")]
 
 ENS_OK, ENS_EINVAL, ENS_ESTATE, ENS_EWORKSPACE, ENS_EDEVICE, ENS_EUNSTABLE, ENS_ENONFINITE, \
     ENS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
@@ -93,14 +94,28 @@ _SIGS = {
     "ens_batch_info": (_I32, [_P, ctypes.POINTER(BatchInfo)]),
     "ens_batch_step": (_I32, [_P, _I64, _P]),
     "ens_batch_autotune": (_I32, [_P, _I32]),
+    "sur_create": (_I32, [_I32, _I32, _I32, _I32, _I32, _I32, ctypes.POINTER(_P)]),
+    "sur_destroy": (_I32, [_P]),
+    "sur_last_error": (ctypes.c_char_p, [_P]),
+    "sur_info": (_I32, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_SZ)]),
+    "sur_bind_workspace": (_I32, [_P, _P, _SZ]),
+    "sur_set_params": (_I32, [_P, _P]),
+    "sur_get_params": (_I32, [_P, _P]),
+    "sur_forward": (_I32, [_P, _P, _I32, _P, _P]),
+    "sur_gradients": (_I32, [_P, _P, _P, _I32, _P, _P, _P]),
+    "sur_train_step": (_I32, [_P, _P, _P, _I32, ctypes.c_float, _P, _P]),
+    "sur_moments": (_I32, [_P, _P, _I64, _P, _P, _P]),
+    "sur_cv_moments": (_I32, [_P, _P, _I64, _I32, _P, _P, _I64, _P, _P, _P, _P]),
 }
 
 
 def header_functions() -> list:
-    """Names of the functions include/ensfem.h declares."""
-    txt = open(HEADER).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(ens_[a-z_]+)\s*\(", txt)) - {"ens_ctx"})
+    """Names of the functions include/*.h declare."""
+    names = set()
+    for h in HEADERS:
+        txt = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b((?:ens|sur)_[a-z_]+)\s*\(", txt))
+    return sorted(names)
 
 
 def load_library(path: str = LIB_PATH):
@@ -319,6 +334,118 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def flatten_params(params) -> np.ndarray:
+    """[(W [out, in], b [out]), ...] -> the FP32 parameter vector layout."""
+    return np.concatenate([np.concatenate([np.asarray(W, np.float32).ravel(), np.asarray(b, np.float32)])
+                           for W, b in params])
+
+
+def unflatten_params(vec: np.ndarray, sizes) -> list:
+    out, o = [], 0
+    for i, n in zip(sizes[:-1], sizes[1:]):
+        W = vec[o:o + n * i].reshape(n, i)
+        o += n * i
+        b = vec[o:o + n]
+        o += n
+        out.append((W, b))
+    return out
+
+
+class Surrogate:
+    """The learned form's network (sur_* functions), device buffers via torch."""
+
+    def __init__(self, n_in: int, width: int, n_hidden: int, n_out: int, max_batch: int = 256,
+                 device: int = 0):
+        import torch
+        self._lib = load_library()
+        h = _P()
+        rc = self._lib.sur_create(device, n_in, width, n_hidden, n_out, max_batch, ctypes.byref(h))
+        if rc != ENS_OK:
+            raise EnsfemError(rc, "sur_create failed")
+        self._h = h
+        self.sizes = [n_in] + [width] * n_hidden + [n_out]
+        self.n_in, self.n_out, self.max_batch, self.device = n_in, n_out, max_batch, device
+        npar, ws = _I64(), _SZ()
+        self._check(self._lib.sur_info(h, ctypes.byref(npar), ctypes.byref(ws)))
+        self.n_params = npar.value
+        self._ws = torch.empty(ws.value, dtype=torch.uint8, device=f"cuda:{device}")
+        self._check(self._lib.sur_bind_workspace(h, self._ws.data_ptr(), self._ws.numel()))
+        self._loss = torch.zeros(1, dtype=torch.float32, device=f"cuda:{device}")
+
+    def _check(self, rc: int):
+        if rc != ENS_OK:
+            msg = self._lib.sur_last_error(self._h)
+            raise EnsfemError(rc, msg.decode() if msg else "")
+
+    def set_params(self, vec):
+        v = np.ascontiguousarray(vec, dtype=np.float32)
+        assert v.size == self.n_params
+        self._check(self._lib.sur_set_params(self._h, _ptr(v)))
+
+    def get_params(self) -> np.ndarray:
+        v = np.empty(self.n_params, np.float32)
+        self._check(self._lib.sur_get_params(self._h, _ptr(v)))
+        return v
+
+    def forward(self, X, out=None, stream=None):
+        import torch
+        X = X.contiguous()
+        Y = out if out is not None else torch.empty((X.shape[0], self.n_out), dtype=torch.float32, device=X.device)
+        self._check(self._lib.sur_forward(self._h, X.data_ptr(), X.shape[0], Y.data_ptr(), _stream_handle(stream)))
+        return Y
+
+    def gradients(self, X, T, stream=None):
+        import torch
+        g = torch.empty(self.n_params, dtype=torch.float32, device=X.device)
+        self._check(self._lib.sur_gradients(self._h, X.contiguous().data_ptr(), T.contiguous().data_ptr(),
+                                            X.shape[0], g.data_ptr(), self._loss.data_ptr(), _stream_handle(stream)))
+        return g, self._loss
+
+    def train_step(self, X, T, lr: float, stream=None):
+        """One Adam step; returns the device loss scalar (before the step)."""
+        self._check(self._lib.sur_train_step(self._h, X.data_ptr(), T.data_ptr(), X.shape[0], float(lr),
+                                             self._loss.data_ptr(), _stream_handle(stream)))
+        return self._loss
+
+    def moments(self, X, stream=None):
+        s1 = np.empty(self.n_out)
+        s2 = np.empty(self.n_out)
+        X = X.contiguous()
+        self._check(self._lib.sur_moments(self._h, X.data_ptr(), X.shape[0], _ptr(s1), _ptr(s2),
+                                          _stream_handle(stream)))
+        return s1, s2
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.sur_destroy(self._h)
+            self._h = None
+        self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def cv_moments(qH, qL, sumL, sumsqL, M: int, device: int = 0):
+    """Control-variate mean, variance and correlation per node (sur_cv_moments)."""
+    import torch
+    lib = load_library()
+    dev = f"cuda:{device}"
+    t = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device=dev)
+    H, L, s1, s2 = t(qH), t(qL), t(sumL), t(sumsqL)
+    n, N = H.shape
+    mean = torch.empty(n, dtype=torch.float64, device=dev)
+    var = torch.empty_like(mean)
+    rho = torch.empty_like(mean)
+    rc = lib.sur_cv_moments(H.data_ptr(), L.data_ptr(), n, N, s1.data_ptr(), s2.data_ptr(), int(M),
+                            mean.data_ptr(), var.data_ptr(), rho.data_ptr(), _stream_handle(None))
+    if rc != ENS_OK:
+        raise EnsfemError(rc, "sur_cv_moments failed")
+    return mean.cpu().numpy(), var.cpu().numpy(), rho.cpu().numpy()
 
 
 def setup_case(mesh, eh, h, F, nu=0.49, shear_k=5.0 / 6.0, rho=1.0, alpha=50.0,
