@@ -290,3 +290,84 @@ CONFIGS = {
     "c4_batch": dict(count=16, seed=4, p0=1.33e5, ramp="step", steps=10000, nu=0.49,
                      shear_k=5.0 / 6.0, rho=1.0, alpha=50.0, safety=0.9, field="circulant"),
 }
+
+
+# ---------------------------------------------------------------------------
+# Karhunen-Loeve expansion of the nodal Matern field on a cylinder lattice
+# ---------------------------------------------------------------------------
+
+def cylinder_kl_basis(mesh: Mesh, n_modes: int, sigma: float, rho: float, nu: float = 1.0,
+                      radius: Optional[float] = None):
+    """Leading eigenpairs of the nodal covariance (Matern of the chord
+    distance, as in matern_nodal_lattice) on the periodic-theta lattice.
+
+    The covariance is block-circulant in theta, so it splits exactly per
+    azimuthal wave number m into symmetric Toeplitz blocks along the axis,
+    T_m(dz) = sum_k c(theta_k, dz) cos(2 pi m k / n_theta); their
+    eigenvectors v give nodal modes w_m(theta_i) v(z_j) with w_0 = n^-1/2,
+    cos / sin pairs sqrt(2/n) cos(m theta), sqrt(2/n) sin(m theta) for
+    0 < m < n/2.  Returns (lam [n_modes] descending, phi [n_nodes, n_modes]
+    orthonormal over the nodes, captured fraction of the total variance)."""
+    from scipy import linalg
+
+    nt, nz = mesh.n_theta, mesh.n_z
+    R = float(np.mean(np.linalg.norm(mesh.xyz[:nt, :2], axis=1))) if radius is None else float(radius)
+    dz = mesh.length / (nz - 1)
+    kappa = math.sqrt(8.0 * nu) / rho
+    th = 2.0 * np.pi * np.arange(nt) / nt
+    chord2 = 2.0 * R * R * (1.0 - np.cos(th))
+    lag = np.arange(nz) * dz
+    c = _matern(np.sqrt(chord2[None, :] + lag[:, None] ** 2), sigma, nu, kappa)   # [nz, nt]
+    spec = np.fft.fft(c, axis=1).real                                              # T_m(dz) per m
+    cands = []  # (lam, m, kind, v)
+    kth = None
+    for m in range(nt // 2 + 1):
+        col = spec[:, m]
+        if kth is not None and col[0] * nz < kth * 1e-3:
+            break
+        w, V = linalg.eigh(linalg.toeplitz(col))
+        order = np.argsort(w)[::-1][:n_modes]
+        kinds = ("c",) if (m == 0 or 2 * m == nt) else ("c", "s")
+        for idx in order:
+            for kd in kinds:
+                cands.append((float(w[idx]), m, kd, V[:, idx]))
+        cands.sort(key=lambda t: -t[0])
+        cands = cands[:n_modes]
+        if len(cands) == n_modes:
+            kth = cands[-1][0]
+            if w.max() < kth:
+                break
+    lam = np.array([t[0] for t in cands])
+    phi = np.empty((nt * nz, len(cands)))
+    ii = np.arange(nt)
+    for k, (_, m, kd, v) in enumerate(cands):
+        if m == 0:
+            w_t = np.full(nt, 1.0 / math.sqrt(nt))
+        elif 2 * m == nt:
+            w_t = np.cos(np.pi * ii) / math.sqrt(nt)
+        elif kd == "c":
+            w_t = math.sqrt(2.0 / nt) * np.cos(2.0 * np.pi * m * ii / nt)
+        else:
+            w_t = math.sqrt(2.0 / nt) * np.sin(2.0 * np.pi * m * ii / nt)
+        phi[:, k] = (v[:, None] * w_t[None, :]).reshape(-1)
+    captured = float(lam.sum() / (nt * nz * sigma * sigma))
+    return lam, phi, captured
+
+
+def kl_fields(mesh: Mesh, lam: np.ndarray, phi: np.ndarray, xi_E: np.ndarray, xi_h: np.ndarray,
+              E_mean: float = 7.0e6, h_mean: float = 0.1):
+    """(E h) and h [n_el, S] from KL coefficients xi_E, xi_h [S, n_modes]:
+    log-fields phi (sqrt(lam) xi) at the nodes, interpolated to centroids."""
+    s = np.sqrt(lam)[None, :]
+    gE = centroid_average(mesh, phi @ (s * xi_E).T)
+    gh = centroid_average(mesh, phi @ (s * xi_h).T)
+    E = np.exp(math.log(E_mean) + gE)
+    h = np.exp(math.log(h_mean) + gh)
+    return np.ascontiguousarray(E * h), np.ascontiguousarray(h)
+
+
+CONFIGS["c5_learned"] = dict(R=1.0, L=10.0, n_theta=400, n_z=500, n_modes=64, p0=1.33e5, ramp="sine_pulse",
+                             T_ramp=0.02, period=1.0, pulse_amp=0.3, window=0.03, nu=0.49, shear_k=5.0 / 6.0,
+                             rho=1.0, alpha=50.0, safety=0.9, width=1024, n_hidden=3, n_train=4096,
+                             n_hf=256, n_lf=65536, n_ref=4096, epochs=60, batch=256, lr=1e-3,
+                             seeds=dict(train=5, hf=6, lf=7, ref=8, init=9))

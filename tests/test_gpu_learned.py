@@ -1,0 +1,75 @@
+"""Learned form end to end on a small cylinder: KL inputs, solver-generated
+training data, GPU training, control variate against a large plain
+reference, the gain over the plain estimator, and the fallback."""
+import numpy as np
+import pytest
+
+from paper_2101_09059_amd import inputs, learned
+from tests._cases import say
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+CFG = dict(p0=1.33e5, T_ramp=0.02, period=1.0, pulse_amp=0.3, window=0.03, nu=0.49, shear_k=5.0 / 6.0,
+           rho=1.0, alpha=50.0, safety=0.9)
+N_MODES = 8
+
+
+@pytest.fixture(scope="module")
+def setup():
+    mesh = inputs.cylinder(1.0, 10.0, 24, 14)
+    prob = learned.Problem(mesh, CFG, N_MODES)
+    say(f"case: learned form, {mesh.n_nodes} nodes, KL captured {prob.captured:.3f}")
+    Xtr = learned.draw_xi(5, 1024, N_MODES)
+    Qtr = np.concatenate([prob.solve(Xtr[i:i + 256]) for i in range(0, 1024, 256)], axis=1).T
+    net = learned.Network(2 * N_MODES, 128, 3, mesh.n_nodes, seed=9, max_batch=256)
+    rmse, hist = net.fit(Xtr, Qtr, epochs=150, batch=128, lr=2e-3, seed=10)
+    say(f"  held-out rel RMSE {rmse:.4f}, loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    Xh = learned.draw_xi(6, 64, N_MODES)
+    qH, (pm, pv) = prob.solve(Xh, return_moments=True)
+    Xl = learned.draw_xi(7, 16384, N_MODES)
+    Xr = learned.draw_xi(8, 4096, N_MODES)
+    qR = np.concatenate([prob.solve(Xr[i:i + 256]) for i in range(0, 4096, 256)], axis=1)
+    yield dict(mesh=mesh, prob=prob, net=net, rmse=rmse, Xh=Xh, qH=qH, pm=pm, pv=pv, Xl=Xl, qR=qR)
+    net.close()
+
+
+def test_control_variate_matches_reference_and_gains(setup):
+    s = setup
+    net, qH = s["net"], s["qH"]
+    assert s["rmse"] < 0.05
+    qL = net.predict(s["Xh"]).T
+    sumL, sumsqL = net.moment_sums(s["Xl"])
+    M, N = s["Xl"].shape[0], qH.shape[1]
+    est = learned.estimate(qH, s["pm"], s["pv"], qL, sumL, sumsqL, M, s["rmse"])
+    say(f"  median rho {est['rho_median']:.4f}, used CV {est['used_cv']}")
+    assert est["used_cv"]
+    qR = s["qR"]
+    act = qR.var(axis=1) > 0
+    ref_m, ref_v = qR.mean(axis=1), qR.var(axis=1, ddof=1)
+    Nr = qR.shape[1]
+    se_m = np.linalg.norm(np.sqrt(ref_v[act] / Nr)) / np.linalg.norm(ref_m[act])
+    e_cv = np.linalg.norm(est["mean"][act] - ref_m[act]) / np.linalg.norm(ref_m[act])
+    e_plain = np.linalg.norm(s["pm"][act] - ref_m[act]) / np.linalg.norm(ref_m[act])
+    e_var = np.linalg.norm(est["var"][act] - ref_v[act]) / np.linalg.norm(ref_v[act])
+    say(f"  mean rel err CV {e_cv:.2e} plain(N={N}) {e_plain:.2e} ref SE {se_m:.2e}; var rel err {e_var:.2e}")
+    assert e_cv < max(0.01, 3 * se_m)
+    assert e_var < 0.05
+    # gain: variance ratio of the CV mean to the plain N-sample mean
+    ratio = 1.0 - est["rho"][act] ** 2 * M / (M + N)
+    gain = 1.0 / np.median(ratio)
+    say(f"  predicted variance reduction x{gain:.1f}; equivalent plain samples {N * gain:.0f}")
+    assert gain > 4.0
+    assert e_cv < e_plain
+
+
+def test_corrupted_network_falls_back_to_plain_statistics(setup):
+    s = setup
+    bad = learned.Network(2 * N_MODES, 128, 3, s["mesh"].n_nodes, seed=123, max_batch=256)
+    bad.mu, bad.sd = s["net"].mu, s["net"].sd
+    qL = bad.predict(s["Xh"]).T
+    sumL, sumsqL = bad.moment_sums(s["Xl"])
+    est = learned.estimate(s["qH"], s["pm"], s["pv"], qL, sumL, sumsqL, s["Xl"].shape[0], 0.5)
+    assert not est["used_cv"]
+    assert np.array_equal(est["mean"], s["pm"]) and np.array_equal(est["var"], s["pv"])
+    bad.close()
