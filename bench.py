@@ -176,6 +176,82 @@ def run_batch_config(args, torch):
     print(json.dumps(out), flush=True)
 
 
+def run_learned_config(args, torch):
+    """Learned form at full size: 200k-node cylinder, 64 + 64 KL inputs,
+    MLP 128 -> 3 x 1024 (GELU) -> 200,000, trained on 4,096 solver samples;
+    control variate from 256 plain samples and 65,536 network draws, judged
+    against a plain reference of 4,096 fresh samples."""
+    from paper_2101_09059_amd import inputs, learned
+    c = inputs.CONFIGS["c5_learned"]
+    sd = c["seeds"]
+    mesh = inputs.cylinder(c["R"], c["L"], c["n_theta"], c["n_z"])
+    prob = learned.Problem(mesh, c, c["n_modes"])
+    log(f"KL basis: {c['n_modes']} modes per field capture {prob.captured:.3f} of the variance")
+    S = 256
+
+    def solve_many(seed, n):
+        X = learned.draw_xi(seed, n, c["n_modes"])
+        qs = []
+        for i in range(0, n, S):
+            qs.append(prob.solve(X[i:i + S]))
+            log(f"  solved {i + S}/{n} (seed {seed}), solver time {prob.solve_seconds:.0f} s")
+        return X, np.concatenate(qs, axis=1)
+
+    t_data0 = prob.solve_seconds
+    Xtr, Qtr = solve_many(sd["train"], c["n_train"])
+    t_data = prob.solve_seconds - t_data0
+    net = learned.Network(2 * c["n_modes"], c["width"], c["n_hidden"], mesh.n_nodes, seed=sd["init"], max_batch=256)
+    rmse, hist = net.fit(Xtr, Qtr.T, epochs=c["epochs"], batch=c["batch"], lr=c["lr"], seed=sd["init"] + 1)
+    log(f"trained in {net.train_seconds:.1f} s: held-out rel RMSE {rmse:.4f}, loss {hist[0]:.3e} -> {hist[-1]:.3e}")
+    del Qtr
+    Xh = learned.draw_xi(sd["hf"], c["n_hf"], c["n_modes"])
+    t0 = prob.solve_seconds
+    qH, (pm, pv) = prob.solve(Xh, return_moments=True)
+    t_hf = prob.solve_seconds - t0
+    qL = net.predict(Xh).T
+    Xl = learned.draw_xi(sd["lf"], c["n_lf"], c["n_modes"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sumL, sumsqL = net.moment_sums(Xl)
+    t_lf = time.perf_counter() - t0
+    est = learned.estimate(qH, pm, pv, qL, sumL, sumsqL, c["n_lf"], rmse)
+    log(f"median rho {est['rho_median']:.4f}, control variate used: {est['used_cv']}")
+    _, qR = solve_many(sd["ref"], c["n_ref"])
+    act = qR.var(axis=1) > 0
+    ref_m, ref_v = qR.mean(axis=1), qR.var(axis=1, ddof=1)
+    Nr = qR.shape[1]
+    rel = lambda a, b: float(np.linalg.norm(a[act] - b[act]) / np.linalg.norm(b[act]))
+    se_mean = float(np.linalg.norm(np.sqrt(ref_v[act] / Nr)) / np.linalg.norm(ref_m[act]))
+    se_var = float(np.sqrt(2.0 / (Nr - 1)))
+    N, M = c["n_hf"], c["n_lf"]
+    ratio = 1.0 - est["rho"][act] ** 2 * M / (M + N)
+    n_eq = N / float(np.median(ratio))
+    t_per_sample = t_hf / N
+    t_plain_eq = n_eq * t_per_sample
+    t_cv = t_hf + t_lf + net.train_seconds
+    out = {
+        "metric": "surrogate-CV QoI rel.err and speedup", "value": t_plain_eq / t_cv,
+        "unit": "speedup over the plain ensemble at equal variance (training data excluded)",
+        "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "bf16 mfma / fp32 accumulate",
+        "config": {"workload": "200k-node clamped cylinder, pulsatile pressure (ramp 0.02 s, window 0.03 s), "
+                               "64+64 KL inputs, MLP 3x1024 GELU -> 200,000, 4,096 training solves, "
+                               "256 high-fidelity + 65,536 low-fidelity, plain reference 4,096"},
+        "mean_rel_err_vs_reference": rel(est["mean"], ref_m),
+        "var_rel_err_vs_reference": rel(est["var"], ref_v),
+        "plain_256_mean_rel_err": rel(pm, ref_m), "plain_256_var_rel_err": rel(pv, ref_v),
+        "reference_se_mean": se_mean, "reference_se_var": se_var,
+        "used_control_variate": est["used_cv"], "rho_median": est["rho_median"],
+        "heldout_rel_rmse": rmse, "kl_captured_variance": prob.captured,
+        "equivalent_plain_samples": n_eq,
+        "speedup_including_training_data": t_plain_eq / (t_cv + t_data),
+        "seconds": {"training_data": t_data, "training": net.train_seconds, "high_fidelity_256": t_hf,
+                    "network_65536_draws": t_lf, "plain_equivalent": t_plain_eq},
+        "n_params": net.net.n_params,
+    }
+    net.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -189,8 +265,9 @@ def main():
                     help="skip the shared-stiffness (block-row product) timing")
     ap.add_argument("--sample-block", type=int, default=0, help="0 = library default")
     ap.add_argument("--sb-inner", action="store_true")
-    ap.add_argument("--config", choices=["c2_cylinder", "c4_batch"], default="c2_cylinder",
-                    help="c2_cylinder: the headline single-mesh workload; c4_batch: the batching form")
+    ap.add_argument("--config", choices=["c2_cylinder", "c4_batch", "c5_learned"], default="c2_cylinder",
+                    help="c2_cylinder: the headline single-mesh workload; c4_batch: the batching form; "
+                         "c5_learned: the learned form (about 10 GPU-minutes)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 10 times (counter calibration)")
     args = ap.parse_args()
@@ -218,6 +295,9 @@ def main():
 
     if args.config == "c4_batch":
         run_batch_config(args, torch)
+        return
+    if args.config == "c5_learned":
+        run_learned_config(args, torch)
         return
 
     from paper_2101_09059_amd import ensfem, inputs

@@ -436,7 +436,7 @@ int32_t ens_create(int32_t device, ens_ctx** out) {
 
 int32_t ens_destroy(ens_ctx* ctx) {
   if (!ctx) return ENS_EINVAL;
-  if (ctx->bound) hipDeviceSynchronize();
+  if (ctx->bound) (void)hipDeviceSynchronize();  // teardown: nothing to report
   delete ctx;
   return ENS_OK;
 }
@@ -1121,8 +1121,8 @@ namespace {
   } while (0)
 
 void drop_graph(ens_batch* b) {
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->graph) hipGraphDestroy(b->graph);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
 }
@@ -1280,14 +1280,15 @@ int32_t ens_batch_create(ens_ctx** ctxs, int32_t n, ens_batch** out) {
 
 int32_t ens_batch_destroy(ens_batch* b) {
   if (!b) return ENS_EINVAL;
-  hipSetDevice(b->device);
-  hipDeviceSynchronize();
+  // teardown: errors here have no caller to go to
+  (void)hipSetDevice(b->device);
+  (void)hipDeviceSynchronize();
   drop_graph(b);
-  if (b->d_tiles) hipFree(b->d_tiles);
-  if (b->d_desc) hipFree(b->d_desc);
-  if (b->ev_in) hipEventDestroy(b->ev_in);
-  if (b->ev_out) hipEventDestroy(b->ev_out);
-  if (b->st) hipStreamDestroy(b->st);
+  if (b->d_tiles) (void)hipFree(b->d_tiles);
+  if (b->d_desc) (void)hipFree(b->d_desc);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->st) (void)hipStreamDestroy(b->st);
   delete b;
   return ENS_OK;
 }
@@ -1411,8 +1412,8 @@ int32_t ens_batch_autotune(ens_batch* b, int32_t trial_steps) {
       }
       if (rc != ENS_OK) break;
     }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (rc != ENS_OK) return rc;
     b->spl = bs;
     b->tile_nodes = bt;

@@ -640,9 +640,9 @@ int32_t sur_create(int32_t device, int32_t n_in, int32_t width, int32_t n_hidden
 
 int32_t sur_destroy(sur_net* s) {
   if (!s) return ENS_EINVAL;
-  if (s->bound) {
-    hipSetDevice(s->device);
-    hipDeviceSynchronize();
+  if (s->bound) {  // teardown: nothing to report
+    (void)hipSetDevice(s->device);
+    (void)hipDeviceSynchronize();
   }
   delete s;
   return ENS_OK;

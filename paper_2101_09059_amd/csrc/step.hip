@@ -23,6 +23,13 @@
 
 #include <cmath>
 
+// Incident elements whose loads a wave keeps in flight together.
+#ifndef ENSFEM_GATHER_UNROLL
+#define ENSFEM_GATHER_UNROLL 2
+#endif
+#define ENSFEM_PRAGMA(x) _Pragma(#x)
+#define ENSFEM_UNROLL_GATHER ENSFEM_PRAGMA(unroll ENSFEM_GATHER_UNROLL)
+
 namespace ensfem {
 namespace {
 
@@ -136,7 +143,7 @@ __device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_
 #pragma unroll
     for (int i = 0; i < SPL; ++i) r[c][i] = AT(0);
   ST ub[3][SPL], uc[3][SPL];
-#pragma unroll 2
+  ENSFEM_UNROLL_GATHER
   for (int k = kb; k < ke; ++k) {
     const int64_t e = maybe_uni<UNI>(gen(p.adj.el)[k]);
     const int2 bc0 = gen(p.adj.nb)[k];
