@@ -54,7 +54,7 @@ def step_kernel_bytes(n_nodes: int, n_el: int, S: int, apply_f32: bool) -> dict:
 
 def source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("step.hip", "internal.h"):
+    for f in ("step.hip", "internal.h", "api.hip"):
         with open(os.path.join(ROOT, "paper_2101_09059_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -22,7 +22,10 @@
  *  - Device pointers given to ens_apply are borrowed for the call.
  *  - Layouts are row-major with samples fastest: an ensemble block is
  *    [rows][S] on the host and [rows][S_pad] on the device, S_pad >= S
- *    (query ens_info); dof index = 3*node + component (x, y, z).
+ *    (query ens_info); dof index = 3*node + component (x, y, z).  Nodes and
+ *    elements are numbered as the caller gave them in ens_set_mesh at every
+ *    entry point; the library reorders them internally for locality (a
+ *    recursive coordinate bisection into compact patches of <= 64 nodes).
  *  - Work is enqueued on the stream given to ens_step / ens_apply (a
  *    hipStream_t; NULL = the legacy default stream).  Set-up calls and
  *    read-backs synchronize.
@@ -185,7 +188,9 @@ int32_t ens_apply(ens_ctx* ctx, int32_t prec, const void* U_dev, void* R_dev, vo
 int32_t ens_set_tuning(ens_ctx* ctx, int32_t sample_block, int32_t sb_inner);
 
 /* Checkpoint of the time-stepping state (state arrays, step count, dt,
- * QoI).  ens_save with host == NULL writes the size to *bytes. */
+ * QoI).  ens_save with host == NULL writes the size to *bytes.  The blob is
+ * opaque: rows are stored in the library's internal node order, so it
+ * restores only into a context given the same mesh and sample count. */
 int32_t ens_save(ens_ctx* ctx, void* host, size_t* bytes);
 int32_t ens_load(ens_ctx* ctx, const void* host, size_t bytes);
 

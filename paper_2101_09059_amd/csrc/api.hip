@@ -25,7 +25,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
   size_t xyz, tri, khat, area, lam, flags, adj_ptr, adj_el, adj_nb, adj_loc, k64, k32, fixed,
-      radial, F, eh64, eh32, h, minv64, minv32, u[2], uh[2], uc, v, q, qmask, bsr_ptr, bsr_col,
+      radial, perm, F, eh64, eh32, h, minv64, minv32, u[2], uh[2], uc, v, q, qmask, bsr_ptr, bsr_col,
       adj_slot, bsr64, bsr32, epart, erec, gtab, base,
       mean, var, aux, total;
 };
@@ -46,6 +46,9 @@ struct ens_ctx {
   std::vector<double> xyz, radial;
   std::vector<int32_t> tri;
   std::vector<uint8_t> fixed;  // bits per node
+  // internal numbering: node i is the caller's node perm[i], element e the
+  // caller's element eperm[e]
+  std::vector<int32_t> perm, eperm;
   bool have_mesh = false;
   // adjacency
   std::vector<int32_t> adj_ptr, adj_el;
@@ -164,6 +167,7 @@ Layout plan(const ens_ctx* c) {
   L.k32 = take(sizeof(float) * 18 * nadj);
   L.fixed = take(nn);
   L.radial = take(sizeof(double) * 3 * nn);
+  L.perm = take(sizeof(int32_t) * nn);
   L.F = take(sizeof(double) * 3 * nn);
   L.eh64 = take(sizeof(double) * ne * ld);
   L.eh32 = take(sizeof(float) * ne * ld);
@@ -350,19 +354,58 @@ void set_state_ptrs(const ens_ctx* c, StepArgs& a, int flip) {
   }
 }
 
-// pad [rows][S] host data to [rows][ld], pads copy column 0
-void pad_rows(const double* src, int64_t rows, int S, int ld, std::vector<double>& dst) {
+// Caller rows <-> internal rows.  Internal row r holds caller row
+// map[r / rep] * rep + r % rep (rep = 3 for dof rows of the node map,
+// 1 for node or element rows); map == null: identity.
+inline int64_t caller_row(const std::vector<int32_t>* map, int rep, int64_t r) {
+  return map ? (int64_t)(*map)[r / rep] * rep + r % rep : r;
+}
+
+// pad [rows][S] caller data to internal [rows][ld]; pads copy column 0
+void pad_rows(const double* src, int64_t rows, int S, int ld, std::vector<double>& dst,
+              const std::vector<int32_t>* map = nullptr, int rep = 1) {
   dst.resize((size_t)rows * ld);
   for (int64_t r = 0; r < rows; ++r) {
-    const double* s = src + r * S;
+    const double* s = src + caller_row(map, rep, r) * S;
     double* d = dst.data() + r * ld;
     std::memcpy(d, s, sizeof(double) * S);
     for (int k = S; k < ld; ++k) d[k] = s[0];
   }
 }
 
-void unpad_rows(const double* src, int64_t rows, int S, int ld, double* dst) {
-  for (int64_t r = 0; r < rows; ++r) std::memcpy(dst + r * S, src + r * ld, sizeof(double) * S);
+void unpad_rows(const double* src, int64_t rows, int S, int ld, double* dst,
+                const std::vector<int32_t>* map = nullptr, int rep = 1) {
+  for (int64_t r = 0; r < rows; ++r)
+    std::memcpy(dst + caller_row(map, rep, r) * S, src + r * ld, sizeof(double) * S);
+}
+
+// Locality order of the nodes: recursive coordinate bisection (split at the
+// median of the longest bounding-box axis) down to patches of <= 64 nodes,
+// patches in recursion order, nodes in a patch along its longest axis.  A
+// workgroup's nodes and their neighbours then lie in one compact surface
+// patch, and consecutive node blocks stay close on the surface.
+void rcb_order(const std::vector<double>& xyz, std::vector<int32_t>& idx, size_t lo, size_t hi) {
+  double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
+  for (size_t i = lo; i < hi; ++i)
+    for (int k = 0; k < 3; ++k) {
+      mn[k] = std::min(mn[k], xyz[3 * (size_t)idx[i] + k]);
+      mx[k] = std::max(mx[k], xyz[3 * (size_t)idx[i] + k]);
+    }
+  int ax = 0;
+  for (int k = 1; k < 3; ++k)
+    if (mx[k] - mn[k] > mx[ax] - mn[ax]) ax = k;
+  auto less = [&](int32_t a, int32_t b) {
+    const double xa = xyz[3 * (size_t)a + ax], xb = xyz[3 * (size_t)b + ax];
+    return xa < xb || (xa == xb && a < b);
+  };
+  if (hi - lo <= 64) {
+    std::sort(idx.begin() + lo, idx.begin() + hi, less);
+    return;
+  }
+  const size_t mid = lo + (hi - lo) / 2;
+  std::nth_element(idx.begin() + lo, idx.begin() + mid, idx.begin() + hi, less);
+  rcb_order(xyz, idx, lo, mid);
+  rcb_order(xyz, idx, mid, hi);
 }
 
 int32_t upload_all(ens_ctx* ctx) {
@@ -377,6 +420,7 @@ int32_t upload_all(ens_ctx* ctx) {
   HIPC(hipMemcpy(ctx->p<void>(L.adj_loc), ctx->adj_loc.data(), 3 * ne, hipMemcpyHostToDevice));
   HIPC(hipMemcpy(ctx->p<void>(L.fixed), ctx->fixed.data(), nn, hipMemcpyHostToDevice));
   HIPC(hipMemcpy(ctx->p<void>(L.radial), ctx->radial.data(), sizeof(double) * 3 * nn, hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(ctx->p<void>(L.perm), ctx->perm.data(), sizeof(int32_t) * nn, hipMemcpyHostToDevice));
   if (ctx->have_load)
     HIPC(hipMemcpy(ctx->p<void>(L.F), ctx->F.data(), sizeof(double) * 3 * nn, hipMemcpyHostToDevice));
   else
@@ -496,13 +540,36 @@ int32_t ens_set_mesh(ens_ctx* ctx, int64_t n_nodes, const double* xyz, int64_t n
   }
   ctx->n_nodes = n_nodes;
   ctx->n_el = n_el;
-  ctx->xyz.assign(xyz, xyz + 3 * n_nodes);
-  ctx->tri.assign(tri, tri + 3 * n_el);
-  ctx->radial.assign(radial, radial + 3 * n_nodes);
-  ctx->fixed.assign(n_nodes, 0);
-  for (int64_t i = 0; i < n_nodes; ++i)
-    for (int k = 0; k < 3; ++k)
-      if (fixed_dof[3 * i + k]) ctx->fixed[i] |= (uint8_t)(1u << k);
+  {
+    std::vector<double> cxyz(xyz, xyz + 3 * n_nodes);
+    std::vector<int32_t>& perm = ctx->perm;
+    perm.resize(n_nodes);
+    for (int64_t i = 0; i < n_nodes; ++i) perm[i] = (int32_t)i;
+    rcb_order(cxyz, perm, 0, (size_t)n_nodes);
+    std::vector<int32_t> inv(n_nodes);
+    for (int64_t i = 0; i < n_nodes; ++i) inv[perm[i]] = (int32_t)i;
+    // elements in order of their first (internal) node, ties by caller index
+    std::vector<int32_t> key(n_el);
+    for (int64_t e = 0; e < n_el; ++e)
+      key[e] = std::min(inv[tri[3 * e]], std::min(inv[tri[3 * e + 1]], inv[tri[3 * e + 2]]));
+    ctx->eperm.resize(n_el);
+    for (int64_t e = 0; e < n_el; ++e) ctx->eperm[e] = (int32_t)e;
+    std::stable_sort(ctx->eperm.begin(), ctx->eperm.end(), [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+    ctx->xyz.resize(3 * n_nodes);
+    ctx->radial.resize(3 * n_nodes);
+    ctx->fixed.assign(n_nodes, 0);
+    for (int64_t i = 0; i < n_nodes; ++i) {
+      const int64_t o = perm[i];
+      for (int k = 0; k < 3; ++k) {
+        ctx->xyz[3 * i + k] = xyz[3 * o + k];
+        ctx->radial[3 * i + k] = radial[3 * o + k];
+        if (fixed_dof[3 * o + k]) ctx->fixed[i] |= (uint8_t)(1u << k);
+      }
+    }
+    ctx->tri.resize(3 * n_el);
+    for (int64_t e = 0; e < n_el; ++e)
+      for (int k = 0; k < 3; ++k) ctx->tri[3 * e + k] = inv[tri[3 * (int64_t)ctx->eperm[e] + k]];
+  }
   build_adjacency(ctx);
   ctx->have_mesh = true;
   ctx->have_ens = false;  // fields are per element: re-set them for a new mesh
@@ -543,8 +610,8 @@ int32_t ens_set_ensemble(ens_ctx* ctx, int32_t S, const double* eh, const double
   ctx->S = S;
   ctx->SB = pick_sample_block(S, ctx->tune_sb);
   ctx->ld = ((S + ctx->SB - 1) / ctx->SB) * ctx->SB;
-  pad_rows(eh, ctx->n_el, S, ctx->ld, ctx->eh);
-  pad_rows(h, ctx->n_el, S, ctx->ld, ctx->h);
+  pad_rows(eh, ctx->n_el, S, ctx->ld, ctx->eh, &ctx->eperm);
+  pad_rows(h, ctx->n_el, S, ctx->ld, ctx->h, &ctx->eperm);
   bool shared = true;
   for (int64_t e = 0; e < ctx->n_el && shared; ++e)
     for (int s = 1; s < S; ++s)
@@ -571,7 +638,9 @@ int32_t ens_set_load(ens_ctx* ctx, const double* F, ens_schedule sched) {
     return ctx->fail(ENS_EINVAL, "ens_set_load: period must be positive");
   for (int64_t i = 0; i < 3 * ctx->n_nodes; ++i)
     if (!std::isfinite(F[i])) return ctx->fail(ENS_EINVAL, "ens_set_load: non-finite load");
-  ctx->F.assign(F, F + 3 * ctx->n_nodes);
+  ctx->F.resize(3 * ctx->n_nodes);
+  for (int64_t i = 0; i < ctx->n_nodes; ++i)
+    for (int k = 0; k < 3; ++k) ctx->F[3 * i + k] = F[3 * (int64_t)ctx->perm[i] + k];
   ctx->sched = Schedule{sched.kind, sched.t_ramp, sched.amp, sched.period};
   ctx->have_load = true;
   if (ctx->bound) {
@@ -671,13 +740,13 @@ int32_t ens_init_state(ens_ctx* ctx, const double* u0, const double* v0) {
         return ctx->fail(ENS_EINVAL, "ens_init_state: non-finite initial state");
   if (ctx->state_prec == ENS_STATE_F64) {
     if (u0) {
-      pad_rows(u0, ndof, ctx->S, (int)ld, buf);
+      pad_rows(u0, ndof, ctx->S, (int)ld, buf, &ctx->perm, 3);
       HIPC(hipMemcpy(ctx->p<void>(L.u[0]), buf.data(), sizeof(double) * n, hipMemcpyHostToDevice));
     } else {
       HIPC(hipMemset(ctx->p<void>(L.u[0]), 0, sizeof(double) * n));
     }
     if (v0) {
-      pad_rows(v0, ndof, ctx->S, (int)ld, buf);
+      pad_rows(v0, ndof, ctx->S, (int)ld, buf, &ctx->perm, 3);
       HIPC(hipMemcpy(ctx->p<void>(L.u[1]), buf.data(), sizeof(double) * n, hipMemcpyHostToDevice));
     } else {
       HIPC(hipMemset(ctx->p<void>(L.u[1]), 0, sizeof(double) * n));
@@ -687,7 +756,7 @@ int32_t ens_init_state(ens_ctx* ctx, const double* u0, const double* v0) {
   } else {
     float* uc = ctx->state_prec == ENS_STATE_F32_KAHAN ? ctx->p<float>(L.uc) : nullptr;
     if (u0) {
-      pad_rows(u0, ndof, ctx->S, (int)ld, buf);
+      pad_rows(u0, ndof, ctx->S, (int)ld, buf, &ctx->perm, 3);
       HIPC(hipMemcpy(ctx->p<void>(L.aux), buf.data(), sizeof(double) * n, hipMemcpyHostToDevice));
       HIPC(launch_split_f32(n, ctx->p<double>(L.aux), ctx->p<float>(L.uh[0]), uc, st));
     } else {
@@ -695,7 +764,7 @@ int32_t ens_init_state(ens_ctx* ctx, const double* u0, const double* v0) {
       if (uc) HIPC(hipMemset(uc, 0, sizeof(float) * n));
     }
     if (v0) {
-      pad_rows(v0, ndof, ctx->S, (int)ld, buf);
+      pad_rows(v0, ndof, ctx->S, (int)ld, buf, &ctx->perm, 3);
       HIPC(hipMemcpy(ctx->p<void>(L.aux), buf.data(), sizeof(double) * n, hipMemcpyHostToDevice));
       HIPC(launch_cast_f32(n, ctx->p<double>(L.aux), ctx->p<float>(L.v), st));
     } else {
@@ -729,7 +798,7 @@ int32_t run_starter(ens_ctx* ctx, double dt, hipStream_t st) {
       HIPC(hipMemsetAsync(R, 0, sizeof(double) * n, st));
     } else {
       StepArgs a = base_args(ctx, false);
-      HIPC(launch_apply(a, false, ctx->SB, use_shared(ctx), ctx->p<double>(L.u[ctx->cur]), R, st));
+      HIPC(launch_apply(a, false, ctx->SB, use_shared(ctx), ctx->p<double>(L.u[ctx->cur]), R, nullptr, st));
     }
     HIPC(launch_starter_f64((int32_t)ctx->n_nodes, ctx->ld, R, ctx->p<double>(L.minv64), ctx->p<double>(L.F),
                             ctx->p<uint8_t>(L.fixed), ctx->p<double>(L.u[ctx->cur]),
@@ -740,7 +809,7 @@ int32_t run_starter(ens_ctx* ctx, double dt, hipStream_t st) {
       HIPC(hipMemsetAsync(R, 0, sizeof(float) * n, st));
     } else {
       StepArgs a = base_args(ctx, true);
-      HIPC(launch_apply(a, true, ctx->SB, use_shared(ctx), ctx->p<float>(L.uh[ctx->cur]), R, st));
+      HIPC(launch_apply(a, true, ctx->SB, use_shared(ctx), ctx->p<float>(L.uh[ctx->cur]), R, nullptr, st));
     }
     HIPC(launch_starter_f32((int32_t)ctx->n_nodes, ctx->ld, R, ctx->p<float>(L.minv32), ctx->p<double>(L.F),
                             ctx->p<uint8_t>(L.fixed), ctx->p<float>(L.v), ctx->p<double>(L.gtab), dt,
@@ -861,7 +930,7 @@ int32_t ens_read_state(ens_ctx* ctx, double* u) {
     HIPC(launch_combine_f32(n, ctx->p<float>(L.uh[ctx->cur]), uc, ctx->p<double>(L.aux), nullptr));
     HIPC(hipMemcpy(buf.data(), ctx->p<void>(L.aux), sizeof(double) * n, hipMemcpyDeviceToHost));
   }
-  unpad_rows(buf.data(), ndof, ctx->S, ctx->ld, u);
+  unpad_rows(buf.data(), ndof, ctx->S, ctx->ld, u, &ctx->perm, 3);
   return ENS_OK;
   GUARD_END
 }
@@ -881,7 +950,7 @@ int32_t ens_read_qoi(ens_ctx* ctx, int32_t kind, double* out) {
   const int64_t n = ctx->n_nodes * ctx->ld;
   std::vector<double> buf(n);
   HIPC(hipMemcpy(buf.data(), ctx->p<void>(ctx->L.q), sizeof(double) * n, hipMemcpyDeviceToHost));
-  unpad_rows(buf.data(), ctx->n_nodes, ctx->S, ctx->ld, out);
+  unpad_rows(buf.data(), ctx->n_nodes, ctx->S, ctx->ld, out, &ctx->perm, 1);
   return ENS_OK;
   GUARD_END
 }
@@ -924,8 +993,13 @@ int32_t ens_moments(ens_ctx* ctx, double* mean, double* var) {
   const Layout& L = ctx->L;
   HIPC(launch_moments((int32_t)ctx->n_nodes, ctx->ld, ctx->S, ctx->p<double>(L.q), ctx->p<double>(L.mean),
                       ctx->p<double>(L.var), nullptr));
-  HIPC(hipMemcpy(mean, ctx->p<void>(L.mean), sizeof(double) * ctx->n_nodes, hipMemcpyDeviceToHost));
-  HIPC(hipMemcpy(var, ctx->p<void>(L.var), sizeof(double) * ctx->n_nodes, hipMemcpyDeviceToHost));
+  std::vector<double> hm(ctx->n_nodes), hv(ctx->n_nodes);
+  HIPC(hipMemcpy(hm.data(), ctx->p<void>(L.mean), sizeof(double) * ctx->n_nodes, hipMemcpyDeviceToHost));
+  HIPC(hipMemcpy(hv.data(), ctx->p<void>(L.var), sizeof(double) * ctx->n_nodes, hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < ctx->n_nodes; ++i) {
+    mean[ctx->perm[i]] = hm[i];
+    var[ctx->perm[i]] = hv[i];
+  }
   return ENS_OK;
 }
 
@@ -936,7 +1010,7 @@ int32_t ens_apply(ens_ctx* ctx, int32_t prec, const void* U_dev, void* R_dev, vo
   if (!U_dev || !R_dev) return ctx->fail(ENS_EINVAL, "ens_apply: null device buffer");
   HIPC(hipSetDevice(ctx->device));
   StepArgs a = base_args(ctx, prec == ENS_F32);
-  HIPC(launch_apply(a, prec == ENS_F32, ctx->SB, use_shared(ctx), U_dev, R_dev,
+  HIPC(launch_apply(a, prec == ENS_F32, ctx->SB, use_shared(ctx), U_dev, R_dev, ctx->p<int32_t>(ctx->L.perm),
                     static_cast<hipStream_t>(stream)));
   return ENS_OK;
 }

@@ -121,8 +121,10 @@ hipError_t launch_bsr_assemble(int32_t n_nodes, int32_t ld, const int32_t* adj_p
 // the apply precision; mode the state storage; qoi / energy the outputs.
 hipError_t launch_step(const StepArgs& a, bool apply_f32, int mode, int sample_block, bool qoi,
                        bool energy, bool shared, hipStream_t st);
+// Stand-alone R = K U; map (internal node -> buffer node) or null when U and
+// R are in the internal numbering.
 hipError_t launch_apply(const StepArgs& a, bool f32, int sample_block, bool shared, const void* U,
-                        void* R, hipStream_t st);
+                        void* R, const int32_t* map, hipStream_t st);
 hipError_t launch_schedule(double* gtab, int64_t* base, int32_t k, double dt, Schedule s,
                            hipStream_t st);
 hipError_t launch_advance(int64_t* base, int32_t k, hipStream_t st);

@@ -129,11 +129,18 @@ __device__ __forceinline__ AT row6(const AT* __restrict__ k, AT d0, AT d1, AT d2
   return fma(k[5], d5, f);
 }
 
+// Row of node n in a caller buffer: map[n] (caller numbering) or n itself.
+template <bool MAP>
+__device__ __forceinline__ int64_t node_row(const int32_t* __restrict__ map, int n) {
+  if constexpr (MAP) return (int64_t)map[n] * 3;
+  else return (int64_t)n * 3;
+}
+
 // R for one node and SPL consecutive samples starting at s0.
-template <typename AT, typename ST, int SPL, bool UNI>
+template <typename AT, typename ST, int SPL, bool UNI, bool MAP = false>
 __device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_t ld, int s0,
                                              const ST* __restrict__ U, const ST (&ua)[3][SPL],
-                                             AT (&r)[3][SPL]) {
+                                             AT (&r)[3][SPL], const int32_t* __restrict__ map = nullptr) {
   const int kb = maybe_uni<UNI>(gen(p.adj.ptr)[node]);
   const int ke = maybe_uni<UNI>(gen(p.adj.ptr)[node + 1]);
   const AT* __restrict__ KB = static_cast<const AT*>(gen(p.adj.k));
@@ -155,7 +162,7 @@ __device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_
     vload<SPL, false>(EH + e * ld + s0, eh);
     // bc.x < 0: this element's first neighbour is the previous one's second
     if (bc.x >= 0) {
-      const int64_t rb = (int64_t)bc.x * 3;
+      const int64_t rb = node_row<MAP>(map, bc.x);
 #pragma unroll
       for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (rb + c) * ld + s0, ub[c]);
     } else {
@@ -164,7 +171,7 @@ __device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_
 #pragma unroll
         for (int i = 0; i < SPL; ++i) ub[c][i] = uc[c][i];
     }
-    const int64_t rc = (int64_t)bc.y * 3;
+    const int64_t rc = node_row<MAP>(map, bc.y);
 #pragma unroll
     for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (rc + c) * ld + s0, uc[c]);
 #pragma unroll
@@ -187,10 +194,10 @@ __device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_
 
 // Shared stiffness: R_i = sum_j K_ij (u_j - u_i) over the assembled
 // off-diagonal 3x3 blocks of row i.
-template <typename AT, typename ST, int SPL, bool UNI>
+template <typename AT, typename ST, int SPL, bool UNI, bool MAP = false>
 __device__ __forceinline__ void gather_blocks(const StepArgs& p, int node, int64_t ld, int s0,
                                               const ST* __restrict__ U, const ST (&ua)[3][SPL],
-                                              AT (&r)[3][SPL]) {
+                                              AT (&r)[3][SPL], const int32_t* __restrict__ map = nullptr) {
   const int kb = maybe_uni<UNI>(gen(p.bsr.ptr)[node]);
   const int ke = maybe_uni<UNI>(gen(p.bsr.ptr)[node + 1]);
   const AT* __restrict__ V = static_cast<const AT*>(gen(p.bsr.val));
@@ -200,7 +207,7 @@ __device__ __forceinline__ void gather_blocks(const StepArgs& p, int node, int64
     for (int i = 0; i < SPL; ++i) r[c][i] = AT(0);
 #pragma unroll 2
   for (int k = kb; k < ke; ++k) {
-    const int64_t rj = (int64_t)maybe_uni<UNI>(gen(p.bsr.col)[k]) * 3;
+    const int64_t rj = node_row<MAP>(map, maybe_uni<UNI>(gen(p.bsr.col)[k]));
     AT B[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) B[i] = maybe_uni<UNI>(V[(int64_t)k * 9 + i]);
@@ -484,9 +491,11 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(const BatchTile* __restri
   }
 }
 
-template <typename AT, int LPN, int SPL, bool SHARED>
+// Stand-alone apply; with MAP the rows of U and R are in the numbering
+// given by map (internal node -> buffer node).
+template <typename AT, int LPN, int SPL, bool SHARED, bool MAP>
 __global__ __launch_bounds__(kBlock) void k_apply(StepArgs p, const AT* __restrict__ U,
-                                                  AT* __restrict__ R) {
+                                                  AT* __restrict__ R, const int32_t* __restrict__ map) {
   constexpr int SB = LPN * SPL;
   constexpr int NPB = kBlock / LPN;
   int nb, sbk;
@@ -496,13 +505,13 @@ __global__ __launch_bounds__(kBlock) void k_apply(StepArgs p, const AT* __restri
   if (node >= p.n_nodes) return;
   const int s0 = sbk * SB + (int)(threadIdx.x % LPN) * SPL;
   const int64_t ld = p.ld;
-  const int64_t row = (int64_t)node * 3;
+  const int64_t row = node_row<MAP>(map, node);
   AT ua[3][SPL];
 #pragma unroll
   for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (row + c) * ld + s0, ua[c]);
   AT r[3][SPL];
-  if constexpr (SHARED) gather_blocks<AT, AT, SPL, (LPN == 64)>(p, node, ld, s0, U, ua, r);
-  else gather_apply<AT, AT, SPL, (LPN == 64)>(p, node, ld, s0, U, ua, r);
+  if constexpr (SHARED) gather_blocks<AT, AT, SPL, (LPN == 64), MAP>(p, node, ld, s0, U, ua, r, map);
+  else gather_apply<AT, AT, SPL, (LPN == 64), MAP>(p, node, ld, s0, U, ua, r, map);
 #pragma unroll
   for (int c = 0; c < 3; ++c) vstore<SPL, true>(R + (row + c) * ld + s0, r[c]);
 }
@@ -732,21 +741,29 @@ hipError_t dispatch_shared(const StepArgs& a, int sb, bool qoi, bool energy, boo
                 : dispatch_sb<AT, MODE, false>(a, sb, qoi, energy, st);
 }
 
-template <typename AT, bool SH>
-hipError_t dispatch_apply(const StepArgs& a, int sb, const void* U, void* R, hipStream_t st) {
+template <typename AT, bool SH, bool MAP>
+hipError_t dispatch_apply(const StepArgs& a, int sb, const void* U, void* R, const int32_t* map,
+                          hipStream_t st) {
   const unsigned g = step_grid(a);
   const AT* u = static_cast<const AT*>(U);
   AT* r = static_cast<AT*>(R);
   switch (sb) {
-    case 8: k_apply<AT, 8, 1, SH><<<g, kBlock, 0, st>>>(a, u, r); break;
-    case 16: k_apply<AT, 16, 1, SH><<<g, kBlock, 0, st>>>(a, u, r); break;
-    case 32: k_apply<AT, 32, 1, SH><<<g, kBlock, 0, st>>>(a, u, r); break;
-    case 64: k_apply<AT, 64, 1, SH><<<g, kBlock, 0, st>>>(a, u, r); break;
-    case 128: k_apply<AT, 64, 2, SH><<<g, kBlock, 0, st>>>(a, u, r); break;
-    case 256: k_apply<AT, 64, 4, SH><<<g, kBlock, 0, st>>>(a, u, r); break;
+    case 8: k_apply<AT, 8, 1, SH, MAP><<<g, kBlock, 0, st>>>(a, u, r, map); break;
+    case 16: k_apply<AT, 16, 1, SH, MAP><<<g, kBlock, 0, st>>>(a, u, r, map); break;
+    case 32: k_apply<AT, 32, 1, SH, MAP><<<g, kBlock, 0, st>>>(a, u, r, map); break;
+    case 64: k_apply<AT, 64, 1, SH, MAP><<<g, kBlock, 0, st>>>(a, u, r, map); break;
+    case 128: k_apply<AT, 64, 2, SH, MAP><<<g, kBlock, 0, st>>>(a, u, r, map); break;
+    case 256: k_apply<AT, 64, 4, SH, MAP><<<g, kBlock, 0, st>>>(a, u, r, map); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <typename AT, bool SH>
+hipError_t dispatch_apply_map(const StepArgs& a, int sb, const void* U, void* R, const int32_t* map,
+                              hipStream_t st) {
+  return map ? dispatch_apply<AT, SH, true>(a, sb, U, R, map, st)
+             : dispatch_apply<AT, SH, false>(a, sb, U, R, nullptr, st);
 }
 
 }  // namespace
@@ -768,13 +785,13 @@ hipError_t launch_step(const StepArgs& a, bool apply_f32, int mode, int sample_b
 }
 
 hipError_t launch_apply(const StepArgs& a, bool f32, int sample_block, bool shared, const void* U,
-                        void* R, hipStream_t st) {
+                        void* R, const int32_t* map, hipStream_t st) {
   if (a.n_nb == 0 || a.n_sb == 0) return hipSuccess;
   if (shared)
-    return f32 ? dispatch_apply<float, true>(a, sample_block, U, R, st)
-               : dispatch_apply<double, true>(a, sample_block, U, R, st);
-  return f32 ? dispatch_apply<float, false>(a, sample_block, U, R, st)
-             : dispatch_apply<double, false>(a, sample_block, U, R, st);
+    return f32 ? dispatch_apply_map<float, true>(a, sample_block, U, R, map, st)
+               : dispatch_apply_map<double, true>(a, sample_block, U, R, map, st);
+  return f32 ? dispatch_apply_map<float, false>(a, sample_block, U, R, map, st)
+             : dispatch_apply_map<double, false>(a, sample_block, U, R, map, st);
 }
 
 hipError_t launch_batch_step(const BatchTile* tiles, int32_t n_tiles, int spl, const StepArgs* desc, int32_t j,
