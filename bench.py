@@ -35,19 +35,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def step_kernel_bytes(n_nodes: int, n_el: int, S: int, apply_f32: bool) -> dict:
-    """Algorithmic HBM bytes of one fused step launch (FP64 state): read
-    u_n and u_{n-1}, write u_{n+1} (8 B per dof and sample each), read
-    (E h) per element and sample and 1/m per node and sample (4 B in the
-    FP32 apply, 8 B in FP64), read and write the at-max bit of the running
-    peak (1/8 B each per node and sample; the stored peak itself is only
-    touched where the radial displacement turns, so it is not counted),
-    plus the per-mesh arrays read once per launch (adjacency and 3x6
-    stiffness blocks, load, radial directions, clamp bits)."""
+def step_kernel_bytes(n_nodes: int, n_el: int, S: int, apply_f32: bool, state: str = "f64") -> dict:
+    """Algorithmic HBM bytes of one fused step launch.  State traffic per
+    dof and sample: FP64 state reads u_n and u_{n-1} and writes u_{n+1}
+    (3 x 8 B); FP32-Kahan reads and writes u, its compensation and the
+    velocity (6 x 4 B); plain FP32 reads and writes u and the velocity
+    (4 x 4 B).  Plus (E h) per element and sample and 1/m per node and
+    sample (4 B in the FP32 apply, 8 B in FP64), the at-max bit of the
+    running peak read and written (1/8 B each per node and sample; the
+    stored peak itself is only touched where the radial displacement turns,
+    so it is not counted), and the per-mesh arrays read once per launch
+    (adjacency and 3x6 stiffness blocks, load, radial directions, clamp
+    bits)."""
     w = 4 if apply_f32 else 8
+    state_b = {"f64": 24, "f32_kahan": 24, "f32": 16}[state]
     n_dof = 3 * n_nodes
     n_adj = 3 * n_el
-    per_sample = 3 * n_dof * 8 + n_el * w + n_nodes * w + n_nodes * 0.25
+    per_sample = n_dof * state_b + n_el * w + n_nodes * w + n_nodes * 0.25
     per_mesh = n_adj * (18 * w + 4 + 8) + (n_nodes + 1) * 4 + n_nodes * (24 + 24 + 1)
     return dict(total=int(per_sample * S + per_mesh), per_sample=per_sample, per_mesh=per_mesh)
 
@@ -252,6 +256,93 @@ def run_learned_config(args, torch):
     print(json.dumps(out), flush=True)
 
 
+def run_precision_config(args, torch):
+    """Precision form at full size: 1M-node curved tapered tube, S = 1,024,
+    sine-ramped pulsatile pressure with axial taper and wall shear.
+    Throughput of each precision mode at S = 1,024, and the error of each
+    FP32 mode against the FP64 path over a longer run on the first 64
+    sample columns (same mesh, fields and load)."""
+    from paper_2101_09059_amd import ensfem, inputs
+    cfg = inputs.CONFIGS["c3_curved"]
+    t0 = time.perf_counter()
+    mesh = inputs.curved_tube(cfg["n_theta"], cfg["n_z"])
+    S = cfg["S"]
+    eh, h = inputs.lognormal_fields_device(mesh, S, cfg["seed"], radius=0.9)
+    F = inputs.traction_load(mesh, cfg["p0"], axial_taper=cfg["axial_taper"], shear_frac=cfg["shear_frac"],
+                             seed=cfg["seed"])
+    log(f"inputs ready in {time.perf_counter() - t0:.1f} s: {mesh.n_nodes} nodes, {mesh.n_el} tri, S={S}")
+    modes = [("f64", ensfem.F64, ensfem.STATE_F64, "f64"),
+             ("f32_apply_f64_state", ensfem.F32, ensfem.STATE_F64, "f64"),
+             ("f32_apply_kahan_f32_state", ensfem.F32, ensfem.STATE_F32_KAHAN, "f32_kahan"),
+             ("f32", ensfem.F32, ensfem.STATE_F32, "f32")]
+
+    def make(fields, hh, ap, st):
+        return ensfem.setup_case(mesh, fields, hh, F, nu=cfg["nu"], shear_k=cfg["shear_k"], rho=cfg["rho"],
+                                 alpha=cfg["alpha"], kind=ensfem.LOAD_PULSATILE, t_ramp=cfg["T_ramp"],
+                                 amp=cfg["pulse_amp"], period=cfg["period"], apply_prec=ap, state_prec=st)
+
+    steps = min(args.steps, 200)
+    stream = torch.cuda.current_stream()
+    thr = {}
+    dt = None
+    for name, ap, st, sb in modes:
+        ens = make(eh, h, ap, st)
+        dt = ens.cfl_dt(cfg["safety"])
+        ens.init_state()
+        ens.step(10, dt, stream=stream)
+        ens.sync()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        ens.step(steps, dt, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        ens.sync()
+        S_pad = ens.info()["S_pad"]
+        ens.close()
+        del ens
+        torch.cuda.empty_cache()
+        b = step_kernel_bytes(mesh.n_nodes, mesh.n_el, S_pad, ap == ensfem.F32, sb)["total"]
+        thr[name] = dict(ms_per_step=ms, value=mesh.n_dof * S / (ms * 1e-3), achieved_GBs=b / (ms * 1e-3) / 1e9)
+        log(f"{name}: {ms:.3f} ms/step, {thr[name]['achieved_GBs']:.0f} GB/s algorithmic")
+
+    n_acc, S_acc = args.c3_error_steps, 64
+    e_acc, h_acc = np.ascontiguousarray(eh[:, :S_acc]), np.ascontiguousarray(h[:, :S_acc])
+    del eh, h
+    ref_u = ref_q = None
+    err = {}
+    for name, ap, st, _ in modes:
+        ens = make(e_acc, h_acc, ap, st)
+        ens.init_state()
+        ens.step(n_acc, dt, stream=stream)
+        ens.sync()
+        u, q = ens.read_state(), ens.read_qoi()
+        ens.close()
+        del ens
+        torch.cuda.empty_cache()
+        if ref_u is None:
+            ref_u, ref_q = u, q
+            continue
+        err[name] = dict(state_rel_l2=float(np.linalg.norm(u - ref_u) / np.linalg.norm(ref_u)),
+                         peak_rel_l2=float(np.linalg.norm(q - ref_q) / np.linalg.norm(ref_q)))
+        log(f"{name}: after {n_acc} steps, state rel. L2 error {err[name]['state_rel_l2']:.2e}, "
+            f"peak {err[name]['peak_rel_l2']:.2e} against FP64")
+    head = thr["f32_apply_f64_state"]
+    out = {
+        "metric": "ensemble dof*sample*steps/s", "value": head["value"], "unit": "dof*sample*steps/s",
+        "n_gpus": 1, "steps": steps, "warmup": 10, "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 apply / f64 state", "data": "synthetic",
+        "config": {"workload": "curved tapered tube 500x2000 nodes (3,000,000 dof), S=1,024 lognormal Matern E,h "
+                               "(device-drawn), sine-ramped pulsatile pressure with axial taper and 1% shear, "
+                               "alpha=50, dt=0.9 x element bound",
+                   "n_dof": mesh.n_dof, "samples": S, "dt": dt, "parallelism": "single GPU"},
+        "modes": thr,
+        "error_vs_f64": {"steps": n_acc, "samples": S_acc, **err},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,9 +356,13 @@ def main():
                     help="skip the shared-stiffness (block-row product) timing")
     ap.add_argument("--sample-block", type=int, default=0, help="0 = library default")
     ap.add_argument("--sb-inner", action="store_true")
-    ap.add_argument("--config", choices=["c2_cylinder", "c4_batch", "c5_learned"], default="c2_cylinder",
-                    help="c2_cylinder: the headline single-mesh workload; c4_batch: the batching form; "
-                         "c5_learned: the learned form (about 10 GPU-minutes)")
+    ap.add_argument("--config", choices=["c2_cylinder", "c3_curved", "c4_batch", "c5_learned"],
+                    default="c2_cylinder",
+                    help="c2_cylinder: the headline single-mesh workload; c3_curved: the precision form at "
+                         "1M nodes x 1,024 samples (about 6 GPU-minutes); c4_batch: the batching form; "
+                         "c5_learned: the learned form (about 12 GPU-minutes)")
+    ap.add_argument("--c3-error-steps", type=int, default=20000,
+                    help="c3_curved: steps of the error run on 64 sample columns")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 10 times (counter calibration)")
     args = ap.parse_args()
@@ -293,6 +388,9 @@ def main():
         print(json.dumps({"calib_copy_bytes_read": n, "calib_copy_bytes_written": n, "launches": 10}))
         return
 
+    if args.config == "c3_curved":
+        run_precision_config(args, torch)
+        return
     if args.config == "c4_batch":
         run_batch_config(args, torch)
         return

@@ -125,6 +125,10 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"libensfem.so not built at {path}: run python -m paper_2101_09059_amd.build")
+    # torch ships its own HIP runtime under the same soname; loading torch
+    # first makes the library bind to that one, so the process holds a single
+    # runtime (the other order loads two and torch then finds no device)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(path)
     for name, (res, args) in _SIGS.items():
         f = getattr(lib, name)

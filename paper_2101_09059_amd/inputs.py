@@ -33,7 +33,7 @@ import numpy as np
 from scipy import special
 
 __all__ = [
-    "Mesh", "cylinder", "curved_tube", "tube_batch_specs",
+    "Mesh", "cylinder", "curved_tube", "tube_batch_specs", "lognormal_fields_device",
     "matern_nodal_lattice", "centroid_average", "lognormal_fields",
     "traction_load", "CONFIGS",
 ]
@@ -214,6 +214,60 @@ def matern_nodal_lattice(mesh: Mesh, n_samples: int, rng: np.random.Generator,
                 out[k] = f[i].imag
                 k += 1
     return np.ascontiguousarray(out.T)
+
+
+def _lattice_spectrum(mesh: Mesh, sigma: float, rho: float, nu: float, radius: Optional[float]):
+    """Square root of the circulant embedding's eigenvalues, scaled for a
+    size-(mz, nt) FFT, as used by matern_nodal_lattice."""
+    nt, nz = mesh.n_theta, mesh.n_z
+    R = float(np.mean(np.linalg.norm(mesh.xyz[:nt, :2], axis=1))) if radius is None else float(radius)
+    dz = mesh.length / (nz - 1)
+    kappa = math.sqrt(8.0 * nu) / rho
+    mz = 1
+    while mz < 2 * (nz - 1):
+        mz *= 2
+    kz = np.arange(mz)
+    lagz = np.minimum(kz, mz - kz) * dz
+    dth = 2.0 * np.pi * np.arange(nt) / nt
+    D = np.sqrt((2.0 * R * R * (1.0 - np.cos(dth)))[None, :] + lagz[:, None] ** 2)
+    lam = np.maximum(np.fft.fft2(_matern(D, sigma, nu, kappa)).real, 0.0)
+    return np.sqrt(lam / (mz * nt)), mz
+
+
+def lognormal_fields_device(mesh: Mesh, S: int, seed: int, E_mean: float = 7.0e6, h_mean: float = 0.1,
+                            sigma_log: float = 0.2, rho: float = 2.0, nu: float = 1.0,
+                            radius: Optional[float] = None, device: str = "cuda"):
+    """lognormal_fields for large lattices, drawn with torch on `device`:
+    the same circulant-embedding construction (each complex FFT gives two
+    independent fields, real and imaginary parts), with torch's seeded
+    generator instead of numpy's, so the draws differ from lognormal_fields
+    but follow the same distribution.  Returns float64 numpy (E h), h
+    [n_el, S]."""
+    import torch
+    nt, nz = mesh.n_theta, mesh.n_z
+    scale_np, mz = _lattice_spectrum(mesh, sigma_log, rho, nu, radius)
+    scale = torch.as_tensor(scale_np, dtype=torch.float64, device=device)
+    tri = torch.as_tensor(mesh.tri.astype(np.int64), device=device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(seed))
+    out = []
+    for mean in (E_mean, h_mean):
+        cols = []
+        k = 0
+        while k < S:
+            b = min(8, (S - k + 1) // 2)
+            z = torch.complex(torch.randn((b, mz, nt), generator=gen, device=device, dtype=torch.float64),
+                              torch.randn((b, mz, nt), generator=gen, device=device, dtype=torch.float64))
+            f = torch.fft.fft2(scale[None] * z)[:, :nz, :].reshape(b, -1)
+            g = torch.stack([f.real, f.imag], 1).reshape(2 * b, -1)[: S - k]      # [fields, n_nodes]
+            cent = (g[:, tri[:, 0]] + g[:, tri[:, 1]] + g[:, tri[:, 2]]) / 3.0     # [fields, n_el]
+            cols.append(torch.exp(math.log(mean) + cent).t().cpu())
+            k += g.shape[0]
+            del z, f, g, cent
+        out.append(torch.cat(cols, 1).numpy())
+    E, h = out
+    np.multiply(E, h, out=E)
+    return np.ascontiguousarray(E), np.ascontiguousarray(h)
 
 
 def centroid_average(mesh: Mesh, nodal: np.ndarray) -> np.ndarray:

@@ -43,3 +43,21 @@ def test_batch_specs_reproducible():
     b = inputs.tube_batch_specs(4)
     assert a == b and len(a) == 16
     assert all(32 <= s["S"] <= 512 and s["S"] % 32 == 0 for s in a)
+
+
+def test_device_fields_follow_the_lattice_distribution():
+    """The torch-drawn fields (used for the 1M-node workload) have the
+    distribution of the numpy ones: log-means, log-std and the correlation
+    of neighbouring elements agree; the draw is reproducible by seed."""
+    m = inputs.curved_tube(40, 100)
+    eh, h = inputs.lognormal_fields_device(m, 64, 3, radius=0.9, device="cpu")
+    eh2, h2 = inputs.lognormal_fields(m, 64, 3, radius=0.9)
+    assert eh.shape == eh2.shape == (m.n_el, 64)
+    for a, b in ((np.log(h), np.log(h2)), (np.log(eh / h), np.log(eh2 / h2))):
+        assert abs(a.mean() - b.mean()) < 0.02
+        assert abs(a.std() - b.std()) < 0.02
+    c1 = np.corrcoef(np.log(h)[0], np.log(h)[1])[0, 1]
+    c2 = np.corrcoef(np.log(h2)[0], np.log(h2)[1])[0, 1]
+    assert abs(c1 - c2) < 0.05
+    again, _ = inputs.lognormal_fields_device(m, 64, 3, radius=0.9, device="cpu")
+    assert np.array_equal(again, eh)
