@@ -65,8 +65,10 @@ def source_hash() -> str:
 
 
 def measured_traffic(workload: str, variant: str, launches_bytes: int):
-    """HBM traffic per launch from the committed rocprofv3 counter summary,
-    if it was taken on the current kernel source; else None."""
+    """(FETCH_SIZE + WRITE_SIZE traffic per launch scaled by the copy
+    calibration, the same with reads counted by request size) from the
+    committed rocprofv3 counter summary, if it was taken on the current
+    kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -75,7 +77,7 @@ def measured_traffic(workload: str, variant: str, launches_bytes: int):
         rec = d.get(f"{workload}:{variant}")
         if not rec or rec.get("source_hash") != source_hash():
             return None
-        return int(rec["bytes_per_launch"])
+        return int(rec["bytes_per_launch"]), rec.get("bytes_per_launch_by_request_size")
     except Exception:
         return None
 
@@ -219,7 +221,9 @@ def run_learned_config(args, torch):
     sumL, sumsqL = net.moment_sums(Xl)
     t_lf = time.perf_counter() - t0
     est = learned.estimate(qH, pm, pv, qL, sumL, sumsqL, c["n_lf"], rmse)
-    log(f"median rho {est['rho_median']:.4f}, control variate used: {est['used_cv']}")
+    vr_boot = learned.bootstrap_variance_ratio(qH, qL, sumL, c["n_lf"])
+    log(f"median rho {est['rho_median']:.4f}, control variate used: {est['used_cv']}, "
+        f"bootstrap variance reduction x{vr_boot:.1f}")
     _, qR = solve_many(sd["ref"], c["n_ref"])
     act = qR.var(axis=1) > 0
     ref_m, ref_v = qR.mean(axis=1), qR.var(axis=1, ddof=1)
@@ -247,6 +251,8 @@ def run_learned_config(args, torch):
         "used_control_variate": est["used_cv"], "rho_median": est["rho_median"],
         "heldout_rel_rmse": rmse, "kl_captured_variance": prob.captured,
         "equivalent_plain_samples": n_eq,
+        "variance_reduction_predicted": float(1.0 / np.median(ratio)),
+        "variance_reduction_bootstrap": vr_boot,
         "speedup_including_training_data": t_plain_eq / (t_cv + t_data),
         "seconds": {"training_data": t_data, "training": net.train_seconds, "high_fidelity_256": t_hf,
                     "network_65536_draws": t_lf, "plain_equivalent": t_plain_eq},
@@ -406,6 +412,8 @@ def main():
     F = inputs.traction_load(mesh, cfg["p0"])
     log(f"inputs ready in {time.perf_counter() - t0:.1f} s: {mesh.n_nodes} nodes, {mesh.n_el} tri, S={cfg['S']}")
 
+    apply_ms = [None]
+
     def run(apply_f32: bool, steps: int, warmup: int, shared: bool = False):
         fields = np.repeat(eh[:, :1], eh.shape[1], axis=1) if shared else eh
         ens = ensfem.setup_case(mesh, fields, h, F, nu=cfg["nu"], shear_k=cfg["shear_k"], rho=cfg["rho"],
@@ -426,6 +434,21 @@ def main():
         ms = e0.elapsed_time(e1)
         ens.sync()
         info = ens.info()
+        if apply_f32 and not shared:
+            # stand-alone FP32 apply R = K(E h) U on [n_dof][S_pad] buffers
+            dtype = torch.float32
+            U = torch.randn(mesh.n_dof, info["S_pad"], device="cuda", dtype=dtype)
+            R = torch.empty_like(U)
+            n_app = 50
+            for _ in range(5):
+                ens.apply(U, R, ensfem.F32, stream=stream)
+            e0.record(stream)
+            for _ in range(n_app):
+                ens.apply(U, R, ensfem.F32, stream=stream)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            apply_ms[0] = e0.elapsed_time(e1) / n_app
+            del U, R
         ens.close()
         del ens
         torch.cuda.empty_cache()
@@ -453,6 +476,7 @@ def main():
     achieved = b["total"] / per_launch_s / 1e9
     variant = f"fused_step_{args.apply}apply_f64state"
     traffic = measured_traffic("c2_cylinder", variant, b["total"])
+    traffic, traffic_req = traffic if traffic else (None, None)
     out = {
         "metric": "ensemble dof*sample*steps/s",
         "value": value,
@@ -471,8 +495,18 @@ def main():
                    "n_dof": mesh.n_dof, "samples": S, "dt": dt, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": f"k_step ({variant})", "algorithmic_bytes_per_launch": b["total"]},
+                     "kernel": f"k_step ({variant})", "algorithmic_bytes_per_launch": b["total"],
+                     "traffic_reads_by_request_size": traffic_req},
     }
+    if apply_ms[0] is not None:
+        # algorithmic bytes of the stand-alone apply: U read and R written
+        # (4 B per dof and sample each), (E h) per element and sample, and the
+        # per-mesh adjacency with its 3x6 blocks
+        ab = (2 * mesh.n_dof * 4 + mesh.n_el * 4) * info["S_pad"] + 3 * mesh.n_el * (18 * 4 + 12)
+        out["apply_only_f32"] = {"ms": apply_ms[0], "algorithmic_bytes": ab,
+                                 "achieved_GBs": ab / (apply_ms[0] * 1e-3) / 1e9,
+                                 "frac": ab / (apply_ms[0] * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                 "kernel": "k_apply (node map: rows in the caller's numbering)"}
     if args.also_shared:
         out["ms_per_step_shared_stiffness"] = ms_sh / args.steps
         out["value_shared_stiffness"] = work / (ms_sh * 1e-3)

@@ -263,12 +263,20 @@ __global__ void k_mse(int64_t n, float scale, const float* __restrict__ Y, const
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
-__global__ void k_loss_final(int nparts, const double* __restrict__ part, double scale,
-                             float* __restrict__ loss) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// One block of 256: each thread sums a fixed stride of the partials, then a
+// fixed tree (deterministic order).
+__global__ __launch_bounds__(256) void k_loss_final(int nparts, const double* __restrict__ part, double scale,
+                                                    float* __restrict__ loss) {
+  __shared__ double red[256];
   double s = 0.0;
-  for (int i = 0; i < nparts; ++i) s += part[i];
-  *loss = (float)(s * scale);
+  for (int i = threadIdx.x; i < nparts; i += 256) s += part[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss = (float)(red[0] * scale);
 }
 
 // column sums of a [rows][cols] FP32 matrix, one thread per column
@@ -558,7 +566,7 @@ int32_t backward(sur_net* s, const float* T, int batch, float* grad, float* loss
   SHIPC((k_mse<<<nb, 256, 0, st>>>(ny, 1.0f / (float)ny, s->p<float>(s->o_y), T, s->p<__bf16>(s->o_dy16), dY32,
                                    s->p<double>(s->o_lpart)),
          hipGetLastError()));
-  SHIPC((k_loss_final<<<1, 64, 0, st>>>((int)nb, s->p<double>(s->o_lpart), 1.0 / (double)ny,
+  SHIPC((k_loss_final<<<1, 256, 0, st>>>((int)nb, s->p<double>(s->o_lpart), 1.0 / (double)ny,
                                         loss_dev ? loss_dev : s->p<float>(s->o_loss)),
          hipGetLastError()));
   const double t = (double)(s->t + 1);

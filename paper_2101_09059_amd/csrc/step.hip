@@ -27,6 +27,11 @@
 #ifndef ENSFEM_GATHER_UNROLL
 #define ENSFEM_GATHER_UNROLL 2
 #endif
+// Issue the node's single-use loads (u_{n-1}, 1/m) before the gather so
+// they are in flight during it (FP64 state).
+#ifndef ENSFEM_HOIST_STREAMS
+#define ENSFEM_HOIST_STREAMS 1
+#endif
 #define ENSFEM_PRAGMA(x) _Pragma(#x)
 #define ENSFEM_UNROLL_GATHER ENSFEM_PRAGMA(unroll ENSFEM_GATHER_UNROLL)
 
@@ -54,6 +59,35 @@ __device__ __forceinline__ bool wg_coords(const StepArgs& p, int& nb, int& sb) {
 template <typename T>
 __device__ __forceinline__ T* gen(ENS_GLOBAL T* ptr) {
   return (T*)ptr;
+}
+
+// Read-only view (constant address space) of mesh data that no kernel of
+// the step writes: adjacency, stiffness blocks, load, clamp bits, radial
+// directions, load factors, and the batch tables.  Uniform loads through it
+// go to the scalar unit even where the kernel stores to other arrays in a
+// loop (through a global pointer the compiler must assume those stores may
+// alias the data and falls back to vector loads).
+template <typename T>
+using ConstPtr = const T __attribute__((address_space(4)))*;
+template <typename T>
+__device__ __forceinline__ ConstPtr<T> cst(ENS_GLOBAL T* ptr) {
+  return (ConstPtr<T>)ptr;
+}
+template <typename T>
+__device__ __forceinline__ ConstPtr<T> cst(const T* ptr) {
+  return (ConstPtr<T>)ptr;
+}
+
+// Copy of an argument block from a device table, word by word through the
+// constant address space (scalar loads for a uniform table index).
+__device__ __forceinline__ StepArgs load_args(const StepArgs* src) {
+  static_assert(sizeof(StepArgs) % 8 == 0, "argument block is copied in 8-byte words");
+  const ConstPtr<unsigned long long> w = (ConstPtr<unsigned long long>)cst(src);
+  StepArgs a;
+  unsigned long long* d = reinterpret_cast<unsigned long long*>(&a);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(StepArgs) / 8); ++i) d[i] = w[i];
+  return a;
 }
 
 // Move a wave-uniform value into a scalar register.  Where the compiler
@@ -141,9 +175,9 @@ template <typename AT, typename ST, int SPL, bool UNI, bool MAP = false>
 __device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_t ld, int s0,
                                              const ST* __restrict__ U, const ST (&ua)[3][SPL],
                                              AT (&r)[3][SPL], const int32_t* __restrict__ map = nullptr) {
-  const int kb = maybe_uni<UNI>(gen(p.adj.ptr)[node]);
-  const int ke = maybe_uni<UNI>(gen(p.adj.ptr)[node + 1]);
-  const AT* __restrict__ KB = static_cast<const AT*>(gen(p.adj.k));
+  const int kb = maybe_uni<UNI>(cst(p.adj.ptr)[node]);
+  const int ke = maybe_uni<UNI>(cst(p.adj.ptr)[node + 1]);
+  const ConstPtr<AT> KB = (ConstPtr<AT>)cst(p.adj.k);
   const AT* __restrict__ EH = static_cast<const AT*>(gen(p.eh));
 #pragma unroll
   for (int c = 0; c < 3; ++c)
@@ -152,8 +186,9 @@ __device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_
   ST ub[3][SPL], uc[3][SPL];
   ENSFEM_UNROLL_GATHER
   for (int k = kb; k < ke; ++k) {
-    const int64_t e = maybe_uni<UNI>(gen(p.adj.el)[k]);
-    const int2 bc0 = gen(p.adj.nb)[k];
+    const int64_t e = maybe_uni<UNI>(cst(p.adj.el)[k]);
+    const ConstPtr<int> nb = (ConstPtr<int>)cst(p.adj.nb);
+    const int2 bc0 = make_int2(nb[2 * k], nb[2 * k + 1]);
     const int2 bc = make_int2(maybe_uni<UNI>(bc0.x), maybe_uni<UNI>(bc0.y));
     AT kk[18];
 #pragma unroll
@@ -198,16 +233,16 @@ template <typename AT, typename ST, int SPL, bool UNI, bool MAP = false>
 __device__ __forceinline__ void gather_blocks(const StepArgs& p, int node, int64_t ld, int s0,
                                               const ST* __restrict__ U, const ST (&ua)[3][SPL],
                                               AT (&r)[3][SPL], const int32_t* __restrict__ map = nullptr) {
-  const int kb = maybe_uni<UNI>(gen(p.bsr.ptr)[node]);
-  const int ke = maybe_uni<UNI>(gen(p.bsr.ptr)[node + 1]);
-  const AT* __restrict__ V = static_cast<const AT*>(gen(p.bsr.val));
+  const int kb = maybe_uni<UNI>(cst(p.bsr.ptr)[node]);
+  const int ke = maybe_uni<UNI>(cst(p.bsr.ptr)[node + 1]);
+  const ConstPtr<AT> V = (ConstPtr<AT>)cst(p.bsr.val);
 #pragma unroll
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int i = 0; i < SPL; ++i) r[c][i] = AT(0);
 #pragma unroll 2
   for (int k = kb; k < ke; ++k) {
-    const int64_t rj = node_row<MAP>(map, maybe_uni<UNI>(gen(p.bsr.col)[k]));
+    const int64_t rj = node_row<MAP>(map, maybe_uni<UNI>(cst(p.bsr.col)[k]));
     AT B[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) B[i] = maybe_uni<UNI>(V[(int64_t)k * 9 + i]);
@@ -267,14 +302,29 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int j, int node, in
   ST ua[3][SPL];
 #pragma unroll
   for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (row + c) * ld + s0, ua[c]);
+  constexpr bool HOIST = ENSFEM_HOIST_STREAMS && MODE == kStateF64;
+  const int64_t ms = (int64_t)node * ld + s0;
+  double up_h[3][SPL];
+  double minv_h[SPL];
+  if constexpr (HOIST) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) vload<SPL, true>(gen(p.u_prev) + (row + c) * ld + s0, up_h[c]);
+    if constexpr (std::is_same<AT, double>::value) {
+      vload<SPL, true>(static_cast<const double*>(gen(p.minv)) + ms, minv_h);
+    } else {
+      float mf[SPL];
+      vload<SPL, true>(static_cast<const float*>(gen(p.minv)) + ms, mf);
+#pragma unroll
+      for (int i = 0; i < SPL; ++i) minv_h[i] = (double)mf[i];
+    }
+  }
   AT r[3][SPL];
   constexpr bool UNI = LPN == 64;
   if constexpr (SHARED) gather_blocks<AT, ST, SPL, UNI>(p, node, ld, s0, U, ua, r);
   else gather_apply<AT, ST, SPL, UNI>(p, node, ld, s0, U, ua, r);
 
-  const double g = maybe_uni<UNI>(gen(p.gtab)[j]);
-  const unsigned fx = maybe_uni<UNI>((unsigned)gen(p.fixed)[node]);
-  const int64_t ms = (int64_t)node * ld + s0;
+  const double g = maybe_uni<UNI>(cst(p.gtab)[j]);
+  const unsigned fx = maybe_uni<UNI>((unsigned)cst(p.fixed)[node]);
   double un[3][SPL];
   double uo[3][SPL];  // u_n as the QoI sees it
   if constexpr (MODE == kStateF64) {
@@ -283,7 +333,10 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int j, int node, in
 #pragma unroll
       for (int i = 0; i < SPL; ++i) uo[c][i] = ua[c][i];
     double minv[SPL];
-    if constexpr (std::is_same<AT, double>::value) {
+    if constexpr (HOIST) {
+#pragma unroll
+      for (int i = 0; i < SPL; ++i) minv[i] = minv_h[i];
+    } else if constexpr (std::is_same<AT, double>::value) {
       vload<SPL, true>(static_cast<const double*>(gen(p.minv)) + ms, minv);
     } else {
       float mf[SPL];
@@ -298,8 +351,13 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int j, int node, in
     for (int c = 0; c < 3; ++c) {
       const int64_t idx = (row + c) * ld + s0;
       double up[SPL];
-      vload<SPL, true>(gen(p.u_prev) + idx, up);
-      const double fc = g * maybe_uni<UNI>(gen(p.F)[row + c]);
+      if constexpr (HOIST) {
+#pragma unroll
+        for (int i = 0; i < SPL; ++i) up[i] = up_h[c][i];
+      } else {
+        vload<SPL, true>(gen(p.u_prev) + idx, up);
+      }
+      const double fc = g * maybe_uni<UNI>(cst(p.F)[row + c]);
 #pragma unroll
       for (int i = 0; i < SPL; ++i) {
         const double acc = (dt2 * minv[i]) * (fc - (double)r[c][i]);
@@ -329,7 +387,7 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int j, int node, in
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int64_t idx = (row + c) * ld + s0;
-      const float fc = (float)(g * maybe_uni<UNI>(gen(p.F)[row + c]));
+      const float fc = (float)(g * maybe_uni<UNI>(cst(p.F)[row + c]));
       float vel[SPL], cc[SPL], uh[SPL];
       vload<SPL, true>(gen(p.v) + idx, vel);
       if constexpr (MODE == kStateF32Kahan) vload<SPL, true>(gen(p.uc) + idx, cc);
@@ -366,9 +424,9 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int j, int node, in
     }
   }
   if constexpr (QOI) {
-    const double e0 = maybe_uni<UNI>(gen(p.radial)[row + 0]);
-    const double e1 = maybe_uni<UNI>(gen(p.radial)[row + 1]);
-    const double e2 = maybe_uni<UNI>(gen(p.radial)[row + 2]);
+    const double e0 = maybe_uni<UNI>(cst(p.radial)[row + 0]);
+    const double e1 = maybe_uni<UNI>(cst(p.radial)[row + 1]);
+    const double e2 = maybe_uni<UNI>(cst(p.radial)[row + 2]);
     if constexpr (LPN == 64) {
       // q is only touched where the radial displacement turns: a rise that
       // continues from the running peak keeps the at-max bit, a fall from it
@@ -478,11 +536,12 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(const BatchTile* __restri
 #pragma nounroll
   for (int t = beg + rank; t < end; t += per) {
     // tile and mesh arguments are uniform: keep them in scalar registers
-    const int mesh = __builtin_amdgcn_readfirstlane(tiles[t].mesh);
-    const int node0 = __builtin_amdgcn_readfirstlane(tiles[t].node0);
-    const int count = __builtin_amdgcn_readfirstlane(tiles[t].count);
-    const int sample0 = __builtin_amdgcn_readfirstlane(tiles[t].sample0);
-    const StepArgs& p = desc[2 * mesh + (j & 1)];
+    const ConstPtr<BatchTile> tile = cst(tiles) + t;
+    const int mesh = __builtin_amdgcn_readfirstlane(tile->mesh);
+    const int node0 = __builtin_amdgcn_readfirstlane(tile->node0);
+    const int count = __builtin_amdgcn_readfirstlane(tile->count);
+    const int sample0 = __builtin_amdgcn_readfirstlane(tile->sample0);
+    const StepArgs p = load_args(desc + 2 * mesh + (j & 1));
 #pragma nounroll
     for (int n = wave; n < count; n += kBlock / 64) {
       const int node = __builtin_amdgcn_readfirstlane(node0 + n);

@@ -283,7 +283,14 @@ class Ensemble:
         return mean, var
 
     def apply(self, U, R, prec: int = F64, stream=None):
-        """R = K(Eh) U on CUDA tensors of shape [n_dof, S_pad]."""
+        """R = K(Eh) U on contiguous CUDA tensors of shape [n_dof, S_pad]
+        (float64 for F64, float32 for F32), rows in the mesh's node order."""
+        import torch
+        want = torch.float64 if prec == F64 else torch.float32
+        shape = (3 * self.n_nodes, self.info()["S_pad"])
+        for name, t in (("U", U), ("R", R)):
+            if not (t.is_cuda and t.dtype == want and tuple(t.shape) == shape and t.is_contiguous()):
+                raise ValueError(f"apply: {name} must be a contiguous CUDA {want} tensor of shape {shape}")
         self._check(self._lib.ens_apply(self._h, prec, U.data_ptr(), R.data_ptr(), _stream_handle(stream)))
 
     def save(self) -> bytes:

@@ -391,3 +391,73 @@ def test_shared_variant_rejected_for_sample_dependent_stiffness():
         ens.bind_workspace()
     assert ei.value.code == ensfem.ENS_EUNSUPPORTED
     ens.close()
+
+
+def test_caller_numbering_invariance():
+    """The library reorders nodes and elements internally; a caller that
+    numbers the same mesh differently gets the same results in its own
+    numbering (state, peak, moments, stand-alone apply), up to the rounding
+    of a different summation order."""
+    say("case: caller numbering invariance (33x17, S=24)")
+    cs = small_case(33, 17, 24, seed=5)
+    m = cs.mesh
+    rng = np.random.default_rng(11)
+    pn = rng.permutation(m.n_nodes)            # new caller index -> old node
+    pe = rng.permutation(m.n_el)
+    inv = np.empty_like(pn)
+    inv[pn] = np.arange(m.n_nodes)
+    m2 = inputs.Mesh(xyz=m.xyz[pn], tri=inv[m.tri[pe]].astype(np.int32), fixed=m.fixed[pn],
+                     radial=m.radial[pn], axial=m.axial[pn], length=m.length, n_theta=m.n_theta,
+                     n_z=m.n_z, name="permuted")
+    u0 = 1e-4 * rng.standard_normal((m.n_dof, 24))
+    u0.reshape(m.n_nodes, 3, 24)[m.fixed.astype(bool)] = 0.0
+    u0_2 = u0.reshape(m.n_nodes, 3, 24)[pn].reshape(m.n_dof, 24)
+    a = ensfem.setup_case(m, cs.eh, cs.h, cs.F, alpha=50.0, kind=ensfem.LOAD_RAMP_SINE, t_ramp=1e-3)
+    b = ensfem.setup_case(m2, cs.eh[pe], cs.h[pe], cs.F[pn], alpha=50.0, kind=ensfem.LOAD_RAMP_SINE, t_ramp=1e-3)
+    for e, u in ((a, u0), (b, u0_2)):
+        e.init_state(u)
+        e.step(300, cs.dt)
+        e.sync()
+    ua = a.read_state().reshape(m.n_nodes, 3, 24)[pn].reshape(m.n_dof, 24)
+    assert rel_l2(b.read_state(), ua) < 1e-12
+    assert rel_l2(b.read_qoi(), a.read_qoi()[pn]) < 1e-12
+    (ma, va), (mb, vb) = a.moments(), b.moments()
+    assert rel_l2(mb, ma[pn]) < 1e-12 and rel_l2(vb, va[pn]) < 1e-10
+    ld = a.info()["S_pad"]
+    U = torch.randn(m.n_dof, ld, dtype=torch.float64, device="cuda")
+    U2 = U.view(m.n_nodes, 3, ld)[torch.as_tensor(pn, device="cuda")].reshape(m.n_dof, ld).contiguous()
+    Ra, Rb = torch.empty_like(U), torch.empty_like(U)
+    a.apply(U, Ra, ensfem.F64)
+    b.apply(U2, Rb, ensfem.F64)
+    torch.cuda.synchronize()
+    Ra2 = Ra.view(m.n_nodes, 3, ld)[torch.as_tensor(pn, device="cuda")].reshape(m.n_dof, ld)
+    assert float((Rb - Ra2).norm() / Ra2.norm()) < 1e-13
+    with pytest.raises(ValueError):
+        a.apply(U[:, :8].contiguous(), Ra, ensfem.F64)
+    a.close()
+    b.close()
+
+
+def test_precision_ladder_on_a_fine_mesh():
+    """Precision modes against the FP64 path on a fine mesh (28,800 nodes,
+    element size ~0.026 cm on a 1 cm radius), 4,000 steps of a ramped load:
+    the FP32 apply with an FP64 state stays within 1e-7; both FP32 states
+    (their error is dominated by the FP32 velocity, which the Kahan update of
+    u does not touch) within 1e-5, the Kahan one no worse than the plain."""
+    say("case: fine cylinder 240x120, S=8, 4000 steps, precision modes")
+    cs = small_case(240, 120, 8, seed=21, R=1.0, L=2.0)
+    out = {}
+    for name, ap, st in (("ref", ensfem.F64, ensfem.STATE_F64), ("f64", ensfem.F32, ensfem.STATE_F64),
+                         ("kahan", ensfem.F32, ensfem.STATE_F32_KAHAN), ("f32", ensfem.F32, ensfem.STATE_F32)):
+        e = ensfem.setup_case(cs.mesh, cs.eh, cs.h, cs.F, alpha=50.0, kind=ensfem.LOAD_RAMP_SINE, t_ramp=2e-3,
+                              apply_prec=ap, state_prec=st)
+        e.init_state()
+        e.step(4000, cs.dt)
+        e.sync()
+        out[name] = e.read_state()
+        e.close()
+    err = {k: rel_l2(out[k], out["ref"]) for k in ("f64", "kahan", "f32")}
+    say(f"  against FP64: " + ", ".join(f"{k} {v:.2e}" for k, v in err.items()))
+    assert err["f64"] <= 1e-7
+    assert err["kahan"] <= 1e-5 and err["f32"] <= 1e-5
+    assert err["kahan"] <= 1.01 * err["f32"]
