@@ -89,7 +89,7 @@ def cpu_baseline(mesh, eh, h, F, cfg, dt, budget_s: float = 20.0) -> dict:
     t0 = time.perf_counter()
     kh, A, _ = element.reference_stiffness(mesh.xyz, mesh.tri, cfg["nu"], cfg["shear_k"])
     t_el = time.perf_counter() - t0
-    steps, samples = 20, [0]
+    steps, samples = 40, [0]
     t0 = time.perf_counter()
     stepper.run_ensemble(mesh.tri, kh, A, eh, h, cfg["rho"], F, mesh.fixed, mesh.radial, dt, steps,
                          cfg["alpha"], lambda t: 1.0, samples=samples)
@@ -97,7 +97,7 @@ def cpu_baseline(mesh, eh, h, F, cfg, dt, budget_s: float = 20.0) -> dict:
     # grow the sample within the budget
     more = max(0, int((budget_s - t_el - t1) / max(t1, 1e-3)))
     if more:
-        extra = list(range(1, 1 + min(more, 7)))
+        extra = list(range(1, 1 + min(more, 15)))
         t0 = time.perf_counter()
         stepper.run_ensemble(mesh.tri, kh, A, eh, h, cfg["rho"], F, mesh.fixed, mesh.radial, dt, steps,
                              cfg["alpha"], lambda t: 1.0, samples=extra)
