@@ -52,6 +52,11 @@ int32_t sur_forward(sur_net* s, const float* X, int32_t batch, float* Y, void* s
  * FP32 scalar) may be NULL.  No update. */
 int32_t sur_gradients(sur_net* s, const float* X, const float* T, int32_t batch, float* grad, float* loss,
                       void* stream);
+/* Decoupled weight decay for the following Adam steps (AdamW, Loshchilov &
+ * Hutter 2019): each step subtracts lr * wd * W from every weight matrix W
+ * besides the Adam update; biases are not decayed.  Default 0.  ENS_EINVAL
+ * for a negative or non-finite wd. */
+int32_t sur_set_weight_decay(sur_net* s, float wd);
 /* One Adam step with step size lr on the batch (X, T device FP32); the
  * batch loss before the step goes to *loss (device FP32) if non-NULL. */
 int32_t sur_train_step(sur_net* s, const float* X, const float* T, int32_t batch, float lr, float* loss,

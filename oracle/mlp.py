@@ -9,13 +9,16 @@ peak radial displacement: layers W_l [out, in], b_l [out]; every hidden
 layer is z = W h + b, h' = GELU(z) with the exact erf form
 GELU(x) = x/2 (1 + erf(x / sqrt 2)); the output layer is linear.  Loss:
 mean squared error over the batch and outputs, L = 1/(B n) sum (y - t)^2.
-Adam (Kingma & Ba 2015) with bias correction.
+Adam (Kingma & Ba 2015) with bias correction; optional decoupled weight
+decay on the weight matrices (AdamW, Loshchilov & Hutter 2019): the step
+adds lr * wd * W to the Adam update of W, biases are not decayed.
 
 Pins (tests/test_oracle_mlp.py): central finite differences of the loss
 against backward() on a small network; GELU identities
 GELU(x) - GELU(-x) = x and GELU(0) = 0 and its derivative against a finite
 difference; a linear single-layer network whose gradient is X^T dY in closed
-form; one Adam step against the update written from its definition.
+form; one Adam step against the update written from its definition; weight
+decay alone (zero gradient) shrinks W by exactly (1 - lr wd) and leaves b.
 """
 from __future__ import annotations
 
@@ -72,17 +75,18 @@ def backward(params, cache, Y, T):
     return grads
 
 
-def adam_step(params, grads, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
-    """One Adam step (t counts from 1).  m, v: lists like params."""
+def adam_step(params, grads, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8, weight_decay=0.0):
+    """One Adam step (t counts from 1).  m, v: lists like params.
+    weight_decay: decoupled decay of the weight matrices (not the biases)."""
     out_p, out_m, out_v = [], [], []
     for (W, b), (gW, gb), (mW, mb), (vW, vb) in zip(params, grads, m, v):
         new = []
-        for p, g, mm, vv in ((W, gW, mW, vW), (b, gb, mb, vb)):
+        for p, g, mm, vv, wd in ((W, gW, mW, vW, weight_decay), (b, gb, mb, vb, 0.0)):
             mm = b1 * mm + (1.0 - b1) * g
             vv = b2 * vv + (1.0 - b2) * g * g
             mhat = mm / (1.0 - b1 ** t)
             vhat = vv / (1.0 - b2 ** t)
-            new.append((p - lr * mhat / (np.sqrt(vhat) + eps), mm, vv))
+            new.append((p - lr * (mhat / (np.sqrt(vhat) + eps) + wd * p), mm, vv))
         out_p.append((new[0][0], new[1][0]))
         out_m.append((new[0][1], new[1][1]))
         out_v.append((new[0][2], new[1][2]))

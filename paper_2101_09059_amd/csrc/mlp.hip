@@ -57,6 +57,7 @@ struct GemmArgs {
   float* M2;
   __bf16* W16;
   float lr, b1, b2, eps, c1, c2;
+  float wd;  // decoupled weight decay of the weight matrix
 };
 
 __device__ __forceinline__ float gelu_f(float x) {
@@ -207,7 +208,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
           } else if constexpr (EPI == EPI_ADAM) {
             const float m1 = fmaf(g.b1, g.M1[idx], (1.f - g.b1) * v);
             const float m2 = fmaf(g.b2, g.M2[idx], (1.f - g.b2) * v * v);
-            const float wv = g.W32[idx] - g.lr * (m1 * g.c1) / (sqrtf(m2 * g.c2) + g.eps);
+            const float w0 = g.W32[idx];
+            const float wv = w0 - g.lr * ((m1 * g.c1) / (sqrtf(m2 * g.c2) + g.eps) + g.wd * w0);
             g.M1[idx] = m1;
             g.M2[idx] = m2;
             g.W32[idx] = wv;
@@ -374,6 +376,7 @@ struct sur_net {
          o_dh = 0, o_dz32 = 0, o_dz16 = 0, o_split = 0, o_db = 0, o_p1 = 0, o_p2 = 0, o_s1 = 0, o_s2 = 0,
          o_lpart = 0, o_loss = 0, total = 0;
   int splits_max = 64;
+  float wd = 0.0f;  // decoupled weight decay (weight matrices only)
   bool bound = false, have_params = false;
   int64_t t = 0;  // Adam steps taken
   int32_t fail(int32_t c, const std::string& m) {
@@ -550,6 +553,7 @@ int32_t backward_weight(sur_net* s, int layer, const __bf16* dZ, const __bf16* H
     g.eps = 1e-8f;
     g.c1 = c1;
     g.c2 = c2;
+    g.wd = s->wd;
     SHIPC((gemm<false, false, EPI_ADAM>(g, 1, st)));
   }
   return ENS_OK;
@@ -675,6 +679,13 @@ int32_t sur_bind_workspace(sur_net* s, void* dptr, size_t bytes) {
   s->ws_bytes = bytes;
   s->bound = true;
   s->have_params = false;
+  return ENS_OK;
+}
+
+int32_t sur_set_weight_decay(sur_net* s, float wd) {
+  if (!s) return ENS_EINVAL;
+  if (!(wd >= 0.0f) || !std::isfinite(wd)) return s->fail(ENS_EINVAL, "sur_set_weight_decay: need a finite wd >= 0");
+  s->wd = wd;
   return ENS_OK;
 }
 

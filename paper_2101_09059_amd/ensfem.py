@@ -103,6 +103,7 @@ _SIGS = {
     "sur_get_params": (_I32, [_P, _P]),
     "sur_forward": (_I32, [_P, _P, _I32, _P, _P]),
     "sur_gradients": (_I32, [_P, _P, _P, _I32, _P, _P, _P]),
+    "sur_set_weight_decay": (_I32, [_P, ctypes.c_float]),
     "sur_train_step": (_I32, [_P, _P, _P, _I32, ctypes.c_float, _P, _P]),
     "sur_moments": (_I32, [_P, _P, _I64, _P, _P, _P]),
     "sur_cv_moments": (_I32, [_P, _P, _I64, _I32, _P, _P, _I64, _P, _P, _P, _P]),
@@ -413,6 +414,10 @@ class Surrogate:
         self._check(self._lib.sur_gradients(self._h, X.contiguous().data_ptr(), T.contiguous().data_ptr(),
                                             X.shape[0], g.data_ptr(), self._loss.data_ptr(), _stream_handle(stream)))
         return g, self._loss
+
+    def set_weight_decay(self, wd: float):
+        """Decoupled weight decay of the weight matrices for later steps."""
+        self._check(self._lib.sur_set_weight_decay(self._h, float(wd)))
 
     def train_step(self, X, T, lr: float, stream=None):
         """One Adam step; returns the device loss scalar (before the step)."""

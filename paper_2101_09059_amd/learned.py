@@ -90,20 +90,26 @@ class Network:
         self.train_seconds = 0.0
 
     def fit(self, X: np.ndarray, Q: np.ndarray, epochs: int, batch: int, lr: float, seed: int,
-            holdout: float = 0.1):
-        """X [N, n_in], Q [N, n_out] physical targets.  Returns the held-out
-        relative RMSE (physical units) and the loss history."""
+            holdout: float = 0.1, val: float = 0.0, weight_decay: float = 0.0, eval_every: int = 10):
+        """X [N, n_in], Q [N, n_out] physical targets.  A `holdout` share is
+        kept out for the reported relative RMSE; with `val` > 0 a further
+        share is used for early stopping (the parameters with the lowest
+        validation RMSE, checked every `eval_every` epochs, are kept).
+        Returns the held-out relative RMSE (physical units) and the loss
+        history (last batch loss of each epoch)."""
         import torch
         rng = np.random.default_rng(seed)
         N = X.shape[0]
         perm = rng.permutation(N)
         n_hold = max(1, int(round(holdout * N)))
-        hold, train = perm[:n_hold], perm[n_hold:]
+        n_val = int(round(val * N))
+        hold, vset, train = perm[:n_hold], perm[n_hold:n_hold + n_val], perm[n_hold + n_val:]
         self.mu = Q[train].mean(axis=0)
         sd = Q[train].std(axis=0)
         # outputs that never vary (clamped nodes) are predicted by their mean
         self.sd = np.where(sd > 0, sd, 0.0)
         scale = np.where(sd > 0, sd, 1.0)
+        self.net.set_weight_decay(weight_decay)
         dev = "cuda"
         Xt = torch.as_tensor(X[train], dtype=torch.float32, device=dev)
         Tt = torch.as_tensor((Q[train] - self.mu) / scale, dtype=torch.float32, device=dev)
@@ -111,6 +117,8 @@ class Network:
         steps_per_epoch = int(math.ceil(n_tr / batch))
         total = epochs * steps_per_epoch
         hist = []
+        best = (np.inf, None, 0)
+        self.val_history = []
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         step = 0
@@ -124,6 +132,15 @@ class Network:
                 loss = self.net.train_step(xb, tb, lr_t)
                 step += 1
             hist.append(float(loss.item()))
+            if n_val and ((ep + 1) % eval_every == 0 or ep + 1 == epochs):
+                pv = self.predict(X[vset])
+                e = float(np.linalg.norm(pv - Q[vset]) / np.linalg.norm(Q[vset]))
+                self.val_history.append((ep + 1, e))
+                if e < best[0]:
+                    best = (e, self.net.get_params(), ep + 1)
+        if best[1] is not None:
+            self.net.set_params(best[1])
+        self.best_epoch = best[2] if best[1] is not None else epochs
         torch.cuda.synchronize()
         self.train_seconds += time.perf_counter() - t0
         pred = self.predict(X[hold])

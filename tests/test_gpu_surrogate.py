@@ -75,7 +75,8 @@ def test_gradients_match_oracle(sizes, batch):
     net.close()
 
 
-def test_adam_step_matches_oracle():
+@pytest.mark.parametrize("wd", [0.0, 0.3])
+def test_adam_step_matches_oracle(wd):
     sizes, batch = [32, 64, 64, 48], 32
     params = _net(sizes, seed=11)
     rng = np.random.default_rng(3)
@@ -84,6 +85,7 @@ def test_adam_step_matches_oracle():
     net = ensfem.Surrogate(sizes[0], sizes[1], 2, sizes[-1], max_batch=batch)
     p0 = ensfem.flatten_params(params)
     net.set_params(p0)
+    net.set_weight_decay(wd)
     lr = 1e-3
     Xt = torch.as_tensor(X, dtype=torch.float32, device="cuda")
     Tt = torch.as_tensor(T, dtype=torch.float32, device="cuda")
@@ -94,7 +96,7 @@ def test_adam_step_matches_oracle():
     gl = ensfem.unflatten_params(g_gpu, sizes)
     zeros = [(np.zeros_like(W), np.zeros_like(b)) for W, b in gl]
     p0l = ensfem.unflatten_params(p0.astype(np.float64), sizes)
-    newp, _, _ = mlp.adam_step(p0l, gl, zeros, zeros, 1, lr)
+    newp, _, _ = mlp.adam_step(p0l, gl, zeros, zeros, 1, lr, weight_decay=wd)
     ref = ensfem.flatten_params(newp).astype(np.float64)
     assert np.max(np.abs(p1 - ref)) <= 1e-6
     # and follow the FP64 oracle's step direction on almost every entry

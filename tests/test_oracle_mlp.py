@@ -67,6 +67,19 @@ def test_adam_step_definition():
     assert np.allclose(v[0][0], 0.001 * np.array([[0.01, 0.04]]))
 
 
+def test_weight_decay_alone_shrinks_weights_only():
+    """Decoupled weight decay with a zero gradient: the Adam part is 0, the
+    weights shrink by exactly (1 - lr wd), the biases do not move."""
+    rng = np.random.default_rng(4)
+    p = [(rng.standard_normal((3, 4)), rng.standard_normal(3)), (rng.standard_normal((2, 3)), rng.standard_normal(2))]
+    g = [(np.zeros_like(W), np.zeros_like(b)) for W, b in p]
+    newp, _, _ = mlp.adam_step(p, g, g, g, 1, 0.05, weight_decay=0.2)
+    for (W, b), (W1, b1) in zip(p, newp):
+        assert np.array_equal(W1, W - 0.05 * (0.0 + 0.2 * W))
+        assert np.allclose(W1, W * (1 - 0.01), rtol=1e-15)
+        assert np.array_equal(b1, b)
+
+
 def test_he_init_scale():
     rng = np.random.default_rng(2)
     W, b = mlp.init_params([400, 300], rng)[0]
