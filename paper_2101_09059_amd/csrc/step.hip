@@ -183,9 +183,7 @@ __device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int i = 0; i < SPL; ++i) r[c][i] = AT(0);
-  // differences to the node, rounded once to the apply precision; the
-  // second neighbour's are kept for the next element of the walk
-  AT db[3][SPL], dc[3][SPL];
+  ST ub[3][SPL], uc[3][SPL];
   ENSFEM_UNROLL_GATHER
   for (int k = kb; k < ke; ++k) {
     const int64_t e = maybe_uni<UNI>(cst(p.adj.el)[k]);
@@ -201,30 +199,24 @@ __device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_
     if (bc.x >= 0) {
       const int64_t rb = node_row<MAP>(map, bc.x);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        ST ub[SPL];
-        vload<SPL, false>(U + (rb + c) * ld + s0, ub);
-#pragma unroll
-        for (int i = 0; i < SPL; ++i) db[c][i] = (AT)(ub[i] - ua[c][i]);
-      }
+      for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (rb + c) * ld + s0, ub[c]);
     } else {
 #pragma unroll
       for (int c = 0; c < 3; ++c)
 #pragma unroll
-        for (int i = 0; i < SPL; ++i) db[c][i] = dc[c][i];
+        for (int i = 0; i < SPL; ++i) ub[c][i] = uc[c][i];
     }
     const int64_t rc = node_row<MAP>(map, bc.y);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      ST uc[SPL];
-      vload<SPL, false>(U + (rc + c) * ld + s0, uc);
-#pragma unroll
-      for (int i = 0; i < SPL; ++i) dc[c][i] = (AT)(uc[i] - ua[c][i]);
-    }
+    for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (rc + c) * ld + s0, uc[c]);
 #pragma unroll
     for (int i = 0; i < SPL; ++i) {
-      const AT d0 = db[0][i], d1 = db[1][i], d2 = db[2][i];
-      const AT d3 = dc[0][i], d4 = dc[1][i], d5 = dc[2][i];
+      const AT d0 = (AT)(ub[0][i] - ua[0][i]);
+      const AT d1 = (AT)(ub[1][i] - ua[1][i]);
+      const AT d2 = (AT)(ub[2][i] - ua[2][i]);
+      const AT d3 = (AT)(uc[0][i] - ua[0][i]);
+      const AT d4 = (AT)(uc[1][i] - ua[1][i]);
+      const AT d5 = (AT)(uc[2][i] - ua[2][i]);
       const AT f0 = row6(kk + 0, d0, d1, d2, d3, d4, d5);
       const AT f1 = row6(kk + 6, d0, d1, d2, d3, d4, d5);
       const AT f2 = row6(kk + 12, d0, d1, d2, d3, d4, d5);
