@@ -200,7 +200,7 @@ def run_learned_config(args, torch):
         X = learned.draw_xi(seed, n, c["n_modes"])
         qs = []
         for i in range(0, n, S):
-            qs.append(prob.solve(X[i:i + S]))
+            qs.append(prob.solve(X[i:i + S], progress=lambda m: log(f"    batch {i // S}: {m}")))
             log(f"  solved {i + S}/{n} (seed {seed}), solver time {prob.solve_seconds:.0f} s")
         return X, np.concatenate(qs, axis=1)
 
@@ -215,7 +215,7 @@ def run_learned_config(args, torch):
     del Qtr
     Xh = learned.draw_xi(sd["hf"], c["n_hf"], c["n_modes"])
     t0 = prob.solve_seconds
-    qH, (pm, pv) = prob.solve(Xh, return_moments=True)
+    qH, (pm, pv) = prob.solve(Xh, return_moments=True, progress=lambda m: log(f"    high fidelity: {m}"))
     t_hf = prob.solve_seconds - t0
     qL = net.predict(Xh).T
     Xl = learned.draw_xi(sd["lf"], c["n_lf"], c["n_modes"])
@@ -269,8 +269,8 @@ def run_precision_config(args, torch):
     """Precision form at full size: 1M-node curved tapered tube, S = 1,024,
     sine-ramped pulsatile pressure with axial taper and wall shear.
     Throughput of each precision mode at S = 1,024, and the error of each
-    FP32 mode against the FP64 path over a longer run on the first 64
-    sample columns (same mesh, fields and load)."""
+    FP32 mode against the FP64 path over a longer run on the first sample
+    columns (same mesh, fields and load)."""
     from paper_2101_09059_amd import ensfem, inputs
     cfg = inputs.CONFIGS["c3_curved"]
     t0 = time.perf_counter()
@@ -315,7 +315,7 @@ def run_precision_config(args, torch):
         thr[name] = dict(ms_per_step=ms, value=mesh.n_dof * S / (ms * 1e-3), achieved_GBs=b / (ms * 1e-3) / 1e9)
         log(f"{name}: {ms:.3f} ms/step, {thr[name]['achieved_GBs']:.0f} GB/s algorithmic")
 
-    n_acc, S_acc = args.c3_error_steps, 64
+    n_acc, S_acc = args.c3_error_steps, args.c3_error_samples
     e_acc, h_acc = np.ascontiguousarray(eh[:, :S_acc]), np.ascontiguousarray(h[:, :S_acc])
     del eh, h
     ref_u = ref_q = None
@@ -371,7 +371,9 @@ def main():
                          "1M nodes x 1,024 samples (about 6 GPU-minutes); c4_batch: the batching form; "
                          "c5_learned: the learned form (about 12 GPU-minutes)")
     ap.add_argument("--c3-error-steps", type=int, default=20000,
-                    help="c3_curved: steps of the error run on 64 sample columns")
+                    help="c3_curved: steps of the error run")
+    ap.add_argument("--c3-error-samples", type=int, default=64,
+                    help="c3_curved: sample columns of the error run (the first ones of the ensemble)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 10 times (counter calibration)")
     args = ap.parse_args()

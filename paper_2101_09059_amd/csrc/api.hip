@@ -1003,6 +1003,9 @@ int32_t ens_moments(ens_ctx* ctx, double* mean, double* var) {
   return ENS_OK;
 }
 
+#ifndef ENSFEM_APPLY_WIDE
+#define ENSFEM_APPLY_WIDE 0
+#endif
 int32_t ens_apply(ens_ctx* ctx, int32_t prec, const void* U_dev, void* R_dev, void* stream) {
   if (!ctx) return ENS_EINVAL;
   if (!ctx->bound) return ctx->fail(ENS_EWORKSPACE, "ens_apply: bind a workspace first");
@@ -1010,7 +1013,12 @@ int32_t ens_apply(ens_ctx* ctx, int32_t prec, const void* U_dev, void* R_dev, vo
   if (!U_dev || !R_dev) return ctx->fail(ENS_EINVAL, "ens_apply: null device buffer");
   HIPC(hipSetDevice(ctx->device));
   StepArgs a = base_args(ctx, prec == ENS_F32);
-  HIPC(launch_apply(a, prec == ENS_F32, ctx->SB, use_shared(ctx), U_dev, R_dev, ctx->p<int32_t>(ctx->L.perm),
+  // the apply alone holds fewer values per sample than the step: a wave
+  // can take 4 samples per lane where the padded width allows
+  int sb = ctx->SB;
+  if (ENSFEM_APPLY_WIDE && sb >= 64 && ctx->ld % 256 == 0) sb = 256;
+  a.n_sb = ctx->ld / sb;
+  HIPC(launch_apply(a, prec == ENS_F32, sb, use_shared(ctx), U_dev, R_dev, ctx->p<int32_t>(ctx->L.perm),
                     static_cast<hipStream_t>(stream)));
   return ENS_OK;
 }

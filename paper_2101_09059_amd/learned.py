@@ -41,16 +41,22 @@ class Problem:
     def fields(self, xi: np.ndarray):
         return inputs.kl_fields(self.mesh, self.lam, self.phi, xi[:, :self.n_modes], xi[:, self.n_modes:])
 
-    def solve(self, xi: np.ndarray, return_moments: bool = False):
-        """Plain solver on the samples xi [S, 2 n_modes]; q [n_nodes, S]."""
+    def solve(self, xi: np.ndarray, return_moments: bool = False, progress=None):
+        """Plain solver on the samples xi [S, 2 n_modes]; q [n_nodes, S].
+        progress(str): optional callback told about each stage."""
         import torch
         c = self.cfg
+        say = progress or (lambda m: None)
+        t_a = time.perf_counter()
         eh, h = self.fields(xi)
+        say(f"fields {time.perf_counter() - t_a:.1f} s")
         ens = ensfem.setup_case(self.mesh, eh, h, self.F, nu=c["nu"], shear_k=c["shear_k"], rho=c["rho"],
                                 alpha=c["alpha"], kind=ensfem.LOAD_PULSATILE, t_ramp=c["T_ramp"],
                                 amp=c["pulse_amp"], period=c["period"], apply_prec=ensfem.F32)
+        del eh, h
         dt = ens.cfl_dt(c["safety"])
         steps = int(math.ceil(c["window"] / dt))
+        say(f"set-up {time.perf_counter() - t_a:.1f} s, {steps} steps")
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         ens.init_state()
@@ -58,6 +64,7 @@ class Problem:
         ens.sync()
         self.solve_seconds += time.perf_counter() - t0
         self.solved += xi.shape[0]
+        say(f"stepped {time.perf_counter() - t_a:.1f} s")
         q = ens.read_qoi()
         mom = ens.moments() if return_moments else None
         ens.close()
