@@ -57,10 +57,16 @@ def step_kernel_bytes(n_nodes: int, n_el: int, S: int, apply_f32: bool, state: s
 
 
 def source_hash() -> str:
+    """Hash of what decides the fused step's memory traffic: the kernel
+    sources and the library's node ordering."""
     h = hashlib.sha256()
-    for f in ("step.hip", "internal.h", "api.hip"):
-        with open(os.path.join(ROOT, "paper_2101_09059_amd", "csrc", f), "rb") as fh:
+    csrc = os.path.join(ROOT, "paper_2101_09059_amd", "csrc")
+    for f in ("step.hip", "internal.h"):
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
+    api = open(os.path.join(csrc, "api.hip")).read()
+    i = api.index("void rcb_order(")
+    h.update(api[i:api.index("\n}\n", i)].encode())
     return h.hexdigest()[:16]
 
 
@@ -208,11 +214,13 @@ def run_learned_config(args, torch):
     Xtr, Qtr = solve_many(sd["train"], c["n_train"])
     t_data = prob.solve_seconds - t_data0
     net = learned.Network(2 * c["n_modes"], c["width"], c["n_hidden"], mesh.n_nodes, seed=sd["init"], max_batch=256)
-    rmse, hist = net.fit(Xtr, Qtr.T, epochs=c["epochs"], batch=c["batch"], lr=c["lr"], seed=sd["init"] + 1,
-                         val=c["val"], weight_decay=c["weight_decay"])
+    Qs = np.ascontiguousarray(Qtr.T)  # [samples][nodes]
+    del Qtr
+    rmse, hist = net.fit(Xtr, Qs, epochs=c["epochs"], batch=c["batch"], lr=c["lr"], seed=sd["init"] + 1,
+                         val=c["val"], weight_decay=c["weight_decay"], progress=log)
+    del Qs
     log(f"trained in {net.train_seconds:.1f} s: held-out rel RMSE {rmse:.4f}, loss {hist[0]:.3e} -> {hist[-1]:.3e}, "
         f"kept epoch {net.best_epoch}")
-    del Qtr
     Xh = learned.draw_xi(sd["hf"], c["n_hf"], c["n_modes"])
     t0 = prob.solve_seconds
     qH, (pm, pv) = prob.solve(Xh, return_moments=True, progress=lambda m: log(f"    high fidelity: {m}"))
@@ -323,8 +331,13 @@ def run_precision_config(args, torch):
     for name, ap, st, _ in modes:
         ens = make(e_acc, h_acc, ap, st)
         ens.init_state()
-        ens.step(n_acc, dt, stream=stream)
-        ens.sync()
+        done = 0
+        while done < n_acc:  # in chunks, with a progress line each
+            k = min(10000, n_acc - done)
+            ens.step(k, dt, stream=stream)
+            ens.sync()
+            done += k
+            log(f"  {name}: {done}/{n_acc} steps")
         u, q = ens.read_state(), ens.read_qoi()
         ens.close()
         del ens

@@ -1004,7 +1004,7 @@ int32_t ens_moments(ens_ctx* ctx, double* mean, double* var) {
 }
 
 #ifndef ENSFEM_APPLY_WIDE
-#define ENSFEM_APPLY_WIDE 0
+#define ENSFEM_APPLY_WIDE 1
 #endif
 int32_t ens_apply(ens_ctx* ctx, int32_t prec, const void* U_dev, void* R_dev, void* stream) {
   if (!ctx) return ENS_EINVAL;

@@ -97,13 +97,15 @@ class Network:
         self.train_seconds = 0.0
 
     def fit(self, X: np.ndarray, Q: np.ndarray, epochs: int, batch: int, lr: float, seed: int,
-            holdout: float = 0.1, val: float = 0.0, weight_decay: float = 0.0, eval_every: int = 10):
+            holdout: float = 0.1, val: float = 0.0, weight_decay: float = 0.0, eval_every: int = 10,
+            progress=None):
         """X [N, n_in], Q [N, n_out] physical targets.  A `holdout` share is
         kept out for the reported relative RMSE; with `val` > 0 a further
         share is used for early stopping (the parameters with the lowest
         validation RMSE, checked every `eval_every` epochs, are kept).
         Returns the held-out relative RMSE (physical units) and the loss
-        history (last batch loss of each epoch)."""
+        history (last batch loss of each epoch).  progress(str): optional
+        callback told about each validation check."""
         import torch
         rng = np.random.default_rng(seed)
         N = X.shape[0]
@@ -111,15 +113,18 @@ class Network:
         n_hold = max(1, int(round(holdout * N)))
         n_val = int(round(val * N))
         hold, vset, train = perm[:n_hold], perm[n_hold:n_hold + n_val], perm[n_hold + n_val:]
-        self.mu = Q[train].mean(axis=0)
-        sd = Q[train].std(axis=0)
+        Qtr = Q[train]
+        Qv, Xv = Q[vset], X[vset]
+        self.mu = Qtr.mean(axis=0)
+        sd = Qtr.std(axis=0)
         # outputs that never vary (clamped nodes) are predicted by their mean
         self.sd = np.where(sd > 0, sd, 0.0)
         scale = np.where(sd > 0, sd, 1.0)
         self.net.set_weight_decay(weight_decay)
         dev = "cuda"
         Xt = torch.as_tensor(X[train], dtype=torch.float32, device=dev)
-        Tt = torch.as_tensor((Q[train] - self.mu) / scale, dtype=torch.float32, device=dev)
+        Tt = torch.as_tensor((Qtr - self.mu) / scale, dtype=torch.float32, device=dev)
+        del Qtr
         n_tr = Xt.shape[0]
         steps_per_epoch = int(math.ceil(n_tr / batch))
         total = epochs * steps_per_epoch
@@ -140,11 +145,13 @@ class Network:
                 step += 1
             hist.append(float(loss.item()))
             if n_val and ((ep + 1) % eval_every == 0 or ep + 1 == epochs):
-                pv = self.predict(X[vset])
-                e = float(np.linalg.norm(pv - Q[vset]) / np.linalg.norm(Q[vset]))
+                pv = self.predict(Xv)
+                e = float(np.linalg.norm(pv - Qv) / np.linalg.norm(Qv))
                 self.val_history.append((ep + 1, e))
                 if e < best[0]:
                     best = (e, self.net.get_params(), ep + 1)
+                if progress:
+                    progress(f"  epoch {ep + 1}/{epochs}: loss {hist[-1]:.3e}, validation rel RMSE {e:.4f}")
         if best[1] is not None:
             self.net.set_params(best[1])
         self.best_epoch = best[2] if best[1] is not None else epochs
