@@ -116,6 +116,16 @@ int32_t ens_set_mesh(ens_ctx* ctx, int64_t n_nodes, const double* xyz, int64_t n
  * 0 <= nu < 0.5, shear_k >= 0, rho > 0 (g/cm^3), alpha >= 0 (1/s). */
 int32_t ens_set_material(ens_ctx* ctx, double nu, double shear_k, double rho, double alpha);
 
+/* Explicit viscous force (Sec. 2.3): f_v = -c_d du/dt is added to the load,
+ * with du/dt at t_n taken as (u_n - u_{n-1}) / dt so the step stays
+ * explicit (and as v_0 in the starter); one coefficient c_d >= 0 for every
+ * free dof, default 0.  The step's stability needs (omega dt)^2 < 4 -
+ * 2 c_d dt / m per mode and node mass m, so c_d dt / m should stay well
+ * below 1; the stability check of ens_step does not include this term.
+ * Resets the state (call ens_init_state again).  ENS_EINVAL for a negative
+ * or non-finite c_d. */
+int32_t ens_set_viscous(ens_ctx* ctx, double c_d);
+
 /* Ensemble fields: eh[n_el*S] = (E h)_{e,s} (element-wise product of
  * modulus and thickness, the scalar that multiplies the reference element
  * stiffness, Sec. 2.2.1 / Sec. 2.4) and h[n_el*S] thickness (lumped mass

@@ -10,11 +10,14 @@ eq. dynamicsCD with both mass matrices lumped reads, per dof,
     (1 + a) u_{n+1} = dt^2 (f_n - K u_n) / m + 2 u_n - (1 - a) u_{n-1},
     a = alpha dt / 2,
 
-with clamped dofs held at zero and f_n = g(t_n) F, t_n = n dt.
+with clamped dofs held at zero and f_n = g(t_n) F, t_n = n dt.  The
+optional explicit viscous force of Sec. 2.3, f_v = -c_d du/dt at t_n, is
+added to f_n with the backward difference du/dt ~ (u_n - u_{n-1}) / dt
+(one coefficient c_d per dof, the update stays explicit).
 
 Start (the paper does not state one): u_0, v_0 given (zero = at rest) and
-u_{-1} = u_0 - dt v_0 + dt^2/2 (M^-1 (f_0 - K u_0) - alpha v_0), the Taylor
-start; for a ramped load that starts at zero this is u_{-1} = u_0 = 0.
+u_{-1} = u_0 - dt v_0 + dt^2/2 (M^-1 (f_0 - K u_0 - c_d v_0) - alpha v_0), the
+Taylor start; for a ramped load that starts at zero this is u_{-1} = u_0 = 0.
 
 Outputs: u_N (and u_{N-1}), optional checkpoints, the running peak radial
 displacement q_i = max_{0<=n<=N} e_r,i . u_i(t_n), and the discrete energy
@@ -24,7 +27,8 @@ the undamped, unforced scheme conserves exactly.
 Pins (tests/test_oracle_stepper.py): single-mode closed form u_n = phi cos(n
 theta) with cos theta = 1 - (omega dt)^2 / 2 (and the damped characteristic
 roots), energy conservation and energy balance, monotone energy decay under
-damping, convergence to the static K^-1 f, and the starter's u_1.
+damping, convergence to the static K^-1 f, the starter's u_1, and the exact
+discrete energy balance of the viscous force.
 """
 from __future__ import annotations
 
@@ -57,7 +61,7 @@ def run_sample(K, m_node: np.ndarray, F: np.ndarray, fixed: np.ndarray, dt: floa
                alpha: float, g: Callable[[float], float], radial: Optional[np.ndarray] = None,
                u0: Optional[np.ndarray] = None, v0: Optional[np.ndarray] = None,
                u_prev: Optional[np.ndarray] = None, checkpoints: Sequence[int] = (),
-               energy_every: int = 0):
+               energy_every: int = 0, c_d: float = 0.0):
     """Step one sample.  K: scipy sparse [n_dof, n_dof]; m_node [n_nodes];
     F [n_dof]; fixed [n_dof] bool.  If u_prev is given it is u_{-1} and the
     starter is skipped.  Returns a dict with u (u_N), u_prev (u_{N-1}),
@@ -69,7 +73,7 @@ def run_sample(K, m_node: np.ndarray, F: np.ndarray, fixed: np.ndarray, dt: floa
     u[fixed] = 0.0
     if u_prev is None:
         v = np.zeros(n_dof) if v0 is None else np.array(v0, dtype=np.float64)
-        acc = minv * (g(0.0) * F - K @ u) - alpha * v
+        acc = minv * (g(0.0) * F - K @ u - c_d * v) - alpha * v
         u_prev = u - dt * v + 0.5 * dt * dt * acc
         u_prev[fixed] = 0.0
     else:
@@ -84,7 +88,7 @@ def run_sample(K, m_node: np.ndarray, F: np.ndarray, fixed: np.ndarray, dt: floa
     m_dof = np.repeat(m_node, 3)
     for n in range(n_steps):
         R = K @ u
-        f = g(n * dt) * F
+        f = g(n * dt) * F - c_d * (u - u_prev) / dt
         u_next = (dt * dt * minv * (f - R) + 2.0 * u - (1.0 - a) * u_prev) / (1.0 + a)
         u_next[fixed] = 0.0
         if energy_every and (n % energy_every == 0):
@@ -102,7 +106,7 @@ def run_ensemble(tri: np.ndarray, khat: np.ndarray, area: np.ndarray, eh: np.nda
                  rho: float, F: np.ndarray, fixed: np.ndarray, radial: np.ndarray, dt: float,
                  n_steps: int, alpha: float, g: Callable[[float], float],
                  checkpoints: Sequence[int] = (), energy_every: int = 0,
-                 samples: Optional[Sequence[int]] = None):
+                 samples: Optional[Sequence[int]] = None, c_d: float = 0.0):
     """S independent solves, sample by sample (no ensemble batching).
     eh, h [n_el, S]; F [n_nodes, 3]; fixed [n_nodes, 3]; radial [n_nodes, 3].
     Returns u [n_dof, S'], q [n_nodes, S'], checkpoints {n: [n_dof, S']},
@@ -117,7 +121,7 @@ def run_ensemble(tri: np.ndarray, khat: np.ndarray, area: np.ndarray, eh: np.nda
         K = assembly.assemble_stiffness(tri, khat, eh[:, s], n_nodes)
         m = assembly.lumped_mass(tri, area, h[:, s], rho, n_nodes)
         r = run_sample(K, m, Fd, fx, dt, n_steps, alpha, g, radial=radial,
-                       checkpoints=checkpoints, energy_every=energy_every)
+                       checkpoints=checkpoints, energy_every=energy_every, c_d=c_d)
         us.append(r["u"])
         qs.append(r["q"])
         en.append(r["energy"])

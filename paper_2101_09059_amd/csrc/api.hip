@@ -59,6 +59,7 @@ struct ens_ctx {
   std::vector<int2> adj_slot;
   // material
   double nu = 0.49, shear_k = 5.0 / 6.0, rho = 1.0, alpha = 0.0;
+  double cd = 0.0;  // explicit viscous force coefficient
   bool have_material = false;
   // ensemble (padded [n_el][ld])
   int32_t S = 0, ld = 0, SB = 0;
@@ -335,6 +336,7 @@ StepArgs base_args(const ens_ctx* c, bool f32) {
   a.qwords = (c->ld + 63) / 64;
   a.gtab = gptr(c->p<double>(c->L.gtab));
   a.energy_part = gptr(c->p<double>(c->L.epart));
+  a.cd = c->cd;
   return a;
 }
 
@@ -596,6 +598,15 @@ int32_t ens_set_material(ens_ctx* ctx, double nu, double shear_k, double rho, do
   return ENS_OK;
 }
 
+int32_t ens_set_viscous(ens_ctx* ctx, double c_d) {
+  if (!ctx) return ENS_EINVAL;
+  if (!(c_d >= 0.0) || !std::isfinite(c_d)) return ctx->fail(ENS_EINVAL, "ens_set_viscous: need a finite c_d >= 0");
+  ctx->gen++;
+  ctx->cd = c_d;
+  ctx->state_init = false;
+  return ENS_OK;
+}
+
 int32_t ens_set_ensemble(ens_ctx* ctx, int32_t S, const double* eh, const double* h) {
   if (!ctx) return ENS_EINVAL;
   ctx->gen++;
@@ -802,7 +813,8 @@ int32_t run_starter(ens_ctx* ctx, double dt, hipStream_t st) {
     }
     HIPC(launch_starter_f64((int32_t)ctx->n_nodes, ctx->ld, R, ctx->p<double>(L.minv64), ctx->p<double>(L.F),
                             ctx->p<uint8_t>(L.fixed), ctx->p<double>(L.u[ctx->cur]),
-                            ctx->p<double>(L.u[1 - ctx->cur]), ctx->p<double>(L.gtab), dt, ctx->alpha, st));
+                            ctx->p<double>(L.u[1 - ctx->cur]), ctx->p<double>(L.gtab), dt, ctx->alpha, ctx->cd,
+                            st));
   } else {
     float* R = ctx->p<float>(L.aux);
     if (ctx->u0_zero) {
@@ -813,7 +825,7 @@ int32_t run_starter(ens_ctx* ctx, double dt, hipStream_t st) {
     }
     HIPC(launch_starter_f32((int32_t)ctx->n_nodes, ctx->ld, R, ctx->p<float>(L.minv32), ctx->p<double>(L.F),
                             ctx->p<uint8_t>(L.fixed), ctx->p<float>(L.v), ctx->p<double>(L.gtab), dt,
-                            ctx->alpha, st));
+                            ctx->alpha, ctx->cd, st));
   }
   return ENS_OK;
 }

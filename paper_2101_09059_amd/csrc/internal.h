@@ -86,6 +86,7 @@ struct StepArgs {
   ENS_GLOBAL const double* gtab;  // load factors of the current chunk
   int32_t j;           // index into gtab
   double dt, a;        // step, alpha dt / 2
+  double cd;           // explicit viscous force coefficient (0: none)
   ENS_GLOBAL double* energy_part; // [n_nb][ld] per node-block energy partial sums
 };
 
@@ -133,10 +134,10 @@ hipError_t launch_energy_reduce(const double* part, int32_t n_nb, int32_t ld, in
 hipError_t launch_starter_f64(int32_t n_nodes, int32_t ld, const double* R, const double* minv,
                               const double* F, const uint8_t* fixed, const double* u0,
                               double* vprev_io, const double* gtab, double dt, double alpha,
-                              hipStream_t st);
+                              double cd, hipStream_t st);
 hipError_t launch_starter_f32(int32_t n_nodes, int32_t ld, const float* R, const float* minv,
                               const double* F, const uint8_t* fixed, float* v_io,
-                              const double* gtab, double dt, double alpha, hipStream_t st);
+                              const double* gtab, double dt, double alpha, double cd, hipStream_t st);
 hipError_t launch_split_f32(int64_t n, const double* u0, float* uh, float* uc, hipStream_t st);
 hipError_t launch_qoi_init(int32_t n_nodes, int32_t ld, const double* radial, const double* u_f64,
                            const float* uh, const float* uc, double* q, hipStream_t st);

@@ -360,7 +360,9 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int j, int node, in
       const double fc = g * maybe_uni<UNI>(cst(p.F)[row + c]);
 #pragma unroll
       for (int i = 0; i < SPL; ++i) {
-        const double acc = (dt2 * minv[i]) * (fc - (double)r[c][i]);
+        double acc = (dt2 * minv[i]) * (fc - (double)r[c][i]);
+        // explicit viscous force -c_d (u_n - u_{n-1}) / dt
+        if (p.cd != 0.0) acc = fma(-(p.dt * minv[i] * p.cd), ua[c][i] - up[i], acc);
         double v = fma(-oma, up[i], fma(2.0, ua[c][i], acc)) * inv1pa;
         if (fx & (1u << c)) v = 0.0;
         un[c][i] = v;
@@ -395,7 +397,9 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int j, int node, in
       for (int i = 0; i < SPL; ++i) {
         if constexpr (MODE == kStateF32Kahan) uo[c][i] = (double)ua[c][i] - (double)cc[i];
         else uo[c][i] = (double)ua[c][i];
-        const float acc = minv[i] * (fc - (float)r[c][i]);
+        float acc = minv[i] * (fc - (float)r[c][i]);
+        // explicit viscous force -c_d v_{n-1/2}
+        if (p.cd != 0.0) acc = fmaf(-(minv[i] * (float)p.cd), vel[i], acc);
         vel[i] = fmaf(dtf, acc, oma * vel[i]) * inv1pa;
         uh[i] = ua[c][i];
         if constexpr (MODE == kStateF32Kahan) {
@@ -627,7 +631,7 @@ __global__ __launch_bounds__(256) void k_starter_f64(int32_t n_nodes, int32_t ld
                                                      const double* __restrict__ u0,
                                                      double* __restrict__ vprev,
                                                      const double* __restrict__ gtab, double dt,
-                                                     double alpha) {
+                                                     double alpha, double cd) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= (int64_t)n_nodes * 3 * ld) return;
   const int64_t row = t / ld;
@@ -635,13 +639,13 @@ __global__ __launch_bounds__(256) void k_starter_f64(int32_t n_nodes, int32_t ld
   const int64_t node = row / 3;
   const int c = (int)(row % 3);
   const double v0 = vprev[t];
-  const double acc = minv[node * ld + s] * (gtab[0] * F[row] - R[t]) - alpha * v0;
+  const double acc = minv[node * ld + s] * (gtab[0] * F[row] - R[t] - cd * v0) - alpha * v0;
   double um = u0[t] - dt * v0 + 0.5 * dt * dt * acc;
   if (fixed[node] & (1u << c)) um = 0.0;
   vprev[t] = um;
 }
 
-// Starter in velocity form: v_{-1/2} = v_0 - dt/2 (m^-1 (g_0 F - K u_0) - alpha v_0).
+// Starter in velocity form: v_{-1/2} = v_0 - dt/2 (m^-1 (g_0 F - K u_0 - c_d v_0) - alpha v_0).
 __global__ __launch_bounds__(256) void k_starter_f32(int32_t n_nodes, int32_t ld,
                                                      const float* __restrict__ R,
                                                      const float* __restrict__ minv,
@@ -649,7 +653,7 @@ __global__ __launch_bounds__(256) void k_starter_f32(int32_t n_nodes, int32_t ld
                                                      const uint8_t* __restrict__ fixed,
                                                      float* __restrict__ v,
                                                      const double* __restrict__ gtab, double dt,
-                                                     double alpha) {
+                                                     double alpha, double cd) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= (int64_t)n_nodes * 3 * ld) return;
   const int64_t row = t / ld;
@@ -657,7 +661,7 @@ __global__ __launch_bounds__(256) void k_starter_f32(int32_t n_nodes, int32_t ld
   const int64_t node = row / 3;
   const int c = (int)(row % 3);
   const double v0 = (double)v[t];
-  const double acc = (double)minv[node * ld + s] * (gtab[0] * F[row] - (double)R[t]) - alpha * v0;
+  const double acc = (double)minv[node * ld + s] * (gtab[0] * F[row] - (double)R[t] - cd * v0) - alpha * v0;
   float vm = (float)(v0 - 0.5 * dt * acc);
   if (fixed[node] & (1u << c)) vm = 0.0f;
   v[t] = vm;
@@ -904,21 +908,21 @@ hipError_t launch_energy_reduce(const double* part, int32_t n_nb, int32_t ld, in
 hipError_t launch_starter_f64(int32_t n_nodes, int32_t ld, const double* R, const double* minv,
                               const double* F, const uint8_t* fixed, const double* u0,
                               double* vprev_io, const double* gtab, double dt, double alpha,
-                              hipStream_t st) {
+                              double cd, hipStream_t st) {
   const int64_t n = (int64_t)n_nodes * 3 * ld;
   if (n == 0) return hipSuccess;
   k_starter_f64<<<grid_for(n, 256), 256, 0, st>>>(n_nodes, ld, R, minv, F, fixed, u0, vprev_io,
-                                                   gtab, dt, alpha);
+                                                   gtab, dt, alpha, cd);
   return hipGetLastError();
 }
 
 hipError_t launch_starter_f32(int32_t n_nodes, int32_t ld, const float* R, const float* minv,
                               const double* F, const uint8_t* fixed, float* v_io,
-                              const double* gtab, double dt, double alpha, hipStream_t st) {
+                              const double* gtab, double dt, double alpha, double cd, hipStream_t st) {
   const int64_t n = (int64_t)n_nodes * 3 * ld;
   if (n == 0) return hipSuccess;
   k_starter_f32<<<grid_for(n, 256), 256, 0, st>>>(n_nodes, ld, R, minv, F, fixed, v_io, gtab, dt,
-                                                   alpha);
+                                                   alpha, cd);
   return hipGetLastError();
 }
 

@@ -142,6 +142,50 @@ def test_nonzero_initial_state_and_pulsatile_load():
         assert rel_l2(u, ref) <= tol, mode
 
 
+def test_explicit_viscous_force_matches_oracle():
+    """The explicit viscous force -c_d (u_n - u_{n-1}) / dt (and -c_d v_0 in
+    the starter) against the oracle, from a moving start under a ramped load,
+    for the FP64, FP32-apply / FP64-state and Kahan-FP32 paths."""
+    cs = small_case(24, 14, 6, seed=8)
+    rng = np.random.default_rng(9)
+    free = ~cs.mesh.fixed.reshape(-1).astype(bool)
+    u0 = rng.standard_normal((cs.mesh.n_dof, 6)) * 1e-3 * free[:, None]
+    v0 = rng.standard_normal((cs.mesh.n_dof, 6)) * 1e-1 * free[:, None]
+    from oracle import assembly
+    m_min = min(assembly.lumped_mass(cs.mesh.tri, cs.area, cs.h[:, s], 1.0, cs.mesh.n_nodes).min()
+                for s in range(6))
+    c_d = 0.05 * m_min / cs.dt
+    n = 2000
+    g = lambda t: stepper.load_factor("sine", t, 0.01)
+    ref = []
+    for s in range(6):
+        K = assembly.assemble_stiffness(cs.mesh.tri, cs.khat, cs.eh[:, s], cs.mesh.n_nodes)
+        m = assembly.lumped_mass(cs.mesh.tri, cs.area, cs.h[:, s], 1.0, cs.mesh.n_nodes)
+        ref.append(stepper.run_sample(K, m, cs.F.reshape(-1), ~free, cs.dt, n, 10.0, g,
+                                      u0=u0[:, s], v0=v0[:, s], c_d=c_d)["u"])
+    ref = np.stack(ref, axis=1)
+    plain = []
+    for s in range(6):
+        K = assembly.assemble_stiffness(cs.mesh.tri, cs.khat, cs.eh[:, s], cs.mesh.n_nodes)
+        m = assembly.lumped_mass(cs.mesh.tri, cs.area, cs.h[:, s], 1.0, cs.mesh.n_nodes)
+        plain.append(stepper.run_sample(K, m, cs.F.reshape(-1), ~free, cs.dt, n, 10.0, g,
+                                        u0=u0[:, s], v0=v0[:, s])["u"])
+    assert rel_l2(np.stack(plain, axis=1), ref) > 1e-3  # the force matters at this c_d
+    for mode, tol, kw in [("f64", 1e-10, {}),
+                          ("f32 apply", 1e-5, dict(apply_prec=ensfem.F32)),
+                          ("kahan", 1e-5, dict(apply_prec=ensfem.F32, state_prec=ensfem.STATE_F32_KAHAN))]:
+        say(f"case: viscous force c_d={c_d:.3e}, {mode}")
+        ens = ensfem.setup_case(cs.mesh, cs.eh, cs.h, cs.F, alpha=10.0, kind=ensfem.LOAD_RAMP_SINE,
+                                t_ramp=0.01, c_d=c_d, **kw)
+        ens.init_state(u0, v0)
+        ens.step(n, cs.dt)
+        u = ens.read_state()
+        ens.close()
+        err = rel_l2(u, ref)
+        say(f"  rel L2 {err:.2e}")
+        assert err <= tol, mode
+
+
 def test_energy_conserved_and_matches_oracle():
     cs = small_case(18, 10, 4, seed=5)
     free = ~cs.mesh.fixed.reshape(-1).astype(bool)

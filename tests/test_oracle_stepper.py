@@ -93,6 +93,32 @@ def test_energy_balance_constant_force_and_damped_decay():
     assert E[-1] < 0.9 * E[0]
 
 
+def test_viscous_force_discrete_energy_balance():
+    """With the explicit viscous force f_v = -c_d (u_n - u_{n-1}) / dt and no
+    other force or damping, multiplying the update by (u_{n+1} - u_{n-1}) / 2
+    gives E_{n+1/2} - E_{n-1/2} = -c_d dt / 2 v_{n-1/2} . (v_{n+1/2} + v_{n-1/2})
+    exactly (v_{n+1/2} = (u_{n+1} - u_n) / dt); the energy then decays."""
+    m, kh, A, eh, h = tiny_case()
+    K, mn, free, w2, phi = _modes(m, kh, A, eh, h)
+    dt = 0.9 * 2.0 / math.sqrt(w2[-1])
+    c_d = 0.05 * mn.min() / dt
+    rng = np.random.default_rng(10)
+    u0 = _embed(free, rng.normal(size=free.sum()))
+    n = 400
+    r = stepper.run_sample(K, mn, np.zeros(m.n_dof), ~free, dt, n, 0.0, lambda t: 0.0, u0=u0,
+                           energy_every=1, checkpoints=range(n + 1), c_d=c_d)
+    E = np.array([e for _, e in r["energy"]])
+    cps = r["checkpoints"]
+    v = [(cps[k + 1] - cps[k]) / dt for k in range(n)]
+    pred = np.array([-0.5 * c_d * dt * v[k - 1] @ (v[k] + v[k - 1]) for k in range(1, n)])
+    assert np.max(np.abs(np.diff(E) - pred)) <= 1e-10 * E[0]
+    assert np.all(np.diff(E) <= 1e-12 * E[0]) and E[-1] < 0.9 * E[0]
+    # c_d = 0 is the plain scheme
+    r0 = stepper.run_sample(K, mn, np.zeros(m.n_dof), ~free, dt, 50, 0.0, lambda t: 0.0, u0=u0, c_d=0.0)
+    r1 = stepper.run_sample(K, mn, np.zeros(m.n_dof), ~free, dt, 50, 0.0, lambda t: 0.0, u0=u0)
+    assert np.array_equal(r0["u"], r1["u"])
+
+
 def test_starter_first_step():
     m, kh, A, eh, h = tiny_case()
     K, mn, free, w2, phi = _modes(m, kh, A, eh, h)
