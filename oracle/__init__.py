@@ -20,7 +20,9 @@ What it computes, following the paper (arXiv 2101.09059, Li & Schiavazzi):
   * stats.py    -- per-node ensemble mean and variance;
   * mlp.py      -- the learned form's GELU network, forward / backward / Adam;
   * control_variate.py -- multifidelity control-variate mean / variance
-                   and its fallback rule.
+                   and its fallback rule;
+  * stress.py   -- wall stresses in the local cylindrical frame (Sec. 2.3)
+                   and their ensemble mean / quantile bands.
 
 Every function is pinned by the CPU tests (closed forms, invariants,
 textbook special cases); see each module header for its pins.
