@@ -85,7 +85,9 @@ typedef struct {
   double period;
 } ens_schedule;
 /* quantities of interest */
-enum { ENS_QOI_PEAK_RADIAL = 1 };
+enum { ENS_QOI_PEAK_RADIAL = 1, ENS_QOI_STRESS = 2 };
+/* Wall-stress components in the cylindrical frame (ens_stress). */
+enum { ENS_STRESS_THETA_THETA = 0, ENS_STRESS_Z_Z = 1, ENS_STRESS_THETA_Z = 2, ENS_STRESS_R_Z = 3 };
 
 typedef struct {
   int64_t n_nodes, n_el, n_dof;
@@ -138,7 +140,8 @@ int32_t ens_set_ensemble(ens_ctx* ctx, int32_t S, const double* eh, const double
 int32_t ens_set_load(ens_ctx* ctx, const double* F, ens_schedule sched);
 
 /* Precision / variant / outputs.  qoi_mask: ENS_QOI_PEAK_RADIAL to track
- * q_{i,s} = max_n e_r,i . u_{i,s}(t_n).  energy_every > 0 records the
+ * q_{i,s} = max_n e_r,i . u_{i,s}(t_n); ENS_QOI_STRESS to reserve the
+ * scratch of ens_stress / ens_stress_bands.  energy_every > 0 records the
  * discrete energy 1/2 v^T M v + 1/2 u_{n+1}^T K u_n per sample at steps
  * n with n % energy_every == 0 (the most recent 4096 records are kept).
  * ENS_VARIANT_CSR_SHARED needs shared stiffness (ENS_EUNSUPPORTED at bind
@@ -183,6 +186,26 @@ int32_t ens_read_qoi(ens_ctx* ctx, int32_t kind, double* out);
 int32_t ens_read_energy(ens_ctx* ctx, int64_t max_records, int64_t* steps_out, double* e_out,
                         int64_t* n_out);
 int32_t ens_moments(ens_ctx* ctx, double* mean, double* var);
+
+/* Wall stress of the current state in the local cylindrical frame (Sec.
+ * 2.3, fluid-structure coupling): per element and sample, the local strains
+ * of Sec. 2.2.1 (B times the element's nodal displacements in its frame),
+ * stresses sigma = C eps with E = (E h)/h and sigma_zz = 0, taken to the
+ * frame r = the element's unit normal, z = axial[e] (the centreline tangent
+ * at the element, caller's element order, [n_el*3] host) with its normal
+ * part removed and normalised, theta = r x z.  component: one of
+ * ENS_STRESS_*; out [n_el*S] host.  Needs ENS_QOI_STRESS in ens_configure
+ * (it sizes a scratch region of n_el*(S_pad+6) doubles in the workspace);
+ * ENS_ESTATE otherwise or without a state, ENS_EINVAL for a zero or
+ * non-finite tangent or one parallel to its element's normal.
+ * Synchronizing. */
+int32_t ens_stress(ens_ctx* ctx, const double* axial, int32_t component, double* out);
+/* Ensemble bands of one stress component per element: mean over the S
+ * samples and the p_lo / p_hi quantiles (linear interpolation between order
+ * statistics at p (S - 1)), host arrays [n_el] in the caller's element
+ * order.  S <= 4096 (ENS_EUNSUPPORTED otherwise); levels in [0, 1]. */
+int32_t ens_stress_bands(ens_ctx* ctx, const double* axial, int32_t component, double p_lo, double p_hi,
+                         double* mean, double* lo, double* hi);
 
 /* Stand-alone stiffness apply R = K(E h)_s U on device buffers of
  * [n_nodes*3][S_pad] in `prec` (ENS_F64: double, ENS_F32: float), using

@@ -26,7 +26,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 struct Layout {
   size_t xyz, tri, khat, area, lam, flags, adj_ptr, adj_el, adj_nb, adj_loc, k64, k32, fixed,
       radial, perm, F, eh64, eh32, h, minv64, minv32, u[2], uh[2], uc, v, q, qmask, bsr_ptr, bsr_col,
-      adj_slot, bsr64, bsr32, epart, erec, gtab, base,
+      adj_slot, bsr64, bsr32, epart, erec, gtab, base, frame, stress,
       mean, var, aux, total;
 };
 
@@ -159,6 +159,7 @@ Layout plan(const ens_ctx* c) {
   L.khat = take(sizeof(double) * 81 * ne);
   L.area = take(sizeof(double) * ne);
   L.lam = take(sizeof(double) * ne);
+  L.frame = take(sizeof(double) * kFrameWords * ne);
   L.flags = take(sizeof(Flags));
   L.adj_ptr = take(sizeof(int32_t) * (nn + 1));
   L.adj_el = take(sizeof(int32_t) * nadj);
@@ -202,6 +203,9 @@ Layout plan(const ens_ctx* c) {
   L.mean = take(sizeof(double) * nn);
   L.var = take(sizeof(double) * nn);
   L.aux = take(sizeof(double) * ndof * ld);
+  // stress values of one component [n_el][ld], the tangents [n_el][3] and
+  // the bands (mean, lo, hi) [3][n_el]
+  if (c->qoi_mask & ENS_QOI_STRESS) L.stress = take(sizeof(double) * (ne * ld + 6 * ne));
   L.total = off;
   return L;
 }
@@ -433,7 +437,7 @@ int32_t upload_all(ens_ctx* ctx) {
   Flags* fl = ctx->p<Flags>(L.flags);
   HIPC(launch_element_setup(ne, ctx->p<double>(L.xyz), ctx->p<int32_t>(L.tri), ctx->nu, ctx->shear_k,
                             ctx->p<double>(L.khat), ctx->p<double>(L.area), ctx->p<double>(L.lam),
-                            &fl->bad, st));
+                            ctx->p<double>(L.frame), &fl->bad, st));
   HIPC(launch_adjacency_blocks(3 * ne, ctx->p<int32_t>(L.adj_el), ctx->p<uint8_t>(L.adj_loc),
                                ctx->p<double>(L.khat), ctx->p<double>(L.k64), ctx->p<float>(L.k32), st));
   HIPC(launch_cast_f32(ne * ld, ctx->p<double>(L.eh64), ctx->p<float>(L.eh32), st));
@@ -675,7 +679,7 @@ int32_t ens_configure(ens_ctx* ctx, int32_t apply_prec, int32_t state_prec, int3
     return ctx->fail(ENS_EUNSUPPORTED, "ens_configure: FP32 states need the FP32 apply");
   if (variant != ENS_VARIANT_AUTO && variant != ENS_VARIANT_NODE_GATHER && variant != ENS_VARIANT_CSR_SHARED)
     return ctx->fail(ENS_EINVAL, "ens_configure: unknown variant");
-  if (qoi_mask & ~ENS_QOI_PEAK_RADIAL) return ctx->fail(ENS_EINVAL, "ens_configure: unknown QoI bit");
+  if (qoi_mask & ~(ENS_QOI_PEAK_RADIAL | ENS_QOI_STRESS)) return ctx->fail(ENS_EINVAL, "ens_configure: unknown QoI bit");
   if (energy_every < 0) return ctx->fail(ENS_EINVAL, "ens_configure: energy_every must be >= 0");
   const bool relayout = state_prec != ctx->state_prec || variant != ctx->variant;
   ctx->apply_prec = apply_prec;
@@ -987,6 +991,85 @@ int32_t ens_read_energy(ens_ctx* ctx, int64_t max_records, int64_t* steps_out, d
                    hipMemcpyDeviceToHost));
     std::memcpy(e_out + k * ctx->S, row.data(), sizeof(double) * ctx->S);
     steps_out[k] = ctx->energy_steps[slot];
+  }
+  return ENS_OK;
+  GUARD_END
+}
+
+namespace {
+// One stress component of the current state into the stress scratch
+// ([n_el][ld], internal element order); axial in the caller's order.
+int32_t stress_values(ens_ctx* ctx, const char* who, const double* axial, int32_t comp) {
+  if (!(ctx->qoi_mask & ENS_QOI_STRESS))
+    return ctx->fail(ENS_ESTATE, std::string(who) + ": enable ENS_QOI_STRESS in ens_configure first");
+  if (!ctx->bound || !ctx->state_init) return ctx->fail(ENS_ESTATE, std::string(who) + ": no state");
+  if (!axial) return ctx->fail(ENS_EINVAL, std::string(who) + ": null tangents");
+  if (comp < ENS_STRESS_THETA_THETA || comp > ENS_STRESS_R_Z)
+    return ctx->fail(ENS_EINVAL, std::string(who) + ": unknown stress component");
+  const int64_t ne = ctx->n_el;
+  std::vector<double> ax(3 * ne);
+  for (int64_t e = 0; e < ne; ++e) {
+    const double* a = axial + 3 * (int64_t)ctx->eperm[e];
+    if (!std::isfinite(a[0]) || !std::isfinite(a[1]) || !std::isfinite(a[2]) ||
+        !(a[0] * a[0] + a[1] * a[1] + a[2] * a[2] > 0.0))
+      return ctx->fail(ENS_EINVAL, std::string(who) + ": tangent of element " + std::to_string(ctx->eperm[e]) +
+                                       " is zero or not finite");
+    for (int k = 0; k < 3; ++k) ax[3 * e + k] = a[k];
+  }
+  const Layout& L = ctx->L;
+  HIPC(hipSetDevice(ctx->device));
+  HIPC(hipDeviceSynchronize());
+  double* vals = ctx->p<double>(L.stress);
+  double* dax = vals + ne * ctx->ld;
+  HIPC(hipMemcpy(dax, ax.data(), sizeof(double) * 3 * ne, hipMemcpyHostToDevice));
+  Flags* fl = ctx->p<Flags>(L.flags);
+  HIPC(hipMemset(&fl->bad, 0, sizeof(int32_t)));
+  const bool f64 = ctx->state_prec == ENS_STATE_F64;
+  const float* uc = ctx->state_prec == ENS_STATE_F32_KAHAN ? ctx->p<float>(L.uc) : nullptr;
+  HIPC(launch_stress(ne, ctx->ld, ctx->p<int32_t>(L.tri), ctx->p<double>(L.frame),
+                     f64 ? ctx->p<double>(L.u[ctx->cur]) : nullptr, f64 ? nullptr : ctx->p<float>(L.uh[ctx->cur]),
+                     f64 ? nullptr : uc, ctx->p<double>(L.eh64), ctx->p<double>(L.h), dax, ctx->nu, ctx->shear_k,
+                     comp, vals, &fl->bad, nullptr));
+  int32_t bad = 0;
+  HIPC(hipMemcpy(&bad, &fl->bad, sizeof(int32_t), hipMemcpyDeviceToHost));
+  if (bad) return ctx->fail(ENS_EINVAL, std::string(who) + ": a tangent is parallel to its element's normal");
+  return ENS_OK;
+}
+}  // namespace
+
+int32_t ens_stress(ens_ctx* ctx, const double* axial, int32_t component, double* out) {
+  if (!ctx || !out) return ENS_EINVAL;
+  GUARD_BEGIN
+  const int32_t rc = stress_values(ctx, "ens_stress", axial, component);
+  if (rc != ENS_OK) return rc;
+  std::vector<double> buf((size_t)ctx->n_el * ctx->ld);
+  HIPC(hipMemcpy(buf.data(), ctx->p<void>(ctx->L.stress), sizeof(double) * buf.size(), hipMemcpyDeviceToHost));
+  unpad_rows(buf.data(), ctx->n_el, ctx->S, ctx->ld, out, &ctx->eperm, 1);
+  return ENS_OK;
+  GUARD_END
+}
+
+int32_t ens_stress_bands(ens_ctx* ctx, const double* axial, int32_t component, double p_lo, double p_hi,
+                         double* mean, double* lo, double* hi) {
+  if (!ctx || !mean || !lo || !hi) return ENS_EINVAL;
+  GUARD_BEGIN
+  if (!(p_lo >= 0.0 && p_lo <= 1.0 && p_hi >= 0.0 && p_hi <= 1.0))
+    return ctx->fail(ENS_EINVAL, "ens_stress_bands: quantile levels must lie in [0, 1]");
+  if (ctx->S > kBandsMax)
+    return ctx->fail(ENS_EUNSUPPORTED, "ens_stress_bands: at most " + std::to_string(kBandsMax) + " samples");
+  const int32_t rc = stress_values(ctx, "ens_stress_bands", axial, component);
+  if (rc != ENS_OK) return rc;
+  const int64_t ne = ctx->n_el;
+  double* vals = ctx->p<double>(ctx->L.stress);
+  double* b = vals + ne * ctx->ld + 3 * ne;
+  HIPC(launch_bands(ne, ctx->ld, ctx->S, vals, p_lo, p_hi, b, b + ne, b + 2 * ne, nullptr));
+  std::vector<double> hb(3 * ne);
+  HIPC(hipMemcpy(hb.data(), b, sizeof(double) * 3 * ne, hipMemcpyDeviceToHost));
+  for (int64_t e = 0; e < ne; ++e) {
+    const int64_t o = ctx->eperm[e];
+    mean[o] = hb[e];
+    lo[o] = hb[ne + e];
+    hi[o] = hb[2 * ne + e];
   }
   return ENS_OK;
   GUARD_END
@@ -1332,7 +1415,8 @@ int32_t ens_batch_create(ens_ctx** ctxs, int32_t n, ens_batch** out) {
     else if (c->device != c0->device) why = "contexts on different devices";
     else if (c->apply_prec != c0->apply_prec || c->state_prec != c0->state_prec)
       why = "all meshes need the same apply and state precision";
-    else if ((c->qoi_mask != 0) != (c0->qoi_mask != 0)) why = "all meshes need the same QoI setting";
+    else if ((c->qoi_mask & ENS_QOI_PEAK_RADIAL) != (c0->qoi_mask & ENS_QOI_PEAK_RADIAL))
+      why = "all meshes need the same QoI setting";
     else if (c->energy_every != 0) why = "energy records are not available in batched stepping";
     else if (use_shared(c)) why = "batched stepping uses the element-by-element variant only";
     else if (c->ld % 64 != 0) why = "padded width must be a multiple of 64 (ens_set_tuning(ctx, 64, 0) before binding)";
@@ -1348,7 +1432,7 @@ int32_t ens_batch_create(ens_ctx** ctxs, int32_t n, ens_batch** out) {
   b->device = c0->device;
   b->apply_f32 = c0->apply_prec == ENS_F32;
   b->mode = c0->state_prec;
-  b->qoi = c0->qoi_mask != 0;
+  b->qoi = (c0->qoi_mask & ENS_QOI_PEAK_RADIAL) != 0;
   b->spl = 2;
   (void)all128;
   b->desc_cur.assign(n, -1);

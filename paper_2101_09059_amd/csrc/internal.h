@@ -100,9 +100,13 @@ struct BatchTile {
 };
 
 // ---- set-up kernels (setup.hip) -------------------------------------------
+// Doubles per element in the frame table written by the element set-up:
+// rows e_x, e_y, e_z of the local frame (9), dN_j/dx (3), dN_j/dy (3), pad.
+constexpr int kFrameWords = 16;
+
 hipError_t launch_element_setup(int64_t n_el, const double* xyz, const int32_t* tri, double nu,
                                 double shear_k, double* khat, double* area, double* lam,
-                                int32_t* bad, hipStream_t st);
+                                double* frame, int32_t* bad, hipStream_t st);
 hipError_t launch_adjacency_blocks(int64_t n_adj, const int32_t* adj_el, const uint8_t* adj_loc,
                                    const double* khat, double* k64, float* k32, hipStream_t st);
 hipError_t launch_lumped_mass(int32_t n_nodes, int32_t ld, const int32_t* adj_ptr,
@@ -152,5 +156,22 @@ hipError_t launch_moments(int32_t n_nodes, int32_t ld, int32_t S, const double* 
                           double* var, hipStream_t st);
 hipError_t launch_check_finite(int64_t n, const void* x, int is_f32, int32_t* flag,
                                hipStream_t st);
+
+// ---- stress post-processing (stress.hip) ------------------------------------
+// Component comp (0 theta-theta, 1 z-z, 2 theta-z, 3 r-z) of the wall stress
+// in the cylindrical frame per element and sample, from the current state
+// (u: FP64 state, or uh - uc for the FP32 states); axial [n_el][3] centreline
+// tangents (internal element order); out [n_el][ld].  bad is set if a
+// tangent is (numerically) parallel to its element's normal.
+hipError_t launch_stress(int64_t n_el, int32_t ld, const int32_t* tri, const double* frame,
+                         const double* u, const float* uh, const float* uc, const double* eh,
+                         const double* h, const double* axial, double nu, double shear_k, int comp,
+                         double* out, int32_t* bad, hipStream_t st);
+// Per row of vals [n_rows][ld] (first S columns): mean and the p_lo / p_hi
+// quantiles (linear interpolation between order statistics at p (S - 1)).
+// S <= kBandsMax.
+constexpr int kBandsMax = 4096;
+hipError_t launch_bands(int64_t n_rows, int32_t ld, int32_t S, const double* vals, double p_lo, double p_hi,
+                        double* mean, double* lo, double* hi, hipStream_t st);
 
 }  // namespace ensfem

@@ -24,6 +24,7 @@ __global__ __launch_bounds__(64) void k_element_setup(int64_t n_el, const double
                                                       double shear_k, double* __restrict__ khat,
                                                       double* __restrict__ area,
                                                       double* __restrict__ lam,
+                                                      double* __restrict__ frame,
                                                       int32_t* __restrict__ bad) {
   const int64_t e = (int64_t)blockIdx.x * 64 + threadIdx.x;
   if (e >= n_el) return;
@@ -64,12 +65,24 @@ __global__ __launch_bounds__(64) void k_element_setup(int64_t n_el, const double
     atomicOr(bad, 1);
     lam[e] = 0.0;
     for (int i = 0; i < 81; ++i) khat[81 * e + i] = 0.0;
+    for (int i = 0; i < kFrameWords; ++i) frame[kFrameWords * e + i] = 0.0;
     return;
   }
   const double inv2A = 1.0 / (2.0 * A);
   // x_ij = x_i - x_j with x_1 = y_1 = 0
   const double bx[3] = {(y2 - y3) * inv2A, (y3 - 0.0) * inv2A, (0.0 - y2) * inv2A};
   const double by[3] = {(x3 - x2) * inv2A, (0.0 - x3) * inv2A, (x2 - 0.0) * inv2A};
+  // frame rows and shape-function derivatives, for stress post-processing
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) frame[kFrameWords * e + 3 * i + c] = R[i][c];
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    frame[kFrameWords * e + 9 + v] = bx[v];
+    frame[kFrameWords * e + 12 + v] = by[v];
+  }
+  frame[kFrameWords * e + 15] = 0.0;
   const double inv = 1.0 / (1.0 - nu * nu);
   const double c11 = inv, c12 = nu * inv, c33 = 0.5 * (1.0 - nu) * inv;
   const double c44 = 0.5 * shear_k * (1.0 - nu) * inv;
@@ -281,10 +294,10 @@ inline unsigned grid_for(int64_t n, int per) { return (unsigned)((n + per - 1) /
 
 hipError_t launch_element_setup(int64_t n_el, const double* xyz, const int32_t* tri, double nu,
                                 double shear_k, double* khat, double* area, double* lam,
-                                int32_t* bad, hipStream_t st) {
+                                double* frame, int32_t* bad, hipStream_t st) {
   if (n_el == 0) return hipSuccess;
   k_element_setup<<<grid_for(n_el, 64), 64, 0, st>>>(n_el, xyz, tri, nu, shear_k, khat, area, lam,
-                                                      bad);
+                                                      frame, bad);
   return hipGetLastError();
 }
 

@@ -26,7 +26,8 @@ F64, F32 = 0, 1
 STATE_F64, STATE_F32_KAHAN, STATE_F32 = 0, 1, 2
 VARIANT_AUTO, VARIANT_NODE_GATHER, VARIANT_CSR_SHARED = 0, 1, 3
 LOAD_STEP, LOAD_RAMP_SINE, LOAD_PULSATILE = 0, 1, 2
-QOI_PEAK_RADIAL = 1
+QOI_PEAK_RADIAL, QOI_STRESS = 1, 2
+STRESS_THETA_THETA, STRESS_Z_Z, STRESS_THETA_Z, STRESS_R_Z = 0, 1, 2, 3
 
 _CODES = {ENS_EINVAL: "EINVAL", ENS_ESTATE: "ESTATE", ENS_EWORKSPACE: "EWORKSPACE",
           ENS_EDEVICE: "EDEVICE", ENS_EUNSTABLE: "EUNSTABLE", ENS_ENONFINITE: "ENONFINITE",
@@ -86,6 +87,8 @@ _SIGS = {
     "ens_read_qoi": (_I32, [_P, _I32, _P]),
     "ens_read_energy": (_I32, [_P, _I64, _P, _P, ctypes.POINTER(_I64)]),
     "ens_moments": (_I32, [_P, _P, _P]),
+    "ens_stress": (_I32, [_P, _P, _I32, _P]),
+    "ens_stress_bands": (_I32, [_P, _P, _I32, _D, _D, _P, _P, _P]),
     "ens_apply": (_I32, [_P, _I32, _P, _P, _P]),
     "ens_save": (_I32, [_P, _P, ctypes.POINTER(_SZ)]),
     "ens_load": (_I32, [_P, _P, _SZ]),
@@ -223,9 +226,10 @@ class Ensemble:
         self._check(self._lib.ens_set_load(self._h, _ptr(F), Schedule(kind, t_ramp, amp, period)))
 
     def configure(self, apply_prec: int = F64, state_prec: int = STATE_F64,
-                  variant: int = VARIANT_AUTO, qoi: bool = True, energy_every: int = 0):
-        self._check(self._lib.ens_configure(self._h, apply_prec, state_prec, variant,
-                                            QOI_PEAK_RADIAL if qoi else 0, energy_every))
+                  variant: int = VARIANT_AUTO, qoi: bool = True, energy_every: int = 0,
+                  stress: bool = False):
+        mask = (QOI_PEAK_RADIAL if qoi else 0) | (QOI_STRESS if stress else 0)
+        self._check(self._lib.ens_configure(self._h, apply_prec, state_prec, variant, mask, energy_every))
 
     def set_tuning(self, sample_block: int = 0, sb_inner: bool = False):
         self._check(self._lib.ens_set_tuning(self._h, sample_block, 1 if sb_inner else 0))
@@ -281,6 +285,22 @@ class Ensemble:
         n = _I64()
         self._check(self._lib.ens_read_energy(self._h, max_records, _ptr(steps), _ptr(e), ctypes.byref(n)))
         return steps[:n.value], e[:n.value]
+
+    def stress(self, axial, component: int) -> np.ndarray:
+        """Wall-stress component [n_el, S] of the current state; axial
+        [n_el, 3] centreline tangents per element."""
+        a = _f64(axial)
+        out = np.empty((self.n_el, self.S))
+        self._check(self._lib.ens_stress(self._h, _ptr(a), component, _ptr(out)))
+        return out
+
+    def stress_bands(self, axial, component: int, p_lo: float = 0.05, p_hi: float = 0.95):
+        """Per-element ensemble mean and p_lo / p_hi quantiles of a component."""
+        a = _f64(axial)
+        mean, lo, hi = np.empty(self.n_el), np.empty(self.n_el), np.empty(self.n_el)
+        self._check(self._lib.ens_stress_bands(self._h, _ptr(a), component, float(p_lo), float(p_hi),
+                                               _ptr(mean), _ptr(lo), _ptr(hi)))
+        return mean, lo, hi
 
     def moments(self):
         mean = np.empty(self.n_nodes)
@@ -472,7 +492,7 @@ def cv_moments(qH, qL, sumL, sumsqL, M: int, device: int = 0):
 def setup_case(mesh, eh, h, F, nu=0.49, shear_k=5.0 / 6.0, rho=1.0, alpha=50.0,
                kind=LOAD_STEP, t_ramp=0.0, amp=0.0, period=1.0, apply_prec=F64,
                state_prec=STATE_F64, qoi=True, energy_every=0, device=0,
-               sample_block=0, sb_inner=False, variant=VARIANT_AUTO, c_d=0.0) -> Ensemble:
+               sample_block=0, sb_inner=False, variant=VARIANT_AUTO, c_d=0.0, stress=False) -> Ensemble:
     """Create, fill, configure and bind a context for one mesh and ensemble."""
     ens = Ensemble(device)
     ens.set_mesh(mesh.xyz, mesh.tri, mesh.fixed, mesh.radial)
@@ -481,7 +501,7 @@ def setup_case(mesh, eh, h, F, nu=0.49, shear_k=5.0 / 6.0, rho=1.0, alpha=50.0,
         ens.set_viscous(c_d)
     ens.set_ensemble(eh, h)
     ens.set_load(F, kind, t_ramp, amp, period)
-    ens.configure(apply_prec, state_prec, variant, qoi, energy_every)
+    ens.configure(apply_prec, state_prec, variant, qoi, energy_every, stress)
     if sample_block or sb_inner:
         ens.set_tuning(sample_block, sb_inner)
     ens.bind_workspace()
