@@ -376,6 +376,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", dest="cpu", action="store_false", default=True)
     ap.add_argument("--no-also-shared", dest="also_shared", action="store_false", default=True,
                     help="skip the shared-stiffness (block-row product) timing")
+    ap.add_argument("--no-also-stress", dest="also_stress", action="store_false", default=True,
+                    help="skip the wall-stress bands timing")
     ap.add_argument("--sample-block", type=int, default=0, help="0 = library default")
     ap.add_argument("--sb-inner", action="store_true")
     ap.add_argument("--config", choices=["c2_cylinder", "c3_curved", "c4_batch", "c5_learned"],
@@ -484,6 +486,26 @@ def main():
         assert info_sh["variant"] == ensfem.VARIANT_CSR_SHARED
         log(f"shared stiffness, apply={args.apply}: {ms_sh / args.steps:.4f} ms/step")
 
+    stress_ms = None
+    if args.also_stress:
+        # wall-stress bands of the state after a short run (post-processing;
+        # host-inclusive: the call synchronizes and returns per-element bands)
+        ens = ensfem.setup_case(mesh, eh, h, F, nu=cfg["nu"], shear_k=cfg["shear_k"], rho=cfg["rho"],
+                                alpha=cfg["alpha"], apply_prec=ensfem.F32, stress=True)
+        ens.init_state()
+        ens.step(200, ens.cfl_dt(cfg["safety"]))
+        ens.sync()
+        axial = np.tile([0.0, 0.0, 1.0], (mesh.n_el, 1))
+        ens.stress_bands(axial, ensfem.STRESS_THETA_THETA)
+        t0 = time.perf_counter()
+        for comp in range(4):
+            ens.stress_bands(axial, comp)
+        stress_ms = (time.perf_counter() - t0) * 1e3 / 4
+        ens.close()
+        del ens
+        torch.cuda.empty_cache()
+        log(f"stress bands: {stress_ms:.1f} ms per component")
+
     ms, dt, info = results[args.apply]
     S = cfg["S"]
     work = mesh.n_dof * S * args.steps
@@ -525,6 +547,8 @@ def main():
                                  "achieved_GBs": ab / (apply_ms[0] * 1e-3) / 1e9,
                                  "frac": ab / (apply_ms[0] * 1e-3) / 1e9 / HBM_PEAK_GBS,
                                  "kernel": "k_apply (node map: rows in the caller's numbering)"}
+    if stress_ms is not None:
+        out["stress_bands_ms_per_component"] = stress_ms
     if args.also_shared:
         out["ms_per_step_shared_stiffness"] = ms_sh / args.steps
         out["value_shared_stiffness"] = work / (ms_sh * 1e-3)

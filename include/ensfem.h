@@ -118,6 +118,15 @@ int32_t ens_set_mesh(ens_ctx* ctx, int64_t n_nodes, const double* xyz, int64_t n
  * 0 <= nu < 0.5, shear_k >= 0, rho > 0 (g/cm^3), alpha >= 0 (1/s). */
 int32_t ens_set_material(ens_ctx* ctx, double nu, double shear_k, double rho, double alpha);
 
+/* Mass scaling (Sec. 1: raising the critical step): for dt_target > 0 the
+ * density of every element and sample whose eigenvalue bound
+ * 3 E lambda_max(Khat_e) / (rho A_e) exceeds (2 / dt_target)^2 is multiplied
+ * by that bound times dt_target^2 / 4, so ens_cfl_dt(ctx, 1.0) >= dt_target;
+ * the lumped masses and the stability bound use the scaled densities.  0
+ * (the default) turns it off.  Drops the workspace binding (re-bind).
+ * ENS_EINVAL for a negative or non-finite dt_target. */
+int32_t ens_set_mass_scaling(ens_ctx* ctx, double dt_target);
+
 /* Explicit viscous force (Sec. 2.3): f_v = -c_d du/dt is added to the load,
  * with du/dt at t_n taken as (u_n - u_{n-1}) / dt so the step stays
  * explicit (and as v_0 in the starter); one coefficient c_d >= 0 for every

@@ -38,9 +38,13 @@ def assemble_stiffness(tri: np.ndarray, khat: np.ndarray, eh_col: np.ndarray, n_
     return K
 
 
-def lumped_mass(tri: np.ndarray, area: np.ndarray, h_col: np.ndarray, rho: float, n_nodes: int) -> np.ndarray:
-    """Nodal lumped mass [n_nodes] for one sample."""
+def lumped_mass(tri: np.ndarray, area: np.ndarray, h_col: np.ndarray, rho: float, n_nodes: int,
+                scale_col: np.ndarray = None) -> np.ndarray:
+    """Nodal lumped mass [n_nodes] for one sample; scale_col [n_el]: optional
+    per-element density factors (mass scaling)."""
     me = rho * h_col * area / 3.0
+    if scale_col is not None:
+        me = rho * scale_col * h_col * area / 3.0
     m = np.zeros(n_nodes)
     for a in range(3):
         np.add.at(m, tri[:, a], me)

@@ -15,9 +15,17 @@ lumped mass rho h_{e,s} A_e / 3 on each of its nodes,
 and dt = safety * 2 / sqrt(max_{e,s} of that), one step for the whole
 ensemble.
 
+Mass scaling (Sec. 1 names it as a way to raise the critical step): for a
+target step dt_t, every element and sample whose bound exceeds (2/dt_t)^2
+gets its density multiplied by f = lambda dt_t^2 / 4 (f = 1 otherwise), so
+its bound lambda / f is at most (2/dt_t)^2; the lumped masses use the scaled
+densities.
+
 Pins (tests/test_oracle_cfl.py): the global generalized eigenvalue never
-exceeds the bound; the undamped scheme stays bounded at 0.99 * 2/omega_glob
-and diverges at 1.05 * 2/omega_glob.
+exceeds the bound (also with scaled masses); the undamped scheme stays
+bounded at 0.99 * 2/omega_glob and diverges at 1.05 * 2/omega_glob; mass
+scaling leaves unscaled elements exactly alone and makes the scaled bound
+(2/dt_t)^2.
 """
 from __future__ import annotations
 
@@ -29,11 +37,24 @@ def element_lambda_max(khat: np.ndarray) -> np.ndarray:
     return np.linalg.eigvalsh(khat)[:, -1]
 
 
-def omega2_bound(khat: np.ndarray, area: np.ndarray, eh: np.ndarray, h: np.ndarray, rho: float) -> float:
+def element_omega2(khat: np.ndarray, area: np.ndarray, eh: np.ndarray, h: np.ndarray, rho: float) -> np.ndarray:
+    """3 E_{e,s} lambda_max(Khat_e) / (rho A_e) [n_el, S]."""
     lam = element_lambda_max(khat)
-    E = eh / h
-    return float(np.max(3.0 * E * (lam / (rho * area))[:, None]))
+    return 3.0 * (eh / h) * (lam / (rho * area))[:, None]
 
 
-def stable_dt(khat, area, eh, h, rho, safety: float = 0.9) -> float:
-    return safety * 2.0 / np.sqrt(omega2_bound(khat, area, eh, h, rho))
+def mass_scale_factors(khat, area, eh, h, rho, dt_target: float) -> np.ndarray:
+    """Density factors f_{e,s} = max(1, omega2_e,s dt_target^2 / 4)."""
+    return np.maximum(1.0, element_omega2(khat, area, eh, h, rho) * (dt_target * dt_target / 4.0))
+
+
+def omega2_bound(khat: np.ndarray, area: np.ndarray, eh: np.ndarray, h: np.ndarray, rho: float,
+                 scale: np.ndarray = None) -> float:
+    w2 = element_omega2(khat, area, eh, h, rho)
+    if scale is not None:
+        w2 = w2 / scale
+    return float(np.max(w2))
+
+
+def stable_dt(khat, area, eh, h, rho, safety: float = 0.9, scale: np.ndarray = None) -> float:
+    return safety * 2.0 / np.sqrt(omega2_bound(khat, area, eh, h, rho, scale))

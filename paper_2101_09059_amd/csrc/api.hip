@@ -59,7 +59,8 @@ struct ens_ctx {
   std::vector<int2> adj_slot;
   // material
   double nu = 0.49, shear_k = 5.0 / 6.0, rho = 1.0, alpha = 0.0;
-  double cd = 0.0;  // explicit viscous force coefficient
+  double cd = 0.0;       // explicit viscous force coefficient
+  double mass_dt = 0.0;  // mass-scaling target step (0: none)
   bool have_material = false;
   // ensemble (padded [n_el][ld])
   int32_t S = 0, ld = 0, SB = 0;
@@ -452,10 +453,12 @@ int32_t upload_all(ens_ctx* ctx) {
     HIPC(launch_cast_f32(9 * nb, ctx->p<double>(L.bsr64), ctx->p<float>(L.bsr32), st));
   }
   HIPC(launch_lumped_mass((int32_t)nn, (int32_t)ld, ctx->p<int32_t>(L.adj_ptr), ctx->p<int32_t>(L.adj_el),
-                          ctx->p<double>(L.area), ctx->p<double>(L.h), ctx->rho,
-                          ctx->p<double>(L.minv64), ctx->p<float>(L.minv32), st));
+                          ctx->p<double>(L.area), ctx->p<double>(L.h), ctx->rho, ctx->p<double>(L.eh64),
+                          ctx->p<double>(L.lam), ctx->mass_dt, ctx->p<double>(L.minv64), ctx->p<float>(L.minv32),
+                          st));
   HIPC(launch_cfl_max(ne, (int32_t)ld, ctx->S, ctx->p<double>(L.eh64), ctx->p<double>(L.h),
-                      ctx->p<double>(L.lam), ctx->p<double>(L.area), ctx->rho, &fl->omega2_bits, st));
+                      ctx->p<double>(L.lam), ctx->p<double>(L.area), ctx->rho, ctx->mass_dt, &fl->omega2_bits,
+                      st));
   HIPC(hipDeviceSynchronize());
   Flags hf{};
   HIPC(hipMemcpy(&hf, fl, sizeof(Flags), hipMemcpyDeviceToHost));
@@ -597,6 +600,17 @@ int32_t ens_set_material(ens_ctx* ctx, double nu, double shear_k, double rho, do
   ctx->rho = rho;
   ctx->alpha = alpha;
   ctx->have_material = true;
+  ctx->bound = false;
+  ctx->state_init = false;
+  return ENS_OK;
+}
+
+int32_t ens_set_mass_scaling(ens_ctx* ctx, double dt_target) {
+  if (!ctx) return ENS_EINVAL;
+  if (!(dt_target >= 0.0) || !std::isfinite(dt_target))
+    return ctx->fail(ENS_EINVAL, "ens_set_mass_scaling: need a finite dt_target >= 0");
+  ctx->gen++;
+  ctx->mass_dt = dt_target;
   ctx->bound = false;
   ctx->state_init = false;
   return ENS_OK;

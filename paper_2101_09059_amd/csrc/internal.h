@@ -109,11 +109,14 @@ hipError_t launch_element_setup(int64_t n_el, const double* xyz, const int32_t* 
                                 double* frame, int32_t* bad, hipStream_t st);
 hipError_t launch_adjacency_blocks(int64_t n_adj, const int32_t* adj_el, const uint8_t* adj_loc,
                                    const double* khat, double* k64, float* k32, hipStream_t st);
+// Nodal 1/m per sample; dt_t > 0 scales each element's density by
+// max(1, omega^2 dt_t^2 / 4) (mass scaling), 0 leaves it.
 hipError_t launch_lumped_mass(int32_t n_nodes, int32_t ld, const int32_t* adj_ptr,
                               const int32_t* adj_el, const double* area, const double* h, double rho,
-                              double* minv64, float* minv32, hipStream_t st);
+                              const double* eh, const double* lam, double dt_t, double* minv64, float* minv32,
+                              hipStream_t st);
 hipError_t launch_cfl_max(int64_t n_el, int32_t ld, int32_t S, const double* eh, const double* h,
-                          const double* lam, const double* area, double rho,
+                          const double* lam, const double* area, double rho, double dt_t,
                           unsigned long long* out_bits, hipStream_t st);
 hipError_t launch_cast_f32(int64_t n, const double* src, float* dst, hipStream_t st);
 hipError_t launch_bsr_assemble(int32_t n_nodes, int32_t ld, const int32_t* adj_ptr,

@@ -204,11 +204,23 @@ __global__ __launch_bounds__(256) void k_adjacency_blocks(int64_t n_adj,
 }
 
 // m_{i,s} = sum over incident elements of rho h_{e,s} A_e / 3; stores 1/m.
+// Mass-scaling factor of an element and sample: max(1, omega^2 dt_t^2 / 4)
+// for a target step dt_t > 0 (density raised just enough for the element's
+// eigenvalue bound to allow dt_t), 1 without scaling.
+__device__ __forceinline__ double mass_factor(double eh, double h, double lam, double area, double rho,
+                                              double dt_t) {
+  if (!(dt_t > 0.0)) return 1.0;
+  const double w2 = 3.0 * (eh / h) * (lam / (rho * area));
+  return fmax(1.0, w2 * (dt_t * dt_t / 4.0));
+}
+
 __global__ __launch_bounds__(256) void k_lumped_mass(int32_t n_nodes, int32_t ld,
                                                      const int32_t* __restrict__ adj_ptr,
                                                      const int32_t* __restrict__ adj_el,
                                                      const double* __restrict__ area,
                                                      const double* __restrict__ h, double rho,
+                                                     const double* __restrict__ eh,
+                                                     const double* __restrict__ lam, double dt_t,
                                                      double* __restrict__ minv64,
                                                      float* __restrict__ minv32) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -218,7 +230,12 @@ __global__ __launch_bounds__(256) void k_lumped_mass(int32_t n_nodes, int32_t ld
   double m = 0.0;
   for (int k = adj_ptr[node]; k < adj_ptr[node + 1]; ++k) {
     const int64_t e = adj_el[k];
-    m += rho * h[e * ld + s] * area[e] / 3.0;
+    if (dt_t > 0.0) {
+      const double f = mass_factor(eh[e * ld + s], h[e * ld + s], lam[e], area[e], rho, dt_t);
+      m += rho * f * h[e * ld + s] * area[e] / 3.0;
+    } else {
+      m += rho * h[e * ld + s] * area[e] / 3.0;
+    }
   }
   const double mi = 1.0 / m;
   minv64[t] = mi;
@@ -230,7 +247,7 @@ __global__ __launch_bounds__(256) void k_cfl_max(int64_t n_el, int32_t ld, int32
                                                  const double* __restrict__ eh,
                                                  const double* __restrict__ h,
                                                  const double* __restrict__ lam,
-                                                 const double* __restrict__ area, double rho,
+                                                 const double* __restrict__ area, double rho, double dt_t,
                                                  unsigned long long* __restrict__ out_bits) {
   __shared__ double red[256];
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -239,7 +256,8 @@ __global__ __launch_bounds__(256) void k_cfl_max(int64_t n_el, int32_t ld, int32
     const int64_t e = t / S;
     const int s = (int)(t % S);
     const double E = eh[e * ld + s] / h[e * ld + s];
-    w = 3.0 * E * lam[e] / (rho * area[e]);
+    w = 3.0 * E * (lam[e] / (rho * area[e]));
+    if (dt_t > 0.0) w = w / mass_factor(eh[e * ld + s], h[e * ld + s], lam[e], area[e], rho, dt_t);
     if (!(w >= 0.0)) w = INFINITY;  // NaN -> flagged as unbounded
   }
   red[threadIdx.x] = w;
@@ -311,20 +329,21 @@ hipError_t launch_adjacency_blocks(int64_t n_adj, const int32_t* adj_el, const u
 
 hipError_t launch_lumped_mass(int32_t n_nodes, int32_t ld, const int32_t* adj_ptr,
                               const int32_t* adj_el, const double* area, const double* h, double rho,
-                              double* minv64, float* minv32, hipStream_t st) {
+                              const double* eh, const double* lam, double dt_t, double* minv64, float* minv32,
+                              hipStream_t st) {
   const int64_t n = (int64_t)n_nodes * ld;
   if (n == 0) return hipSuccess;
-  k_lumped_mass<<<grid_for(n, 256), 256, 0, st>>>(n_nodes, ld, adj_ptr, adj_el, area, h, rho,
+  k_lumped_mass<<<grid_for(n, 256), 256, 0, st>>>(n_nodes, ld, adj_ptr, adj_el, area, h, rho, eh, lam, dt_t,
                                                    minv64, minv32);
   return hipGetLastError();
 }
 
 hipError_t launch_cfl_max(int64_t n_el, int32_t ld, int32_t S, const double* eh, const double* h,
-                          const double* lam, const double* area, double rho,
+                          const double* lam, const double* area, double rho, double dt_t,
                           unsigned long long* out_bits, hipStream_t st) {
   const int64_t n = n_el * S;
   if (n == 0) return hipSuccess;
-  k_cfl_max<<<grid_for(n, 256), 256, 0, st>>>(n_el, ld, S, eh, h, lam, area, rho, out_bits);
+  k_cfl_max<<<grid_for(n, 256), 256, 0, st>>>(n_el, ld, S, eh, h, lam, area, rho, dt_t, out_bits);
   return hipGetLastError();
 }
 

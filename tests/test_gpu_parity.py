@@ -186,6 +186,38 @@ def test_explicit_viscous_force_matches_oracle():
         assert err <= tol, mode
 
 
+def test_mass_scaling_matches_oracle():
+    """Mass scaling to 1.5x the unscaled stable step: the library's bound
+    gives the target, and stepping at 0.99 of it matches the oracle run with
+    the scaled lumped masses (FP64)."""
+    S = 4
+    cs = small_case(28, 12, S, seed=13)
+    from oracle import assembly
+    dt0 = cfl.stable_dt(cs.khat, cs.area, cs.eh, cs.h, 1.0, 1.0)
+    dt_t = 1.5 * dt0
+    f = cfl.mass_scale_factors(cs.khat, cs.area, cs.eh, cs.h, 1.0, dt_t)
+    say(f"case: mass scaling to {dt_t:.3e} ({(f > 1).mean():.2%} of element-samples scaled)")
+    ens = ensfem.setup_case(cs.mesh, cs.eh, cs.h, cs.F, alpha=50.0, kind=ensfem.LOAD_RAMP_SINE, t_ramp=5e-3,
+                            mass_dt=dt_t)
+    assert abs(ens.cfl_dt(1.0) / dt_t - 1.0) < 1e-12
+    dt = 0.99 * dt_t
+    n = 1500
+    ens.init_state()
+    ens.step(n, dt)
+    u = ens.read_state()
+    ens.close()
+    free = ~cs.mesh.fixed.reshape(-1).astype(bool)
+    g = lambda t: stepper.load_factor("sine", t, 5e-3)
+    ref = []
+    for s in range(S):
+        K = assembly.assemble_stiffness(cs.mesh.tri, cs.khat, cs.eh[:, s], cs.mesh.n_nodes)
+        m = assembly.lumped_mass(cs.mesh.tri, cs.area, cs.h[:, s], 1.0, cs.mesh.n_nodes, f[:, s])
+        ref.append(stepper.run_sample(K, m, cs.F.reshape(-1), ~free, dt, n, 50.0, g)["u"])
+    ref = np.stack(ref, axis=1)
+    assert np.all(np.isfinite(u))
+    assert rel_l2(u, ref) <= 1e-10
+
+
 def test_energy_conserved_and_matches_oracle():
     cs = small_case(18, 10, 4, seed=5)
     free = ~cs.mesh.fixed.reshape(-1).astype(bool)
