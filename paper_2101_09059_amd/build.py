@@ -11,7 +11,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libensfem.so")
-SOURCES = ["setup.hip", "step.hip", "stress.hip", "api.hip", "mlp.hip"]
+SOURCES = ["setup.hip", "step.hip", "stress.hip", "api.hip", "mlp.hip", "spde.hip"]
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -18,7 +18,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libensfem.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "ensfem.h")
-HEADERS = [HEADER, os.path.join(os.path.dirname(HERE), "include", "ensfem_surrogate.h")]
+HEADERS = [HEADER, os.path.join(os.path.dirname(HERE), "include", "ensfem_surrogate.h"),
+           os.path.join(os.path.dirname(HERE), "include", "ensfem_spde.h")]
 
 ENS_OK, ENS_EINVAL, ENS_ESTATE, ENS_EWORKSPACE, ENS_EDEVICE, ENS_EUNSTABLE, ENS_ENONFINITE, \
     ENS_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
@@ -112,6 +113,13 @@ _SIGS = {
     "sur_train_step": (_I32, [_P, _P, _P, _I32, ctypes.c_float, _P, _P]),
     "sur_moments": (_I32, [_P, _P, _I64, _P, _P, _P]),
     "sur_cv_moments": (_I32, [_P, _P, _I64, _I32, _P, _P, _I64, _P, _P, _P, _P]),
+    "spde_create": (_I32, [_I32, _P]),
+    "spde_destroy": (_I32, [_P]),
+    "spde_last_error": (ctypes.c_char_p, [_P]),
+    "spde_set_mesh": (_I32, [_P, _I64, _P, _I64, _P]),
+    "spde_workspace_size": (_I32, [_P, _I32, _P]),
+    "spde_bind_workspace": (_I32, [_P, _I32, _P, _SZ]),
+    "spde_sample": (_I32, [_P, _D, _P, _D, _I32, _P, _P, _P]),
 }
 
 
@@ -120,7 +128,7 @@ def header_functions() -> list:
     names = set()
     for h in HEADERS:
         txt = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
-        names |= set(re.findall(r"\b((?:ens|sur)_[a-z_]+)\s*\(", txt))
+        names |= set(re.findall(r"\b((?:ens|sur|spde)_[a-z_]+)\s*\(", txt))
     return sorted(names)
 
 
@@ -371,6 +379,56 @@ class Batch:
         if getattr(self, "_h", None):
             self._lib.ens_batch_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Spde:
+    """SPDE / GMRF Matern sampler (spde_* functions) on one mesh for S
+    samples per call; device workspace via torch."""
+
+    def __init__(self, xyz, tri, S: int, device: int = 0):
+        import torch
+        self._lib = load_library()
+        h = _P()
+        rc = self._lib.spde_create(device, ctypes.byref(h))
+        if rc != ENS_OK:
+            raise EnsfemError(rc, "spde_create failed")
+        self._h = h
+        xyz, tri = _f64(xyz), np.ascontiguousarray(tri, dtype=np.int32)
+        self.n_nodes, self.S = xyz.shape[0], int(S)
+        self._check(self._lib.spde_set_mesh(h, xyz.shape[0], _ptr(xyz), tri.shape[0], _ptr(tri)))
+        n = _SZ()
+        self._check(self._lib.spde_workspace_size(h, self.S, ctypes.byref(n)))
+        self._ws = torch.empty(max(n.value, 1), dtype=torch.uint8, device=f"cuda:{device}")
+        self._check(self._lib.spde_bind_workspace(h, self.S, self._ws.data_ptr(), self._ws.numel()))
+
+    def _check(self, rc: int):
+        if rc != ENS_OK:
+            msg = self._lib.spde_last_error(self._h)
+            raise EnsfemError(rc, msg.decode() if msg else "")
+
+    def sample(self, z, kappa: float, tol: float = 1e-10, max_iter: int = 20000):
+        """x = K^-1 C~^(1/2) z for z [n_nodes, S]; returns (x, iterations,
+        largest relative residual)."""
+        z = _f64(z)
+        if z.shape != (self.n_nodes, self.S):
+            raise ValueError(f"sample: z must have shape {(self.n_nodes, self.S)}")
+        x = np.empty_like(z)
+        it, res = _I32(), ctypes.c_double()
+        self._check(self._lib.spde_sample(self._h, float(kappa), _ptr(z), float(tol), int(max_iter), _ptr(x),
+                                          ctypes.byref(it), ctypes.byref(res)))
+        return x, it.value, res.value
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.spde_destroy(self._h)
+            self._h = None
+        self._ws = None
 
     def __del__(self):
         try:

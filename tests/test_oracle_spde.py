@@ -57,11 +57,11 @@ def test_variance_and_correlation_match_matern():
     e[c] = 1.0
     w = spla.splu(K.tocsc()).solve(e)
     var = float(np.sum(w * w * C))
-    assert abs(var / spde.marginal_variance(kappa) - 1.0) < 0.03
+    assert abs(var / spde.marginal_variance(kappa) - 1.0) < 0.01
     rho = math.sqrt(8.0) / kappa
     j = c + int(round(rho / (side / (n - 1))))            # same row, distance rho
     d = np.linalg.norm(xyz[j] - xyz[c])
     cov = float(np.sum(w * C * spla.splu(K.tocsc()).solve(np.eye(1, n * n, j).ravel())))
     corr = cov / var
     expect = kappa * d * special.k1(kappa * d)
-    assert abs(corr - expect) < 0.02
+    assert abs(corr - expect) < 0.005
