@@ -17,6 +17,7 @@ oracle timed on a bounded sample on the host.
 from __future__ import annotations
 
 import argparse
+import math
 import hashlib
 import json
 import os
@@ -378,6 +379,8 @@ def main():
                     help="skip the shared-stiffness (block-row product) timing")
     ap.add_argument("--no-also-stress", dest="also_stress", action="store_false", default=True,
                     help="skip the wall-stress bands timing")
+    ap.add_argument("--no-also-spde", dest="also_spde", action="store_false", default=True,
+                    help="skip the SPDE field-sampler timing")
     ap.add_argument("--sample-block", type=int, default=0, help="0 = library default")
     ap.add_argument("--sb-inner", action="store_true")
     ap.add_argument("--config", choices=["c2_cylinder", "c3_curved", "c4_batch", "c5_learned"],
@@ -506,6 +509,23 @@ def main():
         torch.cuda.empty_cache()
         log(f"stress bands: {stress_ms:.1f} ms per component")
 
+    spde_out = None
+    if args.also_spde:
+        # S Matern fields on the same mesh by the GPU SPDE sampler (kappa for
+        # rho = 2 cm); host-inclusive (white noise in, fields out)
+        sp = ensfem.Spde(mesh.xyz, mesh.tri, cfg["S"])
+        z = np.random.default_rng(11).standard_normal((mesh.n_nodes, cfg["S"]))
+        sp.sample(z[:, :], math.sqrt(2.0), tol=1e-8, max_iter=20000)
+        t0 = time.perf_counter()
+        _, it, res = sp.sample(z, math.sqrt(2.0), tol=1e-8, max_iter=20000)
+        spde_ms = (time.perf_counter() - t0) * 1e3
+        sp.close()
+        del sp, z
+        torch.cuda.empty_cache()
+        spde_out = {"ms": spde_ms, "iterations": it, "relative_residual": res, "samples": cfg["S"],
+                    "kappa": math.sqrt(2.0)}
+        log(f"spde fields: {spde_ms:.0f} ms for {cfg['S']} samples, {it} CG iterations")
+
     ms, dt, info = results[args.apply]
     S = cfg["S"]
     work = mesh.n_dof * S * args.steps
@@ -549,6 +569,8 @@ def main():
                                  "kernel": "k_apply (node map: rows in the caller's numbering)"}
     if stress_ms is not None:
         out["stress_bands_ms_per_component"] = stress_ms
+    if spde_out is not None:
+        out["spde_fields"] = spde_out
     if args.also_shared:
         out["ms_per_step_shared_stiffness"] = ms_sh / args.steps
         out["value_shared_stiffness"] = work / (ms_sh * 1e-3)
