@@ -22,7 +22,7 @@
 namespace {
 
 constexpr int kRowsWG = 4;      // waves (rows in flight) per workgroup
-constexpr int kPartWG = 1024;   // workgroups along the rows (reduction partials)
+constexpr int kPartWG = 512;    // workgroups along the rows (reduction partials)
 
 __device__ __forceinline__ int wave_row(int64_t& r) {
   r = (int64_t)blockIdx.x * kRowsWG + threadIdx.x / 64;
@@ -89,14 +89,36 @@ __global__ __launch_bounds__(256) void k_spmv(int64_t n, int32_t ld, const int32
   block_partials(pq, 0.0, lane, part_pq, nullptr, col, ld);
 }
 
-// Column sums of partials [kPartWG][ld] -> out [ld], rows in order.
-__global__ __launch_bounds__(256) void k_colsum(int32_t ld, int32_t nparts, const double* __restrict__ part,
-                                                double* __restrict__ out) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c >= ld) return;
-  double s = 0.0;
-  for (int b = 0; b < nparts; ++b) s += part[(int64_t)b * ld + c];
-  out[c] = s;
+// Column sums of one or two partial arrays [nparts][ld] -> out [ld]: a
+// workgroup takes 64 columns, its kColWaves waves sum every kColWaves-th
+// partial row (in order) and their results are added in wave order.
+constexpr int kColWaves = 16;
+
+__global__ __launch_bounds__(64 * kColWaves) void k_colsum(int32_t ld, int32_t nparts,
+                                                           const double* __restrict__ part_a,
+                                                           double* __restrict__ out_a,
+                                                           const double* __restrict__ part_b,
+                                                           double* __restrict__ out_b) {
+  __shared__ double ra[64 * kColWaves], rb[64 * kColWaves];
+  const int lane = threadIdx.x % 64, g = threadIdx.x / 64;
+  const int64_t c = (int64_t)blockIdx.x * 64 + lane;
+  double sa = 0.0, sb = 0.0;
+#pragma unroll 4
+  for (int b = g; b < nparts; b += kColWaves) {
+    sa += part_a[(int64_t)b * ld + c];
+    if (part_b) sb += part_b[(int64_t)b * ld + c];
+  }
+  ra[threadIdx.x] = sa;
+  rb[threadIdx.x] = sb;
+  __syncthreads();
+  if (g == 0) {
+    for (int w = 1; w < kColWaves; ++w) {
+      sa += ra[64 * w + lane];
+      sb += rb[64 * w + lane];
+    }
+    out_a[c] = sa;
+    if (part_b) out_b[c] = sb;
+  }
 }
 
 // alpha = rz / pq; x += alpha p; r -= alpha q; partials of r.D^-1.r, r.r.
@@ -361,15 +383,14 @@ int32_t spde_sample(spde_ctx* s, double kappa, const double* z, double tol, int3
   }
   const dim3 grid((unsigned)std::min<int64_t>(kPartWG, (n + kRowsWG - 1) / kRowsWG), (unsigned)(ld / 64));
   const int nparts = (int)grid.x;
-  const unsigned cgrid = (unsigned)((ld + 255) / 256);
+  const unsigned cgrid = (unsigned)(ld / 64);
   double *X = s->p<double>(s->o_x), *R = s->p<double>(s->o_r), *P = s->p<double>(s->o_p), *Q = s->p<double>(s->o_q);
   double *pa = s->p<double>(s->o_pa), *pb = s->p<double>(s->o_pb);
   double *rz = s->p<double>(s->o_rz), *rz2 = s->p<double>(s->o_rz2), *rr = s->p<double>(s->o_rr);
   double *pq = s->p<double>(s->o_pq), *bb = s->p<double>(s->o_bb);
   const double* dv = s->p<double>(s->o_dinv);
   k_init<<<grid, 256>>>(n, ld, s->p<double>(s->o_sqrtc), dv, s->p<double>(s->o_z), X, R, P, pa, pb);
-  k_colsum<<<cgrid, 256>>>(ld, nparts, pa, rz);
-  k_colsum<<<cgrid, 256>>>(ld, nparts, pb, bb);
+  k_colsum<<<cgrid, 64 * kColWaves>>>(ld, nparts, pa, rz, pb, bb);
   SHIPC(hipGetLastError());
   std::vector<double> hbb(ld), hrr(ld);
   SHIPC(hipMemcpy(hbb.data(), bb, 8 * ld, hipMemcpyDeviceToHost));
@@ -387,10 +408,9 @@ int32_t spde_sample(spde_ctx* s, double kappa, const double* z, double tol, int3
     while (it < max_iter) {
       k_spmv<<<grid, 256>>>(n, ld, s->p<int32_t>(s->o_ptr), s->p<int32_t>(s->o_col), s->p<double>(s->o_val), P, Q,
                             pa);
-      k_colsum<<<cgrid, 256>>>(ld, nparts, pa, pq);
+      k_colsum<<<cgrid, 64 * kColWaves>>>(ld, nparts, pa, pq, nullptr, nullptr);
       k_update_xr<<<grid, 256>>>(n, ld, dv, rz, pq, X, R, P, Q, pa, pb);
-      k_colsum<<<cgrid, 256>>>(ld, nparts, pa, rz2);
-      k_colsum<<<cgrid, 256>>>(ld, nparts, pb, rr);
+      k_colsum<<<cgrid, 64 * kColWaves>>>(ld, nparts, pa, rz2, pb, rr);
       k_update_p<<<grid, 256>>>(n, ld, dv, rz2, rz, R, P);
       SHIPC(hipGetLastError());
       std::swap(rz, rz2);
