@@ -2,11 +2,17 @@
 // x = K^-1 C~^(1/2) z, K = kappa^2 C~ + G, by block conjugate gradients
 // over S right-hand sides with a diagonal preconditioner.
 //
-// Block vectors are [n][ld] with samples fastest (ld = S rounded up to 64);
-// a wave owns one matrix row for 64 samples, so the row's column indices
-// and values are wave-uniform (scalar loads).  Every per-sample scalar of
-// CG (r.z, p.q, r.r) is reduced in a fixed order: per-workgroup partials,
-// then one pass over the partials per column.
+// Block vectors are [n][ld] with samples fastest (ld = S rounded up to 64).
+// A wave owns one matrix row for 64 * SPL samples (SPL consecutive samples
+// per lane, SPL = 4, 2 or 1 as ld allows), so the row's column indices and
+// values are wave-uniform (scalar loads) and each neighbour load moves
+// 512 * SPL contiguous bytes.  The matrix is stored as padded rows (ELL) of
+// width W, a multiple of 8: a row's neighbour loads are issued 8 at a time,
+// for two rows at once in the product.
+//
+// Every per-sample scalar of CG (r.z, p.q, r.r) is reduced in a fixed
+// order: per-workgroup partials, then one pass over the partials per
+// column, so a run is reproducible bit for bit.
 #include "ensfem_spde.h"
 #include "ensfem.h"
 
@@ -22,71 +28,160 @@
 namespace {
 
 constexpr int kRowsWG = 4;      // waves (rows in flight) per workgroup
-constexpr int kPartWG = 512;    // workgroups along the rows (reduction partials)
+constexpr int kPartWG = 512;    // most workgroups along the rows (reduction partials)
+constexpr int kEllChunk = 8;    // ELL width granularity (loads in flight per row)
+constexpr int kRowsWave = 2;    // rows a wave of the product works on at once
 
-__device__ __forceinline__ int wave_row(int64_t& r) {
-  r = (int64_t)blockIdx.x * kRowsWG + threadIdx.x / 64;
-  return threadIdx.x % 64;
+// Rows of this wave: r0, r0 + step, ... below n.
+struct Rows {
+  int64_t r0, step;
+};
+__device__ __forceinline__ Rows wave_rows() {
+  return {(int64_t)blockIdx.x * kRowsWG + threadIdx.x / 64, (int64_t)gridDim.x * kRowsWG};
 }
 
+__device__ __forceinline__ int64_t uniform(int64_t row) {
+  return (int64_t)__builtin_amdgcn_readfirstlane((int)row);
+}
+
+// SPL consecutive doubles of one lane (16-byte aligned for SPL >= 2).
+template <int SPL>
+struct Lane {
+  double v[SPL];
+  __device__ __forceinline__ void load(const double* p) {
+    if constexpr (SPL == 1) {
+      v[0] = *p;
+    } else {
+#pragma unroll
+      for (int k = 0; k < SPL; k += 2) {
+        const double2 t = *reinterpret_cast<const double2*>(p + k);
+        v[k] = t.x;
+        v[k + 1] = t.y;
+      }
+    }
+  }
+  __device__ __forceinline__ void store(double* p) const {
+    if constexpr (SPL == 1) {
+      *p = v[0];
+    } else {
+#pragma unroll
+      for (int k = 0; k < SPL; k += 2) *reinterpret_cast<double2*>(p + k) = make_double2(v[k], v[k + 1]);
+    }
+  }
+};
+
 // Partial sums of up to two per-column quantities over the rows a
-// workgroup visits: LDS tree over its 4 waves, one value per column.
-__device__ __forceinline__ void block_partials(double a, double b, int lane, double* __restrict__ part_a,
-                                               double* __restrict__ part_b, int64_t col, int32_t ld) {
-  __shared__ double ra[256], rb[256];
-  ra[threadIdx.x] = a;
-  rb[threadIdx.x] = b;
+// workgroup visits: its 4 waves added in order; one value per column.
+template <int SPL>
+__device__ __forceinline__ void block_partials(const double (&a)[SPL], const double (&b)[SPL], int lane,
+                                               double* __restrict__ part_a, double* __restrict__ part_b,
+                                               int64_t col, int32_t ld) {
+  __shared__ double ra[256 * SPL], rb[256 * SPL];
+#pragma unroll
+  for (int k = 0; k < SPL; ++k) {
+    ra[threadIdx.x * SPL + k] = a[k];
+    rb[threadIdx.x * SPL + k] = b[k];
+  }
   __syncthreads();
   if (threadIdx.x < 64) {
-    double sa = ra[lane], sb = rb[lane];
-    for (int w = 1; w < kRowsWG; ++w) {
-      sa += ra[64 * w + lane];
-      sb += rb[64 * w + lane];
+#pragma unroll
+    for (int k = 0; k < SPL; ++k) {
+      double sa = ra[lane * SPL + k], sb = rb[lane * SPL + k];
+      for (int w = 1; w < kRowsWG; ++w) {
+        sa += ra[(64 * w + lane) * SPL + k];
+        sb += rb[(64 * w + lane) * SPL + k];
+      }
+      part_a[(int64_t)blockIdx.x * ld + col + k] = sa;
+      if (part_b) part_b[(int64_t)blockIdx.x * ld + col + k] = sb;
     }
-    part_a[(int64_t)blockIdx.x * ld + col] = sa;
-    if (part_b) part_b[(int64_t)blockIdx.x * ld + col] = sb;
   }
 }
 
+template <int SPL>
+__device__ __forceinline__ int64_t lane_col(int lane) {
+  return ((int64_t)blockIdx.y * 64 + lane) * SPL;
+}
+
 // r = sqrt(C~) z, x = 0, p = D^-1 r; partials of r.D^-1.r and r.r.
+template <int SPL>
 __global__ __launch_bounds__(256) void k_init(int64_t n, int32_t ld, const double* __restrict__ sqrtc,
                                               const double* __restrict__ dinv, const double* __restrict__ z,
                                               double* __restrict__ X, double* __restrict__ R,
                                               double* __restrict__ P, double* __restrict__ part_rz,
                                               double* __restrict__ part_rr) {
   const int lane = threadIdx.x % 64;
-  const int64_t col = (int64_t)blockIdx.y * 64 + lane;
-  double rz = 0.0, rr = 0.0;
-  for (int64_t row = (int64_t)blockIdx.x * kRowsWG + threadIdx.x / 64; row < n; row += (int64_t)gridDim.x * kRowsWG) {
-    const int64_t i = row * ld + col;
-    const double r = sqrtc[row] * z[i];
-    const double zz = dinv[row] * r;
-    X[i] = 0.0;
-    R[i] = r;
-    P[i] = zz;
-    rz += r * zz;
-    rr += r * r;
+  const int64_t col = lane_col<SPL>(lane);
+  double rz[SPL] = {}, rr[SPL] = {};
+  const Rows w = wave_rows();
+  for (int64_t row = w.r0; row < n; row += w.step) {
+    const int64_t r = uniform(row);
+    const int64_t i = r * ld + col;
+    Lane<SPL> zz, x, rv, pv;
+    zz.load(z + i);
+#pragma unroll
+    for (int k = 0; k < SPL; ++k) {
+      const double v = sqrtc[r] * zz.v[k];
+      x.v[k] = 0.0;
+      rv.v[k] = v;
+      pv.v[k] = dinv[r] * v;
+      rz[k] = fma(v, pv.v[k], rz[k]);
+      rr[k] = fma(v, v, rr[k]);
+    }
+    x.store(X + i);
+    rv.store(R + i);
+    pv.store(P + i);
   }
-  block_partials(rz, rr, lane, part_rz, part_rr, col, ld);
+  block_partials<SPL>(rz, rr, lane, part_rz, part_rr, col, ld);
 }
 
-// Q = K P (CSR, wave-uniform rows); partials of p.q.
-__global__ __launch_bounds__(256) void k_spmv(int64_t n, int32_t ld, const int32_t* __restrict__ ptr,
-                                              const int32_t* __restrict__ colidx, const double* __restrict__ val,
-                                              const double* __restrict__ P, double* __restrict__ Q,
-                                              double* __restrict__ part_pq) {
+// Q = K P (ELL rows, kRowsWave rows per wave at once); partials of p.q.
+template <int SPL>
+__global__ __launch_bounds__(256) void k_spmv(int64_t n, int32_t ld, int32_t W, const int32_t* __restrict__ ecol,
+                                              const double* __restrict__ eval, const double* __restrict__ P,
+                                              double* __restrict__ Q, double* __restrict__ part_pq) {
   const int lane = threadIdx.x % 64;
-  const int64_t col = (int64_t)blockIdx.y * 64 + lane;
-  double pq = 0.0;
-  for (int64_t row = (int64_t)blockIdx.x * kRowsWG + threadIdx.x / 64; row < n; row += (int64_t)gridDim.x * kRowsWG) {
-    const int r = __builtin_amdgcn_readfirstlane((int)row);
-    const int kb = ptr[r], ke = ptr[r + 1];
-    double q = 0.0;
-    for (int k = kb; k < ke; ++k) q = fma(val[k], P[(int64_t)colidx[k] * ld + col], q);
-    Q[(int64_t)r * ld + col] = q;
-    pq = fma(P[(int64_t)r * ld + col], q, pq);
+  const int64_t col = lane_col<SPL>(lane);
+  double pq[SPL] = {}, zero[SPL] = {};
+  const Rows w = wave_rows();
+  for (int64_t row = w.r0; row < n; row += kRowsWave * w.step) {
+    int64_t r[kRowsWave];
+#pragma unroll
+    for (int m = 0; m < kRowsWave; ++m) {
+      const int64_t rm = row + m * w.step;
+      r[m] = uniform(rm < n ? rm : row);  // a row past the end repeats the first (not stored)
+    }
+    double q[kRowsWave][SPL] = {};
+    for (int c0 = 0; c0 < W; c0 += kEllChunk) {
+      Lane<SPL> pj[kRowsWave][kEllChunk];
+#pragma unroll
+      for (int m = 0; m < kRowsWave; ++m)
+#pragma unroll
+        for (int u = 0; u < kEllChunk; ++u) pj[m][u].load(P + (int64_t)ecol[r[m] * W + c0 + u] * ld + col);
+#pragma unroll
+      for (int m = 0; m < kRowsWave; ++m)
+#pragma unroll
+        for (int u = 0; u < kEllChunk; ++u) {
+          const double a = eval[r[m] * W + c0 + u];
+#pragma unroll
+          for (int k = 0; k < SPL; ++k) q[m][k] = fma(a, pj[m][u].v[k], q[m][k]);
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < kRowsWave; ++m) {
+      if (row + m * w.step < n) {
+        const int64_t i = r[m] * ld + col;
+        Lane<SPL> pv, qv;
+        pv.load(P + i);
+#pragma unroll
+        for (int k = 0; k < SPL; ++k) {
+          qv.v[k] = q[m][k];
+          pq[k] = fma(pv.v[k], q[m][k], pq[k]);
+        }
+        qv.store(Q + i);
+      }
+    }
   }
-  block_partials(pq, 0.0, lane, part_pq, nullptr, col, ld);
+  block_partials<SPL>(pq, zero, lane, part_pq, nullptr, col, ld);
 }
 
 // Column sums of one or two partial arrays [nparts][ld] -> out [ld]: a
@@ -122,38 +217,111 @@ __global__ __launch_bounds__(64 * kColWaves) void k_colsum(int32_t ld, int32_t n
 }
 
 // alpha = rz / pq; x += alpha p; r -= alpha q; partials of r.D^-1.r, r.r.
+template <int SPL>
 __global__ __launch_bounds__(256) void k_update_xr(int64_t n, int32_t ld, const double* __restrict__ dinv,
                                                    const double* __restrict__ rz, const double* __restrict__ pq,
                                                    double* __restrict__ X, double* __restrict__ R,
                                                    const double* __restrict__ P, const double* __restrict__ Q,
                                                    double* __restrict__ part_rz, double* __restrict__ part_rr) {
   const int lane = threadIdx.x % 64;
-  const int64_t col = (int64_t)blockIdx.y * 64 + lane;
-  const double alpha = pq[col] > 0.0 ? rz[col] / pq[col] : 0.0;
-  double srz = 0.0, srr = 0.0;
-  for (int64_t row = (int64_t)blockIdx.x * kRowsWG + threadIdx.x / 64; row < n; row += (int64_t)gridDim.x * kRowsWG) {
-    const int64_t i = row * ld + col;
-    X[i] = fma(alpha, P[i], X[i]);
-    const double r = fma(-alpha, Q[i], R[i]);
-    R[i] = r;
-    srz = fma(r, dinv[row] * r, srz);
-    srr = fma(r, r, srr);
+  const int64_t col = lane_col<SPL>(lane);
+  double alpha[SPL], srz[SPL] = {}, srr[SPL] = {};
+#pragma unroll
+  for (int k = 0; k < SPL; ++k) alpha[k] = pq[col + k] > 0.0 ? rz[col + k] / pq[col + k] : 0.0;
+  const Rows w = wave_rows();
+  for (int64_t row = w.r0; row < n; row += w.step) {
+    const int64_t r = uniform(row);
+    const int64_t i = r * ld + col;
+    Lane<SPL> x, pv, qv, rv;
+    x.load(X + i);
+    pv.load(P + i);
+    qv.load(Q + i);
+    rv.load(R + i);
+#pragma unroll
+    for (int k = 0; k < SPL; ++k) {
+      x.v[k] = fma(alpha[k], pv.v[k], x.v[k]);
+      const double v = fma(-alpha[k], qv.v[k], rv.v[k]);
+      rv.v[k] = v;
+      srz[k] = fma(v, dinv[r] * v, srz[k]);
+      srr[k] = fma(v, v, srr[k]);
+    }
+    x.store(X + i);
+    rv.store(R + i);
   }
-  block_partials(srz, srr, lane, part_rz, part_rr, col, ld);
+  block_partials<SPL>(srz, srr, lane, part_rz, part_rr, col, ld);
 }
 
 // beta = rz_new / rz_old; p = D^-1 r + beta p.
+template <int SPL>
 __global__ __launch_bounds__(256) void k_update_p(int64_t n, int32_t ld, const double* __restrict__ dinv,
                                                   const double* __restrict__ rz_new,
                                                   const double* __restrict__ rz_old, const double* __restrict__ R,
                                                   double* __restrict__ P) {
   const int lane = threadIdx.x % 64;
-  const int64_t col = (int64_t)blockIdx.y * 64 + lane;
-  const double beta = rz_old[col] > 0.0 ? rz_new[col] / rz_old[col] : 0.0;
-  for (int64_t row = (int64_t)blockIdx.x * kRowsWG + threadIdx.x / 64; row < n; row += (int64_t)gridDim.x * kRowsWG) {
-    const int64_t i = row * ld + col;
-    P[i] = fma(beta, P[i], dinv[row] * R[i]);
+  const int64_t col = lane_col<SPL>(lane);
+  double beta[SPL];
+#pragma unroll
+  for (int k = 0; k < SPL; ++k) beta[k] = rz_old[col + k] > 0.0 ? rz_new[col + k] / rz_old[col + k] : 0.0;
+  const Rows w = wave_rows();
+  for (int64_t row = w.r0; row < n; row += w.step) {
+    const int64_t r = uniform(row);
+    const int64_t i = r * ld + col;
+    Lane<SPL> pv, rv;
+    pv.load(P + i);
+    rv.load(R + i);
+#pragma unroll
+    for (int k = 0; k < SPL; ++k) pv.v[k] = fma(beta[k], pv.v[k], dinv[r] * rv.v[k]);
+    pv.store(P + i);
   }
+}
+
+// One CG solve on the bound workspace with SPL samples per lane.
+struct Solve {
+  int64_t n;
+  int32_t ld, W, S;
+  const int32_t* ecol;
+  const double *eval, *dinv, *sqrtc, *z;
+  double *X, *R, *P, *Q, *pa, *pb, *rz, *rz2, *rr, *pq, *bb;
+};
+
+template <int SPL>
+hipError_t cg(const Solve& v, double tol, int32_t max_iter, int& it, double& worst) {
+  const dim3 grid((unsigned)std::min<int64_t>(kPartWG, (v.n + kRowsWG - 1) / kRowsWG),
+                  (unsigned)(v.ld / (64 * SPL)));
+  const int nparts = (int)grid.x;
+  const unsigned cgrid = (unsigned)(v.ld / 64);
+  double *rz = v.rz, *rz2 = v.rz2;
+  k_init<SPL><<<grid, 256>>>(v.n, v.ld, v.sqrtc, v.dinv, v.z, v.X, v.R, v.P, v.pa, v.pb);
+  k_colsum<<<cgrid, 64 * kColWaves>>>(v.ld, nparts, v.pa, rz, v.pb, v.bb);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  std::vector<double> hbb(v.ld), hrr(v.ld);
+  if ((e = hipMemcpy(hbb.data(), v.bb, 8 * (size_t)v.ld, hipMemcpyDeviceToHost)) != hipSuccess) return e;
+  it = 0;
+  auto converged = [&](const std::vector<double>& r2) {
+    worst = 0.0;
+    for (int c = 0; c < v.S; ++c) {
+      const double rel = hbb[c] > 0.0 ? std::sqrt(r2[c] / hbb[c]) : 0.0;
+      worst = std::max(worst, rel);
+    }
+    return worst <= tol;
+  };
+  if (converged(hbb)) return hipSuccess;
+  while (it < max_iter) {
+    k_spmv<SPL><<<grid, 256>>>(v.n, v.ld, v.W, v.ecol, v.eval, v.P, v.Q, v.pa);
+    k_colsum<<<cgrid, 64 * kColWaves>>>(v.ld, nparts, v.pa, v.pq, nullptr, nullptr);
+    k_update_xr<SPL><<<grid, 256>>>(v.n, v.ld, v.dinv, rz, v.pq, v.X, v.R, v.P, v.Q, v.pa, v.pb);
+    k_colsum<<<cgrid, 64 * kColWaves>>>(v.ld, nparts, v.pa, rz2, v.pb, v.rr);
+    k_update_p<SPL><<<grid, 256>>>(v.n, v.ld, v.dinv, rz2, rz, v.R, v.P);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    std::swap(rz, rz2);
+    ++it;
+    if (it % 8 == 0 || it == max_iter) {
+      if ((e = hipMemcpy(hrr.data(), v.rr, 8 * (size_t)v.ld, hipMemcpyDeviceToHost)) != hipSuccess) return e;
+      if (converged(hrr)) break;
+    }
+  }
+  return hipSuccess;
 }
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -168,11 +336,14 @@ struct spde_ctx {
   std::vector<double> g;  // G values in CSR order
   std::vector<int64_t> diag;  // position of (i, i) in CSR
   std::vector<double> cmass;  // lumped mass
+  int32_t W = 0;                // ELL width (multiple of kEllChunk)
+  std::vector<int32_t> ecol;    // [n][W] column of each slot (the row itself in padding)
+  std::vector<int64_t> epos;    // [n][W] CSR position of each slot, -1 in padding
   bool have_mesh = false;
   // workspace
   char* ws = nullptr;
   int32_t S = 0, ld = 0;
-  size_t o_ptr = 0, o_col = 0, o_val = 0, o_dinv = 0, o_sqrtc = 0, o_z = 0, o_x = 0, o_r = 0, o_p = 0, o_q = 0,
+  size_t o_col = 0, o_val = 0, o_dinv = 0, o_sqrtc = 0, o_z = 0, o_x = 0, o_r = 0, o_p = 0, o_q = 0,
          o_pa = 0, o_pb = 0, o_rz = 0, o_rz2 = 0, o_rr = 0, o_pq = 0, o_bb = 0, total = 0;
   bool bound = false;
   template <typename T>
@@ -187,14 +358,13 @@ namespace {
 
 void plan(spde_ctx* s, int32_t S) {
   const int32_t ld = ((S + 63) / 64) * 64;
-  const size_t n = (size_t)s->n, nnz = s->col.size();
+  const size_t n = (size_t)s->n, nnz = n * (size_t)s->W;
   size_t off = 0;
   auto take = [&](size_t b) {
     const size_t o = off;
     off = align256(off + b);
     return o;
   };
-  s->o_ptr = take(4 * (n + 1));
   s->o_col = take(4 * nnz);
   s->o_val = take(8 * nnz);
   s->o_dinv = take(8 * n);
@@ -320,6 +490,23 @@ int32_t spde_set_mesh(spde_ctx* s, int64_t n_nodes, const double* xyz, int64_t n
         if (s->col[k] == i) s->diag[i] = k;
     for (int64_t i = 0; i < n_nodes; ++i)
       if (s->diag[i] < 0) return s->fail(ENS_EINVAL, "spde_set_mesh: node " + std::to_string(i) + " is in no element");
+    int32_t wmax = 0;
+    for (int64_t i = 0; i < n_nodes; ++i) wmax = std::max(wmax, s->ptr[i + 1] - s->ptr[i]);
+    s->W = (wmax + kEllChunk - 1) / kEllChunk * kEllChunk;
+    s->ecol.assign((size_t)n_nodes * s->W, 0);
+    s->epos.assign((size_t)n_nodes * s->W, -1);
+    for (int64_t i = 0; i < n_nodes; ++i) {
+      const int32_t len = s->ptr[i + 1] - s->ptr[i];
+      for (int32_t k = 0; k < s->W; ++k) {
+        const size_t slot = (size_t)i * s->W + k;
+        if (k < len) {
+          s->ecol[slot] = s->col[s->ptr[i] + k];
+          s->epos[slot] = s->ptr[i] + k;
+        } else {
+          s->ecol[slot] = (int32_t)i;
+        }
+      }
+    }
     s->cmass = cm;
     s->n = n_nodes;
     s->have_mesh = true;
@@ -349,8 +536,7 @@ int32_t spde_bind_workspace(spde_ctx* s, int32_t S, void* dptr, size_t bytes) {
   s->ws = static_cast<char*>(dptr);
   s->S = S;
   SHIPC(hipSetDevice(s->device));
-  SHIPC(hipMemcpy(s->p<void>(s->o_ptr), s->ptr.data(), 4 * s->ptr.size(), hipMemcpyHostToDevice));
-  SHIPC(hipMemcpy(s->p<void>(s->o_col), s->col.data(), 4 * s->col.size(), hipMemcpyHostToDevice));
+  SHIPC(hipMemcpy(s->p<void>(s->o_col), s->ecol.data(), 4 * s->ecol.size(), hipMemcpyHostToDevice));
   std::vector<double> sq(s->n);
   for (int64_t i = 0; i < s->n; ++i) sq[i] = std::sqrt(s->cmass[i]);
   SHIPC(hipMemcpy(s->p<void>(s->o_sqrtc), sq.data(), 8 * sq.size(), hipMemcpyHostToDevice));
@@ -374,56 +560,47 @@ int32_t spde_sample(spde_ctx* s, double kappa, const double* z, double tol, int3
     val[s->diag[i]] += kappa * kappa * s->cmass[i];
     dinv[i] = 1.0 / val[s->diag[i]];
   }
-  SHIPC(hipMemcpy(s->p<void>(s->o_val), val.data(), 8 * val.size(), hipMemcpyHostToDevice));
+  {
+    std::vector<double> ev(s->epos.size(), 0.0);
+    for (size_t k = 0; k < ev.size(); ++k)
+      if (s->epos[k] >= 0) ev[k] = val[s->epos[k]];
+    SHIPC(hipMemcpy(s->p<void>(s->o_val), ev.data(), 8 * ev.size(), hipMemcpyHostToDevice));
+  }
   SHIPC(hipMemcpy(s->p<void>(s->o_dinv), dinv.data(), 8 * n, hipMemcpyHostToDevice));
   {
     std::vector<double> zp((size_t)n * ld, 0.0);
     for (int64_t i = 0; i < n; ++i) std::memcpy(&zp[(size_t)i * ld], z + i * S, 8 * (size_t)S);
     SHIPC(hipMemcpy(s->p<void>(s->o_z), zp.data(), 8 * zp.size(), hipMemcpyHostToDevice));
   }
-  const dim3 grid((unsigned)std::min<int64_t>(kPartWG, (n + kRowsWG - 1) / kRowsWG), (unsigned)(ld / 64));
-  const int nparts = (int)grid.x;
-  const unsigned cgrid = (unsigned)(ld / 64);
-  double *X = s->p<double>(s->o_x), *R = s->p<double>(s->o_r), *P = s->p<double>(s->o_p), *Q = s->p<double>(s->o_q);
-  double *pa = s->p<double>(s->o_pa), *pb = s->p<double>(s->o_pb);
-  double *rz = s->p<double>(s->o_rz), *rz2 = s->p<double>(s->o_rz2), *rr = s->p<double>(s->o_rr);
-  double *pq = s->p<double>(s->o_pq), *bb = s->p<double>(s->o_bb);
-  const double* dv = s->p<double>(s->o_dinv);
-  k_init<<<grid, 256>>>(n, ld, s->p<double>(s->o_sqrtc), dv, s->p<double>(s->o_z), X, R, P, pa, pb);
-  k_colsum<<<cgrid, 64 * kColWaves>>>(ld, nparts, pa, rz, pb, bb);
-  SHIPC(hipGetLastError());
-  std::vector<double> hbb(ld), hrr(ld);
-  SHIPC(hipMemcpy(hbb.data(), bb, 8 * ld, hipMemcpyDeviceToHost));
+  Solve v;
+  v.n = n;
+  v.ld = ld;
+  v.W = s->W;
+  v.S = S;
+  v.ecol = s->p<int32_t>(s->o_col);
+  v.eval = s->p<double>(s->o_val);
+  v.dinv = s->p<double>(s->o_dinv);
+  v.sqrtc = s->p<double>(s->o_sqrtc);
+  v.z = s->p<double>(s->o_z);
+  v.X = s->p<double>(s->o_x);
+  v.R = s->p<double>(s->o_r);
+  v.P = s->p<double>(s->o_p);
+  v.Q = s->p<double>(s->o_q);
+  v.pa = s->p<double>(s->o_pa);
+  v.pb = s->p<double>(s->o_pb);
+  v.rz = s->p<double>(s->o_rz);
+  v.rz2 = s->p<double>(s->o_rz2);
+  v.rr = s->p<double>(s->o_rr);
+  v.pq = s->p<double>(s->o_pq);
+  v.bb = s->p<double>(s->o_bb);
   int it = 0;
   double worst = 0.0;
-  auto converged = [&](const std::vector<double>& r2) {
-    worst = 0.0;
-    for (int c = 0; c < S; ++c) {
-      const double rel = hbb[c] > 0.0 ? std::sqrt(r2[c] / hbb[c]) : 0.0;
-      worst = std::max(worst, rel);
-    }
-    return worst <= tol;
-  };
-  if (!converged(hbb)) {
-    while (it < max_iter) {
-      k_spmv<<<grid, 256>>>(n, ld, s->p<int32_t>(s->o_ptr), s->p<int32_t>(s->o_col), s->p<double>(s->o_val), P, Q,
-                            pa);
-      k_colsum<<<cgrid, 64 * kColWaves>>>(ld, nparts, pa, pq, nullptr, nullptr);
-      k_update_xr<<<grid, 256>>>(n, ld, dv, rz, pq, X, R, P, Q, pa, pb);
-      k_colsum<<<cgrid, 64 * kColWaves>>>(ld, nparts, pa, rz2, pb, rr);
-      k_update_p<<<grid, 256>>>(n, ld, dv, rz2, rz, R, P);
-      SHIPC(hipGetLastError());
-      std::swap(rz, rz2);
-      ++it;
-      if (it % 8 == 0 || it == max_iter) {
-        SHIPC(hipMemcpy(hrr.data(), rr, 8 * ld, hipMemcpyDeviceToHost));
-        if (converged(hrr)) break;
-      }
-    }
-  }
+  if (ld % 256 == 0) SHIPC((cg<4>(v, tol, max_iter, it, worst)));
+  else if (ld % 128 == 0) SHIPC((cg<2>(v, tol, max_iter, it, worst)));
+  else SHIPC((cg<1>(v, tol, max_iter, it, worst)));
   SHIPC(hipDeviceSynchronize());
   std::vector<double> xp((size_t)n * ld);
-  SHIPC(hipMemcpy(xp.data(), X, 8 * xp.size(), hipMemcpyDeviceToHost));
+  SHIPC(hipMemcpy(xp.data(), v.X, 8 * xp.size(), hipMemcpyDeviceToHost));
   for (int64_t i = 0; i < n; ++i) std::memcpy(x + i * S, &xp[(size_t)i * ld], 8 * (size_t)S);
   if (iterations) *iterations = it;
   if (max_relres) *max_relres = worst;

@@ -13,7 +13,9 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("nt,nz,S", [(40, 30, 37), (24, 60, 64), (17, 9, 1)])
+# S = 37, 64, 1 run one sample per lane, S = 100 two, S = 256 four; the
+# 65 x 71 tube gives every wave several rows and a ragged last pair
+@pytest.mark.parametrize("nt,nz,S", [(40, 30, 37), (24, 60, 64), (17, 9, 1), (31, 13, 100), (65, 71, 256)])
 def test_samples_match_direct_solve(nt, nz, S):
     m = inputs.cylinder(1.0, 6.0, nt, nz)
     kappa = math.sqrt(2.0)
@@ -27,6 +29,20 @@ def test_samples_match_direct_solve(nt, nz, S):
     say(f"  {it} iterations, relative residual {res:.1e}, max column error {err.max():.1e}")
     assert res <= 1e-12
     assert err.max() <= 1e-9
+
+
+def test_sampler_is_reproducible():
+    """Per-sample reductions run in a fixed order: a second call returns
+    the same fields bit for bit."""
+    m = inputs.cylinder(1.0, 6.0, 33, 41)
+    z = np.random.default_rng(5).standard_normal((m.n_nodes, 256))
+    say("case: spde reproducibility 33x41 S=256")
+    sp = ensfem.Spde(m.xyz, m.tri, 256)
+    x1, it1, _ = sp.sample(z, 1.3, tol=1e-10, max_iter=3000)
+    x2, it2, _ = sp.sample(z, 1.3, tol=1e-10, max_iter=3000)
+    sp.close()
+    assert it1 == it2
+    assert np.array_equal(x1, x2)
 
 
 def test_fields_have_the_matern_variance():
