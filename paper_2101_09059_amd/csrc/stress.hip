@@ -87,8 +87,9 @@ __global__ __launch_bounds__(256) void k_stress(int64_t n_el, int32_t ld, const 
   out[t] = v;
 }
 
-// One workgroup per row: bitonic sort of the row's S values (padded with
-// +inf to a power of two) in LDS, then mean and interpolated quantiles.
+// One workgroup per row (S > 512): bitonic sort of the row's S values
+// (padded with +inf to a power of two) in LDS, then mean and interpolated
+// quantiles.
 __global__ __launch_bounds__(256) void k_bands(int64_t n_rows, int32_t ld, int32_t S, const double* __restrict__ vals,
                                                double p_lo, double p_hi, double* __restrict__ mean,
                                                double* __restrict__ lo, double* __restrict__ hi) {
@@ -137,6 +138,108 @@ __global__ __launch_bounds__(256) void k_bands(int64_t n_rows, int32_t ld, int32
   }
 }
 
+// Value of lane (lane ^ M) for a compile-time lane mask M: DPP quad
+// permutes for 1 and 2, ds_swizzle (bitmask mode, within 32 lanes) up to
+// 16, ds_bpermute for 32.
+template <int M>
+__device__ __forceinline__ int xor_lane_b32(int x, int lane) {
+  if constexpr (M == 1) return __builtin_amdgcn_mov_dpp(x, 0xB1, 0xF, 0xF, true);  // quad_perm(1,0,3,2)
+  else if constexpr (M == 2) return __builtin_amdgcn_mov_dpp(x, 0x4E, 0xF, 0xF, true);  // quad_perm(2,3,0,1)
+  else if constexpr (M < 32) return __builtin_amdgcn_ds_swizzle(x, (M << 10) | 0x1F);
+  else return __builtin_amdgcn_ds_bpermute((lane ^ M) << 2, x);
+}
+
+template <int M>
+__device__ __forceinline__ double xor_lane(double x, int lane) {
+  const int lo = xor_lane_b32<M>(__double2loint(x), lane);
+  const int hi = xor_lane_b32<M>(__double2hiint(x), lane);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double xor_lane(double x, int m, int lane) {
+  switch (m) {
+    case 1: return xor_lane<1>(x, lane);
+    case 2: return xor_lane<2>(x, lane);
+    case 4: return xor_lane<4>(x, lane);
+    case 8: return xor_lane<8>(x, lane);
+    case 16: return xor_lane<16>(x, lane);
+    default: return xor_lane<32>(x, lane);
+  }
+}
+
+// One wave per row for S <= 64 K: element e = K lane + k sits in register
+// k of lane `lane` (+inf past S), so the bitonic network's exchanges at
+// distance j < K stay inside a lane and the others are cross-lane
+// exchanges at lane distance j / K; no LDS array and no barrier.  The
+// mean sums each lane's K values in order, then the lanes by a butterfly.
+template <int K>
+__device__ __forceinline__ double pick(const double (&v)[K], int k) {
+  double x = v[0];
+#pragma unroll
+  for (int t = 1; t < K; ++t)
+    if (t == k) x = v[t];
+  return x;
+}
+
+template <int K>
+__global__ __launch_bounds__(256) void k_bands_wave(int64_t n_rows, int32_t ld, int32_t S,
+                                                    const double* __restrict__ vals, double p_lo, double p_hi,
+                                                    double* __restrict__ mean, double* __restrict__ lo,
+                                                    double* __restrict__ hi) {
+  constexpr int P = 64 * K;
+  const int lane = threadIdx.x % 64;
+  const int64_t row = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  if (row >= n_rows) return;  // whole wave
+  const double* r = vals + row * ld;
+  double v[K];
+  double part = 0.0;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int e = K * lane + k;
+    v[k] = e < S ? r[e] : INFINITY;
+    if (e < S) part += v[k];
+  }
+#pragma unroll
+  for (int size = 2; size <= P; size <<= 1) {
+    // ascending block?  For size >= K the bit lies in the lane index.
+    const bool up_lane = size >= K ? (lane & (size / K)) == 0 : true;
+#pragma unroll
+    for (int j = size >> 1; j > 0; j >>= 1) {
+      if (j >= K) {
+        const int m = j / K;
+        const bool keep_min = ((lane & m) == 0) == up_lane;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          const double b = xor_lane(v[k], m, lane);
+          const double mn = fmin(v[k], b), mx = fmax(v[k], b);
+          v[k] = keep_min ? mn : mx;
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+          if (k & j) continue;
+          const bool up = size >= K ? up_lane : (k & size) == 0;
+          const double mn = fmin(v[k], v[k | j]), mx = fmax(v[k], v[k | j]);
+          v[k] = up ? mn : mx;
+          v[k | j] = up ? mx : mn;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o);
+  const double pl = p_lo * (double)(S - 1), ph = p_hi * (double)(S - 1);
+  const int il = (int)floor(pl), ih = (int)floor(ph);
+  const int il1 = il < S - 1 ? il + 1 : il, ih1 = ih < S - 1 ? ih + 1 : ih;
+  const double a0 = __shfl(pick<K>(v, il % K), il / K), a1 = __shfl(pick<K>(v, il1 % K), il1 / K);
+  const double b0 = __shfl(pick<K>(v, ih % K), ih / K), b1 = __shfl(pick<K>(v, ih1 % K), ih1 / K);
+  if (lane == 0) {
+    mean[row] = part / (double)S;
+    lo[row] = a0 + (pl - (double)il) * (a1 - a0);
+    hi[row] = b0 + (ph - (double)ih) * (b1 - b0);
+  }
+}
+
 inline unsigned grid_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 }  // namespace
@@ -157,7 +260,17 @@ hipError_t launch_bands(int64_t n_rows, int32_t ld, int32_t S, const double* val
                         double* mean, double* lo, double* hi, hipStream_t st) {
   if (n_rows == 0) return hipSuccess;
   if (S < 1 || S > kBandsMax || S > ld) return hipErrorInvalidValue;
-  k_bands<<<(unsigned)n_rows, 256, 0, st>>>(n_rows, ld, S, vals, p_lo, p_hi, mean, lo, hi);
+  const unsigned g4 = grid_for(n_rows, 4);
+  if (S <= 64)
+    k_bands_wave<1><<<g4, 256, 0, st>>>(n_rows, ld, S, vals, p_lo, p_hi, mean, lo, hi);
+  else if (S <= 128)
+    k_bands_wave<2><<<g4, 256, 0, st>>>(n_rows, ld, S, vals, p_lo, p_hi, mean, lo, hi);
+  else if (S <= 256)
+    k_bands_wave<4><<<g4, 256, 0, st>>>(n_rows, ld, S, vals, p_lo, p_hi, mean, lo, hi);
+  else if (S <= 512)
+    k_bands_wave<8><<<g4, 256, 0, st>>>(n_rows, ld, S, vals, p_lo, p_hi, mean, lo, hi);
+  else
+    k_bands<<<(unsigned)n_rows, 256, 0, st>>>(n_rows, ld, S, vals, p_lo, p_hi, mean, lo, hi);
   return hipGetLastError();
 }
 

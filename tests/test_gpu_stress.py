@@ -50,6 +50,28 @@ def test_stress_and_bands_match_oracle(mode, tol):
     ens.close()
 
 
+# S = 100, 256, 512 take the one-wave-per-element sort with 2, 4 and 8
+# values per lane, S = 600 the workgroup sort in LDS
+@pytest.mark.parametrize("S", [100, 256, 512, 600])
+def test_bands_of_wide_ensembles(S):
+    """Mean and 5-95 % band of the library's own stress values against the
+    oracle's percentiles of the same values: the sort must be exact."""
+    cs = small_case(12, 6, S, seed=4)
+    say(f"case: stress bands 12x6 S={S}")
+    ens = ensfem.setup_case(cs.mesh, cs.eh, cs.h, cs.F, alpha=50.0, stress=True)
+    ens.init_state()
+    ens.step(40, cs.dt)
+    axial = _axial(cs.mesh.n_el, 5)
+    for comp in (0, 3):
+        got = ens.stress(axial, comp)
+        mean, lo, hi = ens.stress_bands(axial, comp, 0.05, 0.95)
+        rm, rl, rh = ostress.ensemble_bands(got, 0.05, 0.95)
+        scale = np.abs(got).max()
+        for a, b in ((mean, rm), (lo, rl), (hi, rh)):
+            assert np.max(np.abs(a - b)) <= 1e-13 * scale
+    ens.close()
+
+
 def test_stress_requires_its_flag_and_valid_tangents():
     cs = small_case(12, 6, 8, seed=2)
     say("case: stress error paths")
