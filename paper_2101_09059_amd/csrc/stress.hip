@@ -15,6 +15,10 @@
 namespace ensfem {
 namespace {
 
+// UNI: ld is a multiple of 64, so a wave's 64 threads share one element and
+// the element's connectivity, frame and tangent are wave-uniform (scalar
+// loads).
+template <bool UNI>
 __global__ __launch_bounds__(256) void k_stress(int64_t n_el, int32_t ld, const int32_t* __restrict__ tri,
                                                 const double* __restrict__ frame, const double* __restrict__ u,
                                                 const float* __restrict__ uh, const float* __restrict__ uc,
@@ -23,7 +27,7 @@ __global__ __launch_bounds__(256) void k_stress(int64_t n_el, int32_t ld, const 
                                                 int comp, double* __restrict__ out, int32_t* __restrict__ bad) {
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (t >= n_el * ld) return;
-  const int64_t e = t / ld;
+  const int64_t e = UNI ? (int64_t)__builtin_amdgcn_readfirstlane((int)(t / ld)) : t / ld;
   const int s = (int)(t % ld);
   const double* f = frame + (int64_t)kFrameWords * e;
   double R[3][3];
@@ -251,8 +255,12 @@ hipError_t launch_stress(int64_t n_el, int32_t ld, const int32_t* tri, const dou
   const int64_t n = n_el * ld;
   if (n == 0) return hipSuccess;
   if (comp < 0 || comp > 3) return hipErrorInvalidValue;
-  k_stress<<<grid_for(n, 256), 256, 0, st>>>(n_el, ld, tri, frame, u, uh, uc, eh, h, axial, nu, shear_k, comp,
-                                              out, bad);
+  if (ld % 64 == 0 && n_el <= INT32_MAX)
+    k_stress<true><<<grid_for(n, 256), 256, 0, st>>>(n_el, ld, tri, frame, u, uh, uc, eh, h, axial, nu, shear_k,
+                                                      comp, out, bad);
+  else
+    k_stress<false><<<grid_for(n, 256), 256, 0, st>>>(n_el, ld, tri, frame, u, uh, uc, eh, h, axial, nu, shear_k,
+                                                       comp, out, bad);
   return hipGetLastError();
 }
 
