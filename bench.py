@@ -379,6 +379,9 @@ def main():
                     help="skip the shared-stiffness (block-row product) timing")
     ap.add_argument("--no-also-stress", dest="also_stress", action="store_false", default=True,
                     help="skip the wall-stress bands timing")
+    ap.add_argument("--no-also-geom", dest="also_geom", action="store_false", default=True,
+                    help="skip timing the geometry-refresh step")
+    ap.add_argument("--geom-every", type=int, default=100, help="geometry refresh interval of that leg")
     ap.add_argument("--no-also-spde", dest="also_spde", action="store_false", default=True,
                     help="skip the SPDE field-sampler timing")
     ap.add_argument("--sample-block", type=int, default=0, help="0 = library default")
@@ -437,11 +440,11 @@ def main():
 
     apply_ms = [None]
 
-    def run(apply_f32: bool, steps: int, warmup: int, shared: bool = False):
+    def run(apply_f32: bool, steps: int, warmup: int, shared: bool = False, geom_every: int = 0):
         fields = np.repeat(eh[:, :1], eh.shape[1], axis=1) if shared else eh
         ens = ensfem.setup_case(mesh, fields, h, F, nu=cfg["nu"], shear_k=cfg["shear_k"], rho=cfg["rho"],
                                 alpha=cfg["alpha"], apply_prec=ensfem.F32 if apply_f32 else ensfem.F64,
-                                sample_block=args.sample_block, sb_inner=args.sb_inner)
+                                sample_block=args.sample_block, sb_inner=args.sb_inner, geom_every=geom_every)
         dt = ens.cfl_dt(cfg["safety"])
         ens.init_state()
         stream = torch.cuda.current_stream()
@@ -457,7 +460,7 @@ def main():
         ms = e0.elapsed_time(e1)
         ens.sync()
         info = ens.info()
-        if apply_f32 and not shared:
+        if apply_f32 and not shared and not geom_every:
             # stand-alone FP32 apply R = K(E h) U on [n_dof][S_pad] buffers
             dtype = torch.float32
             U = torch.randn(mesh.n_dof, info["S_pad"], device="cuda", dtype=dtype)
@@ -488,6 +491,14 @@ def main():
         ms_sh, _, info_sh = run(args.apply == "f32", args.steps, args.warmup, shared=True)
         assert info_sh["variant"] == ensfem.VARIANT_CSR_SHARED
         log(f"shared stiffness, apply={args.apply}: {ms_sh / args.steps:.4f} ms/step")
+
+    geom_out = None
+    if args.also_geom:
+        # geometry update: element matrices on each sample's moved geometry,
+        # refreshed every --geom-every steps (the refresh copies included)
+        ms_g, _, _ = run(args.apply == "f32", args.steps, args.warmup, geom_every=args.geom_every)
+        geom_out = {"ms_per_step": ms_g / args.steps, "every": args.geom_every, "apply": args.apply}
+        log(f"geometry refresh every {args.geom_every}, apply={args.apply}: {ms_g / args.steps:.4f} ms/step")
 
     stress_ms = None
     if args.also_stress:
@@ -571,6 +582,8 @@ def main():
         out["stress_bands_ms_per_component"] = stress_ms
     if spde_out is not None:
         out["spde_fields"] = spde_out
+    if geom_out is not None:
+        out["geometry_refresh"] = geom_out
     if args.also_shared:
         out["ms_per_step_shared_stiffness"] = ms_sh / args.steps
         out["value_shared_stiffness"] = work / (ms_sh * 1e-3)

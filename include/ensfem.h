@@ -137,6 +137,22 @@ int32_t ens_set_mass_scaling(ens_ctx* ctx, double dt_target);
  * or non-finite c_d. */
 int32_t ens_set_viscous(ens_ctx* ctx, double c_d);
 
+/* Geometry update with selective stiffness refresh (Sec. 2.3): for every > 0
+ * each sample's element matrices are evaluated on its own deformed
+ * geometry x + u_m, where u_m is that sample's displacement at the last
+ * refresh; the refresh happens after every `every` steps (u_m = u at steps
+ * every, 2 every, ...), and the first interval runs on the reference
+ * geometry (u_m = 0, which is also what the starter uses).  The force is
+ * K(x + u_m) u_n with the total displacement u_n; masses, the load and the
+ * stability bound stay those of the reference geometry.  ens_stress and
+ * ens_apply keep the reference geometry.  Needs the FP64 state
+ * (ENS_STATE_F64) and no energy records: ens_step returns ENS_EUNSUPPORTED
+ * otherwise, and ens_save / ens_load / ens_batch_create refuse such a
+ * context.  0 (the default) turns it off.  Switching it on or off drops the
+ * workspace binding (the snapshot takes 24 B per node and padded sample);
+ * any change resets the state.  ENS_EINVAL for every < 0. */
+int32_t ens_set_geometry_refresh(ens_ctx* ctx, int32_t every);
+
 /* Ensemble fields: eh[n_el*S] = (E h)_{e,s} (element-wise product of
  * modulus and thickness, the scalar that multiplies the reference element
  * stiffness, Sec. 2.2.1 / Sec. 2.4) and h[n_el*S] thickness (lumped mass

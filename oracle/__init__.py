@@ -22,7 +22,10 @@ What it computes, following the paper (arXiv 2101.09059, Li & Schiavazzi):
   * control_variate.py -- multifidelity control-variate mean / variance
                    and its fallback rule;
   * stress.py   -- wall stresses in the local cylindrical frame (Sec. 2.3)
-                   and their ensemble mean / quantile bands.
+                   and their ensemble mean / quantile bands;
+  * geometry.py -- stiffness rebuilt on the moved geometry (geometry update
+                   with selective refresh, Sec. 2.3);
+  * spde.py     -- Matern fields from the SPDE / GMRF formulation (Sec. 2.1).
 
 Every function is pinned by the CPU tests (closed forms, invariants,
 textbook special cases); see each module header for its pins.

@@ -15,6 +15,10 @@ optional explicit viscous force of Sec. 2.3, f_v = -c_d du/dt at t_n, is
 added to f_n with the backward difference du/dt ~ (u_n - u_{n-1}) / dt
 (one coefficient c_d per dof, the update stays explicit).
 
+Optional geometry refresh (Sec. 2.3, oracle/geometry.py): with every > 0 the
+matrix is rebuilt from the moved geometry before steps every, 2 every, ...
+through a callable K_at(u_n).
+
 Start (the paper does not state one): u_0, v_0 given (zero = at rest) and
 u_{-1} = u_0 - dt v_0 + dt^2/2 (M^-1 (f_0 - K u_0 - c_d v_0) - alpha v_0), the
 Taylor start; for a ramped load that starts at zero this is u_{-1} = u_0 = 0.
@@ -61,10 +65,12 @@ def run_sample(K, m_node: np.ndarray, F: np.ndarray, fixed: np.ndarray, dt: floa
                alpha: float, g: Callable[[float], float], radial: Optional[np.ndarray] = None,
                u0: Optional[np.ndarray] = None, v0: Optional[np.ndarray] = None,
                u_prev: Optional[np.ndarray] = None, checkpoints: Sequence[int] = (),
-               energy_every: int = 0, c_d: float = 0.0):
+               energy_every: int = 0, c_d: float = 0.0,
+               K_at: Optional[Callable[[np.ndarray], object]] = None, every: int = 0):
     """Step one sample.  K: scipy sparse [n_dof, n_dof]; m_node [n_nodes];
     F [n_dof]; fixed [n_dof] bool.  If u_prev is given it is u_{-1} and the
-    starter is skipped.  Returns a dict with u (u_N), u_prev (u_{N-1}),
+    starter is skipped.  With every > 0, K = K_at(u_n) before steps
+    n = every, 2 every, ...  Returns a dict with u (u_N), u_prev (u_{N-1}),
     q (peak radial, [n_nodes]), checkpoints {n: u_n}, energy [(n, E_{n+1/2})]."""
     n_dof = K.shape[0]
     minv = np.repeat(1.0 / m_node, 3)
@@ -87,6 +93,8 @@ def run_sample(K, m_node: np.ndarray, F: np.ndarray, fixed: np.ndarray, dt: floa
     energy = []
     m_dof = np.repeat(m_node, 3)
     for n in range(n_steps):
+        if every and n > 0 and n % every == 0:
+            K = K_at(u)
         R = K @ u
         f = g(n * dt) * F - c_d * (u - u_prev) / dt
         u_next = (dt * dt * minv * (f - R) + 2.0 * u - (1.0 - a) * u_prev) / (1.0 + a)
@@ -106,11 +114,12 @@ def run_ensemble(tri: np.ndarray, khat: np.ndarray, area: np.ndarray, eh: np.nda
                  rho: float, F: np.ndarray, fixed: np.ndarray, radial: np.ndarray, dt: float,
                  n_steps: int, alpha: float, g: Callable[[float], float],
                  checkpoints: Sequence[int] = (), energy_every: int = 0,
-                 samples: Optional[Sequence[int]] = None, c_d: float = 0.0):
+                 samples: Optional[Sequence[int]] = None, c_d: float = 0.0, geometry=None):
     """S independent solves, sample by sample (no ensemble batching).
     eh, h [n_el, S]; F [n_nodes, 3]; fixed [n_nodes, 3]; radial [n_nodes, 3].
     Returns u [n_dof, S'], q [n_nodes, S'], checkpoints {n: [n_dof, S']},
-    energy [S'] lists, for the chosen sample columns."""
+    energy [S'] lists, for the chosen sample columns.  geometry = (xyz, nu,
+    shear_k, every) turns on the geometry refresh."""
     n_nodes = radial.shape[0]
     cols = list(range(eh.shape[1])) if samples is None else list(samples)
     Fd = F.reshape(-1)
@@ -120,8 +129,13 @@ def run_ensemble(tri: np.ndarray, khat: np.ndarray, area: np.ndarray, eh: np.nda
     for s in cols:
         K = assembly.assemble_stiffness(tri, khat, eh[:, s], n_nodes)
         m = assembly.lumped_mass(tri, area, h[:, s], rho, n_nodes)
+        kw = {}
+        if geometry is not None:
+            from . import geometry as geo
+            xyz, nu, shear_k, every = geometry
+            kw = dict(every=every, K_at=lambda u, s=s: geo.deformed_stiffness(xyz, tri, u, eh[:, s], nu, shear_k))
         r = run_sample(K, m, Fd, fx, dt, n_steps, alpha, g, radial=radial,
-                       checkpoints=checkpoints, energy_every=energy_every, c_d=c_d)
+                       checkpoints=checkpoints, energy_every=energy_every, c_d=c_d, **kw)
         us.append(r["u"])
         qs.append(r["q"])
         en.append(r["energy"])

@@ -25,7 +25,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
   size_t xyz, tri, khat, area, lam, flags, adj_ptr, adj_el, adj_nb, adj_loc, k64, k32, fixed,
-      radial, perm, F, eh64, eh32, h, minv64, minv32, u[2], uh[2], uc, v, q, qmask, bsr_ptr, bsr_col,
+      radial, perm, F, eh64, eh32, h, minv64, minv32, u[2], uh[2], uc, v, usnap, q, qmask, bsr_ptr, bsr_col,
       adj_slot, bsr64, bsr32, epart, erec, gtab, base, frame, stress,
       mean, var, aux, total;
 };
@@ -61,6 +61,7 @@ struct ens_ctx {
   double nu = 0.49, shear_k = 5.0 / 6.0, rho = 1.0, alpha = 0.0;
   double cd = 0.0;       // explicit viscous force coefficient
   double mass_dt = 0.0;  // mass-scaling target step (0: none)
+  int32_t geom_every = 0;  // geometry refresh interval in steps (0: reference geometry)
   bool have_material = false;
   // ensemble (padded [n_el][ld])
   int32_t S = 0, ld = 0, SB = 0;
@@ -186,6 +187,8 @@ Layout plan(const ens_ctx* c) {
     if (c->state_prec == ENS_STATE_F32_KAHAN) L.uc = take(sizeof(float) * ndof * ld);
     L.v = take(sizeof(float) * ndof * ld);
   }
+  // displacement of the last geometry refresh
+  if (c->geom_every > 0) L.usnap = take(sizeof(double) * ndof * ld);
   if (use_shared(c)) {
     const int64_t nb = (int64_t)c->bsr_col.size();
     L.bsr_ptr = take(sizeof(int32_t) * (nn + 1));
@@ -616,6 +619,16 @@ int32_t ens_set_mass_scaling(ens_ctx* ctx, double dt_target) {
   return ENS_OK;
 }
 
+int32_t ens_set_geometry_refresh(ens_ctx* ctx, int32_t every) {
+  if (!ctx) return ENS_EINVAL;
+  if (every < 0) return ctx->fail(ENS_EINVAL, "ens_set_geometry_refresh: need every >= 0");
+  ctx->gen++;
+  if ((every > 0) != (ctx->geom_every > 0)) ctx->bound = false;  // the snapshot buffer comes or goes
+  ctx->geom_every = every;
+  ctx->state_init = false;
+  return ENS_OK;
+}
+
 int32_t ens_set_viscous(ens_ctx* ctx, double c_d) {
   if (!ctx) return ENS_EINVAL;
   if (!(c_d >= 0.0) || !std::isfinite(c_d)) return ctx->fail(ENS_EINVAL, "ens_set_viscous: need a finite c_d >= 0");
@@ -782,6 +795,8 @@ int32_t ens_init_state(ens_ctx* ctx, const double* u0, const double* v0) {
     }
     HIPC(launch_qoi_init((int32_t)ctx->n_nodes, (int32_t)ld, ctx->p<double>(L.radial),
                          ctx->p<double>(L.u[0]), nullptr, nullptr, ctx->p<double>(L.q), st));
+    // the first refresh interval runs on the reference geometry
+    if (ctx->geom_every > 0) HIPC(hipMemset(ctx->p<void>(L.usnap), 0, sizeof(double) * n));
   } else {
     float* uc = ctx->state_prec == ENS_STATE_F32_KAHAN ? ctx->p<float>(L.uc) : nullptr;
     if (u0) {
@@ -877,6 +892,9 @@ int32_t ens_step(ens_ctx* ctx, int64_t n_steps, double dt, int32_t force, void* 
   if (!(dt > 0.0) || !std::isfinite(dt)) return ctx->fail(ENS_EINVAL, "ens_step: dt must be positive");
   if (ctx->started && dt != ctx->dt)
     return ctx->fail(ENS_EINVAL, "ens_step: dt is fixed once stepping has started (re-init the state to change it)");
+  const bool geom = ctx->geom_every > 0;
+  if (geom && (ctx->state_prec != ENS_STATE_F64 || ctx->energy_every > 0))
+    return ctx->fail(ENS_EUNSUPPORTED, "ens_step: the geometry refresh needs the FP64 state and no energy records");
   const double dt_max = 2.0 / std::sqrt(ctx->omega2);
   if (dt > dt_max && !force)
     return ctx->fail(ENS_EUNSTABLE, "ens_step: dt " + std::to_string(dt) + " exceeds the stability bound " +
@@ -890,6 +908,12 @@ int32_t ens_step(ens_ctx* ctx, int64_t n_steps, double dt, int32_t force, void* 
   StepArgs a = base_args(ctx, f32);
   a.dt = dt;
   a.a = 0.5 * ctx->alpha * dt;
+  if (geom) {
+    a.usnap = gptr(ctx->p<double>(L.usnap));
+    a.xyz = gptr(ctx->p<double>(L.xyz));
+    a.nu = ctx->nu;
+    a.shear_k = ctx->shear_k;
+  }
   if (!ctx->started) {  // Taylor starter at t = 0, fixes dt
     HIPC(launch_schedule(ctx->p<double>(L.gtab), ctx->p<int64_t>(L.base), 1, dt, ctx->sched, st));
     const int32_t rc = run_starter(ctx, dt, st);
@@ -907,7 +931,7 @@ int32_t ens_step(ens_ctx* ctx, int64_t n_steps, double dt, int32_t force, void* 
       const bool energy = ctx->energy_every > 0 && (n % ctx->energy_every) == 0;
       a.j = j;
       set_state_ptrs(ctx, a, 0);
-      HIPC(launch_step(a, f32, ctx->state_prec, ctx->SB, qoi, energy, use_shared(ctx), st));
+      HIPC(launch_step(a, f32, ctx->state_prec, ctx->SB, qoi, energy, use_shared(ctx) && !geom, st));
       if (energy) {
         const int64_t rec = ctx->energy_records % kEnergyCap;
         HIPC(launch_energy_reduce(ctx->p<double>(L.epart), a.n_nb, ctx->ld, ctx->ld,
@@ -916,6 +940,10 @@ int32_t ens_step(ens_ctx* ctx, int64_t n_steps, double dt, int32_t force, void* 
         ctx->energy_records++;
       }
       ctx->cur = 1 - ctx->cur;
+      // geometry refresh: u_{n+1} becomes the snapshot for steps n+1 .. n+every
+      if (geom && (n + 1) % ctx->geom_every == 0)
+        HIPC(launch_copy_f64(3 * ctx->n_nodes * (int64_t)ctx->ld, ctx->p<double>(L.u[ctx->cur]),
+                             ctx->p<double>(L.usnap), st));
     }
     HIPC(launch_advance(ctx->p<int64_t>(L.base), k, st));
     ctx->steps += k;
@@ -1145,6 +1173,8 @@ int32_t ens_save(ens_ctx* ctx, void* host, size_t* bytes) {
   if (!ctx || !bytes) return ENS_EINVAL;
   GUARD_BEGIN
   if (!ctx->bound || !ctx->state_init) return ctx->fail(ENS_ESTATE, "ens_save: no state");
+  if (ctx->geom_every > 0)
+    return ctx->fail(ENS_EUNSUPPORTED, "ens_save: checkpoints do not hold the geometry snapshot");
   const Layout& L = ctx->L;
   const int64_t n = 3 * ctx->n_nodes * (int64_t)ctx->ld, nq = ctx->n_nodes * (int64_t)ctx->ld;
   const bool f64 = ctx->state_prec == ENS_STATE_F64;
@@ -1193,6 +1223,8 @@ int32_t ens_load(ens_ctx* ctx, const void* host, size_t bytes) {
   ctx->gen++;
   GUARD_BEGIN
   if (!ctx->bound) return ctx->fail(ENS_EWORKSPACE, "ens_load: bind a workspace first");
+  if (ctx->geom_every > 0)
+    return ctx->fail(ENS_EUNSUPPORTED, "ens_load: checkpoints do not hold the geometry snapshot");
   if (bytes < sizeof(CkptHeader)) return ctx->fail(ENS_EINVAL, "ens_load: truncated checkpoint");
   CkptHeader hd;
   std::memcpy(&hd, host, sizeof hd);
@@ -1432,6 +1464,7 @@ int32_t ens_batch_create(ens_ctx** ctxs, int32_t n, ens_batch** out) {
     else if ((c->qoi_mask & ENS_QOI_PEAK_RADIAL) != (c0->qoi_mask & ENS_QOI_PEAK_RADIAL))
       why = "all meshes need the same QoI setting";
     else if (c->energy_every != 0) why = "energy records are not available in batched stepping";
+    else if (c->geom_every != 0) why = "the geometry refresh is not available in batched stepping";
     else if (use_shared(c)) why = "batched stepping uses the element-by-element variant only";
     else if (c->ld % 64 != 0) why = "padded width must be a multiple of 64 (ens_set_tuning(ctx, 64, 0) before binding)";
     for (int j = 0; j < i && why.empty(); ++j)

@@ -88,6 +88,10 @@ struct StepArgs {
   double dt, a;        // step, alpha dt / 2
   double cd;           // explicit viscous force coefficient (0: none)
   ENS_GLOBAL double* energy_part; // [n_nb][ld] per node-block energy partial sums
+  // Geometry form (usnap non-null): element matrices from x + u_snap.
+  ENS_GLOBAL const double* usnap; // displacement of the last geometry refresh [n_nodes*3][ld]
+  ENS_GLOBAL const double* xyz;   // reference coordinates [n_nodes][3]
+  double nu, shear_k;
 };
 
 // One work item of the batched step: `count` nodes from `node0` of mesh
@@ -135,6 +139,7 @@ hipError_t launch_apply(const StepArgs& a, bool f32, int sample_block, bool shar
                         void* R, const int32_t* map, hipStream_t st);
 hipError_t launch_schedule(double* gtab, int64_t* base, int32_t k, double dt, Schedule s,
                            hipStream_t st);
+hipError_t launch_copy_f64(int64_t n, const double* src, double* dst, hipStream_t st);
 hipError_t launch_advance(int64_t* base, int32_t k, hipStream_t st);
 hipError_t launch_energy_reduce(const double* part, int32_t n_nb, int32_t ld, int32_t S,
                                 double* out_row, hipStream_t st);

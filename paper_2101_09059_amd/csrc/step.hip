@@ -260,6 +260,137 @@ __device__ __forceinline__ void gather_blocks(const StepArgs& p, int node, int64
   }
 }
 
+// Geometry form: R for one node from element matrices evaluated on the
+// refreshed geometry x + u_snap of each sample (matrix-free, no stored
+// K^e).  For the element (i, b, c) of the walk, with a = P_b - P_i and
+// w = P_c - P_i: e_x = a/|a|, e_z = a x w/|a x w|, e_y = e_z x e_x; node i
+// sits at the local origin, b at (x2, 0), c at (x3, y3).  The local
+// differences d_b = R (u_b - u_i), d_c = R (u_c - u_i) give the strains
+// (the rows of the strain-displacement matrix: du_x/dx, du_y/dy, gamma_xy,
+// du_z/dx, du_z/dy, Sec. 2.2.1), the constitutive matrix per unit (E h)
+// the stresses, and node i's force A B_i^T sigma is rotated back to global
+// axes.  The element matrix is invariant under a proper rotation of its
+// local frame (isotropic material), so the walk's vertex order serves as
+// well as the connectivity's.  Edge vectors are formed in FP64 before the
+// conversion to AT.
+template <typename AT, int SPL, bool UNI>
+__device__ __forceinline__ void gather_geom(const StepArgs& p, int node, int64_t ld, int s0,
+                                            const double* __restrict__ U, const double (&ua)[3][SPL],
+                                            AT (&r)[3][SPL]) {
+  const int kb = maybe_uni<UNI>(cst(p.adj.ptr)[node]);
+  const int ke = maybe_uni<UNI>(cst(p.adj.ptr)[node + 1]);
+  const AT* __restrict__ EH = static_cast<const AT*>(gen(p.eh));
+  const double* __restrict__ US = gen(p.usnap);
+  const ConstPtr<double> X = cst(p.xyz);
+  const int64_t row = (int64_t)node * 3;
+  const AT nu = (AT)p.nu;
+  const AT c0 = (AT)(1.0 / (1.0 - p.nu * p.nu));
+  const AT cg = (AT)(0.5 * (1.0 - p.nu) / (1.0 - p.nu * p.nu));
+  const AT cs = (AT)(0.5 * p.shear_k * (1.0 - p.nu) / (1.0 - p.nu * p.nu));
+  double xi[3], si[3][SPL];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    xi[c] = maybe_uni<UNI>(X[row + c]);
+    vload<SPL, false>(US + (row + c) * ld + s0, si[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < SPL; ++i) r[c][i] = AT(0);
+  double ub[3][SPL], uc[3][SPL], sb[3][SPL], sc[3][SPL], xb[3], xc[3];
+#pragma unroll 2
+  for (int k = kb; k < ke; ++k) {
+    const int64_t e = maybe_uni<UNI>(cst(p.adj.el)[k]);
+    const ConstPtr<int> nb = (ConstPtr<int>)cst(p.adj.nb);
+    const int bx = maybe_uni<UNI>(nb[2 * k]);
+    const int cx = maybe_uni<UNI>(nb[2 * k + 1]);
+    AT eh[SPL];
+    vload<SPL, false>(EH + e * ld + s0, eh);
+    // bx < 0: this element's first neighbour is the previous one's second
+    if (bx >= 0) {
+      const int64_t rb = (int64_t)bx * 3;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        xb[c] = maybe_uni<UNI>(X[rb + c]);
+        vload<SPL, false>(U + (rb + c) * ld + s0, ub[c]);
+        vload<SPL, false>(US + (rb + c) * ld + s0, sb[c]);
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        xb[c] = xc[c];
+#pragma unroll
+        for (int i = 0; i < SPL; ++i) {
+          ub[c][i] = uc[c][i];
+          sb[c][i] = sc[c][i];
+        }
+      }
+    }
+    const int64_t rc = (int64_t)cx * 3;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      xc[c] = maybe_uni<UNI>(X[rc + c]);
+      vload<SPL, false>(U + (rc + c) * ld + s0, uc[c]);
+      vload<SPL, false>(US + (rc + c) * ld + s0, sc[c]);
+    }
+#pragma unroll
+    for (int i = 0; i < SPL; ++i) {
+      AT a[3], w[3], db[3], dc[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        a[c] = (AT)((xb[c] - xi[c]) + (sb[c][i] - si[c][i]));
+        w[c] = (AT)((xc[c] - xi[c]) + (sc[c][i] - si[c][i]));
+        db[c] = (AT)(ub[c][i] - ua[c][i]);
+        dc[c] = (AT)(uc[c][i] - ua[c][i]);
+      }
+      // frame
+      const AT aa = fma(a[2], a[2], fma(a[1], a[1], a[0] * a[0]));
+      const AT ia = (AT)1 / sqrt(aa);  // 1 / x2
+      const AT ex[3] = {a[0] * ia, a[1] * ia, a[2] * ia};
+      const AT n[3] = {fma(a[1], w[2], -(a[2] * w[1])), fma(a[2], w[0], -(a[0] * w[2])),
+                       fma(a[0], w[1], -(a[1] * w[0]))};
+      const AT nn = fma(n[2], n[2], fma(n[1], n[1], n[0] * n[0]));
+      const AT in = (AT)1 / sqrt(nn);
+      const AT ez[3] = {n[0] * in, n[1] * in, n[2] * in};
+      const AT ey[3] = {fma(ez[1], ex[2], -(ez[2] * ex[1])), fma(ez[2], ex[0], -(ez[0] * ex[2])),
+                        fma(ez[0], ex[1], -(ez[1] * ex[0]))};
+      const AT area = (AT)0.5 * (nn * in);                   // x2 y3 / 2
+      const AT x3 = fma(w[2], ex[2], fma(w[1], ex[1], w[0] * ex[0]));
+      const AT iy = (aa * ia) * in;                          // 1 / y3 = x2 / |n|
+      const AT q = x3 * ia * iy;                             // x3 / (x2 y3)
+      // local differences
+      const AT b0 = fma(ex[2], db[2], fma(ex[1], db[1], ex[0] * db[0]));
+      const AT b1 = fma(ey[2], db[2], fma(ey[1], db[1], ey[0] * db[0]));
+      const AT b2 = fma(ez[2], db[2], fma(ez[1], db[1], ez[0] * db[0]));
+      const AT d0 = fma(ex[2], dc[2], fma(ex[1], dc[1], ex[0] * dc[0]));
+      const AT d1 = fma(ey[2], dc[2], fma(ey[1], dc[1], ey[0] * dc[0]));
+      const AT d2 = fma(ez[2], dc[2], fma(ez[1], dc[1], ez[0] * dc[0]));
+      // strains
+      const AT exx = b0 * ia;
+      const AT eyy = fma(d1, iy, -(q * b1));
+      const AT gxy = fma(b1, ia, fma(d0, iy, -(q * b0)));
+      const AT gxz = b2 * ia;
+      const AT gyz = fma(d2, iy, -(q * b2));
+      // stresses per unit (E h)
+      const AT sxx = c0 * fma(nu, eyy, exx);
+      const AT syy = c0 * fma(nu, exx, eyy);
+      const AT txy = cg * gxy;
+      const AT txz = cs * gxz;
+      const AT tyz = cs * gyz;
+      // node i: dN/dx = -1/x2, dN/dy = x3/(x2 y3) - 1/y3
+      const AT gx = -ia, gy = q - iy;
+      const AT fx = area * fma(gy, txy, gx * sxx);
+      const AT fy = area * fma(gx, txy, gy * syy);
+      const AT fz = area * fma(gy, tyz, gx * txz);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const AT fg = fma(ez[c], fz, fma(ey[c], fy, ex[c] * fx));
+        r[c][i] = fma(eh[i], fg, r[c][i]);
+      }
+    }
+  }
+}
+
 // At-max bits use a sample-indexed layout, independent of the lane mapping:
 // per node ld/64 words, sample s in word s/64, bit s%64.  With SPL samples
 // per lane, lane l holds samples SPL*l + i of its block: word
@@ -290,9 +421,10 @@ __device__ __forceinline__ uint64_t spread_bits(uint64_t x) {
 // stiffness apply, central-difference update, QoI and energy terms.
 // `lane` in [0, LPN); samples base + lane*SPL + i (base a multiple of
 // LPN*SPL, and of 64 when LPN = 64).
-template <typename AT, int MODE, int LPN, int SPL, bool QOI, bool ENERGY, bool SHARED>
+template <typename AT, int MODE, int LPN, int SPL, bool QOI, bool ENERGY, bool SHARED, bool GEOM = false>
 __device__ __forceinline__ void step_node(const StepArgs& p, int j, int node, int base, int lane,
                                           double (&e_loc)[SPL]) {
+  static_assert(!GEOM || (MODE == kStateF64 && !SHARED && !ENERGY), "geometry form: FP64 state only");
   const int s0 = base + lane * SPL;
   const int64_t ld = p.ld;
   using ST = typename std::conditional<MODE == kStateF64, double, float>::type;
@@ -320,7 +452,8 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int j, int node, in
   }
   AT r[3][SPL];
   constexpr bool UNI = LPN == 64;
-  if constexpr (SHARED) gather_blocks<AT, ST, SPL, UNI>(p, node, ld, s0, U, ua, r);
+  if constexpr (GEOM) gather_geom<AT, SPL, UNI>(p, node, ld, s0, U, ua, r);
+  else if constexpr (SHARED) gather_blocks<AT, ST, SPL, UNI>(p, node, ld, s0, U, ua, r);
   else gather_apply<AT, ST, SPL, UNI>(p, node, ld, s0, U, ua, r);
 
   const double g = maybe_uni<UNI>(cst(p.gtab)[j]);
@@ -486,7 +619,7 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int j, int node, in
 // LPN lanes per node, SPL consecutive samples per lane: a workgroup covers
 // kBlock/LPN nodes times LPN*SPL samples.  With LPN = 64 a wave owns one
 // node, so adjacency and stiffness blocks are wave-uniform (scalar loads).
-template <typename AT, int MODE, int LPN, int SPL, bool QOI, bool ENERGY, bool SHARED>
+template <typename AT, int MODE, int LPN, int SPL, bool QOI, bool ENERGY, bool SHARED, bool GEOM = false>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
   constexpr int NPB = kBlock / LPN;
   int nb, sbk;
@@ -499,7 +632,7 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
 #pragma unroll
   for (int i = 0; i < SPL; ++i) e_loc[i] = 0.0;
   if (node < p.n_nodes)
-    step_node<AT, MODE, LPN, SPL, QOI, ENERGY, SHARED>(p, p.j, node, sbk * LPN * SPL, lane, e_loc);
+    step_node<AT, MODE, LPN, SPL, QOI, ENERGY, SHARED, GEOM>(p, p.j, node, sbk * LPN * SPL, lane, e_loc);
   if constexpr (ENERGY) {
     __shared__ double red[kBlock * SPL];
 #pragma unroll
@@ -591,6 +724,11 @@ __global__ __launch_bounds__(256) void k_schedule(double* __restrict__ gtab,
                                                   double dt, Schedule sc) {
   const int64_t n0 = *base;
   for (int j = threadIdx.x; j < k; j += 256) gtab[j] = load_factor(sc, (double)(n0 + j) * dt);
+}
+
+__global__ __launch_bounds__(256) void k_copy_f64(int64_t n, const double* __restrict__ src,
+                                                  double* __restrict__ dst) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) dst[i] = src[i];
 }
 
 __global__ void k_advance(int64_t* base, int32_t k) {
@@ -798,6 +936,27 @@ hipError_t dispatch_sb(const StepArgs& a, int sb, bool qoi, bool energy, hipStre
   }
 }
 
+template <typename AT, int LPN, int SPL>
+hipError_t dispatch_geom_flags(const StepArgs& a, bool qoi, hipStream_t st) {
+  const unsigned g = step_grid(a);
+  if (qoi) k_step<AT, kStateF64, LPN, SPL, true, false, false, true><<<g, kBlock, 0, st>>>(a);
+  else k_step<AT, kStateF64, LPN, SPL, false, false, false, true><<<g, kBlock, 0, st>>>(a);
+  return hipGetLastError();
+}
+
+template <typename AT>
+hipError_t dispatch_geom(const StepArgs& a, int sb, bool qoi, hipStream_t st) {
+  switch (sb) {
+    case 8: return dispatch_geom_flags<AT, 8, 1>(a, qoi, st);
+    case 16: return dispatch_geom_flags<AT, 16, 1>(a, qoi, st);
+    case 32: return dispatch_geom_flags<AT, 32, 1>(a, qoi, st);
+    case 64: return dispatch_geom_flags<AT, 64, 1>(a, qoi, st);
+    case 128: return dispatch_geom_flags<AT, 64, 2>(a, qoi, st);
+    case 256: return dispatch_geom_flags<AT, 64, 4>(a, qoi, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <typename AT, int MODE>
 hipError_t dispatch_shared(const StepArgs& a, int sb, bool qoi, bool energy, bool shared, hipStream_t st) {
   return shared ? dispatch_sb<AT, MODE, true>(a, sb, qoi, energy, st)
@@ -834,6 +993,10 @@ hipError_t dispatch_apply_map(const StepArgs& a, int sb, const void* U, void* R,
 hipError_t launch_step(const StepArgs& a, bool apply_f32, int mode, int sample_block, bool qoi,
                        bool energy, bool shared, hipStream_t st) {
   if (a.n_nb == 0 || a.n_sb == 0) return hipSuccess;
+  if (a.usnap) {  // geometry form
+    if (mode != kStateF64 || energy || shared) return hipErrorInvalidValue;
+    return apply_f32 ? dispatch_geom<float>(a, sample_block, qoi, st) : dispatch_geom<double>(a, sample_block, qoi, st);
+  }
   if (!apply_f32) {
     if (mode != kStateF64) return hipErrorInvalidValue;
     return dispatch_shared<double, kStateF64>(a, sample_block, qoi, energy, shared, st);
@@ -886,6 +1049,13 @@ hipError_t launch_batch_step(const BatchTile* tiles, int32_t n_tiles, int spl, c
 hipError_t launch_schedule(double* gtab, int64_t* base, int32_t k, double dt, Schedule s,
                            hipStream_t st) {
   k_schedule<<<1, 256, 0, st>>>(gtab, base, k, dt, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_f64(int64_t n, const double* src, double* dst, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const unsigned g = (unsigned)std::min<int64_t>(grid_for(n, 256), 65536);
+  k_copy_f64<<<g, 256, 0, st>>>(n, src, dst);
   return hipGetLastError();
 }
 

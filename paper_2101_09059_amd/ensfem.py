@@ -75,6 +75,7 @@ _SIGS = {
     "ens_set_material": (_I32, [_P, _D, _D, _D, _D]),
     "ens_set_viscous": (_I32, [_P, _D]),
     "ens_set_mass_scaling": (_I32, [_P, _D]),
+    "ens_set_geometry_refresh": (_I32, [_P, _I32]),
     "ens_set_ensemble": (_I32, [_P, _I32, _P, _P]),
     "ens_set_load": (_I32, [_P, _P, Schedule]),
     "ens_configure": (_I32, [_P, _I32, _I32, _I32, _I32, _I32]),
@@ -222,6 +223,11 @@ class Ensemble:
         """Scale element densities so the stable step is at least dt_target
         (0: off); drops the workspace binding."""
         self._check(self._lib.ens_set_mass_scaling(self._h, float(dt_target)))
+
+    def set_geometry_refresh(self, every: int):
+        """Element matrices on each sample's deformed geometry, refreshed
+        every `every` steps (0: reference geometry); resets the state."""
+        self._check(self._lib.ens_set_geometry_refresh(self._h, int(every)))
 
     def set_viscous(self, c_d: float):
         """Explicit viscous force -c_d du/dt (backward difference); resets the state."""
@@ -557,7 +563,7 @@ def setup_case(mesh, eh, h, F, nu=0.49, shear_k=5.0 / 6.0, rho=1.0, alpha=50.0,
                kind=LOAD_STEP, t_ramp=0.0, amp=0.0, period=1.0, apply_prec=F64,
                state_prec=STATE_F64, qoi=True, energy_every=0, device=0,
                sample_block=0, sb_inner=False, variant=VARIANT_AUTO, c_d=0.0, stress=False,
-               mass_dt=0.0) -> Ensemble:
+               mass_dt=0.0, geom_every=0) -> Ensemble:
     """Create, fill, configure and bind a context for one mesh and ensemble."""
     ens = Ensemble(device)
     ens.set_mesh(mesh.xyz, mesh.tri, mesh.fixed, mesh.radial)
@@ -566,6 +572,8 @@ def setup_case(mesh, eh, h, F, nu=0.49, shear_k=5.0 / 6.0, rho=1.0, alpha=50.0,
         ens.set_viscous(c_d)
     if mass_dt:
         ens.set_mass_scaling(mass_dt)
+    if geom_every:
+        ens.set_geometry_refresh(geom_every)
     ens.set_ensemble(eh, h)
     ens.set_load(F, kind, t_ramp, amp, period)
     ens.configure(apply_prec, state_prec, variant, qoi, energy_every, stress)
