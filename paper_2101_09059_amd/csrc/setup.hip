@@ -250,15 +250,16 @@ __global__ __launch_bounds__(256) void k_cfl_max(int64_t n_el, int32_t ld, int32
                                                  const double* __restrict__ area, double rho, double dt_t,
                                                  unsigned long long* __restrict__ out_bits) {
   __shared__ double red[256];
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double w = 0.0;
-  if (t < n_el * S) {
+  // grid-stride: one atomic per workgroup, not per element-sample
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n_el * S; t += (int64_t)gridDim.x * 256) {
     const int64_t e = t / S;
     const int s = (int)(t % S);
     const double E = eh[e * ld + s] / h[e * ld + s];
-    w = 3.0 * E * (lam[e] / (rho * area[e]));
-    if (dt_t > 0.0) w = w / mass_factor(eh[e * ld + s], h[e * ld + s], lam[e], area[e], rho, dt_t);
-    if (!(w >= 0.0)) w = INFINITY;  // NaN -> flagged as unbounded
+    double v = 3.0 * E * (lam[e] / (rho * area[e]));
+    if (dt_t > 0.0) v = v / mass_factor(eh[e * ld + s], h[e * ld + s], lam[e], area[e], rho, dt_t);
+    if (!(v >= 0.0)) v = INFINITY;  // NaN -> flagged as unbounded
+    w = fmax(w, v);
   }
   red[threadIdx.x] = w;
   __syncthreads();
@@ -343,7 +344,8 @@ hipError_t launch_cfl_max(int64_t n_el, int32_t ld, int32_t S, const double* eh,
                           unsigned long long* out_bits, hipStream_t st) {
   const int64_t n = n_el * S;
   if (n == 0) return hipSuccess;
-  k_cfl_max<<<grid_for(n, 256), 256, 0, st>>>(n_el, ld, S, eh, h, lam, area, rho, dt_t, out_bits);
+  const unsigned g = grid_for(n, 256) < 2048u ? grid_for(n, 256) : 2048u;
+  k_cfl_max<<<g, 256, 0, st>>>(n_el, ld, S, eh, h, lam, area, rho, dt_t, out_bits);
   return hipGetLastError();
 }
 

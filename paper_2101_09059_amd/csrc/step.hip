@@ -273,6 +273,9 @@ __device__ __forceinline__ void gather_blocks(const StepArgs& p, int node, int64
 // local frame (isotropic material), so the walk's vertex order serves as
 // well as the connectivity's.  Edge vectors are formed in FP64 before the
 // conversion to AT.
+__device__ __forceinline__ float rsq(float x) { return rsqrtf(x); }
+__device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
+
 template <typename AT, int SPL, bool UNI>
 __device__ __forceinline__ void gather_geom(const StepArgs& p, int node, int64_t ld, int s0,
                                             const double* __restrict__ U, const double (&ua)[3][SPL],
@@ -345,12 +348,12 @@ __device__ __forceinline__ void gather_geom(const StepArgs& p, int node, int64_t
       }
       // frame
       const AT aa = fma(a[2], a[2], fma(a[1], a[1], a[0] * a[0]));
-      const AT ia = (AT)1 / sqrt(aa);  // 1 / x2
+      const AT ia = rsq(aa);  // 1 / x2
       const AT ex[3] = {a[0] * ia, a[1] * ia, a[2] * ia};
       const AT n[3] = {fma(a[1], w[2], -(a[2] * w[1])), fma(a[2], w[0], -(a[0] * w[2])),
                        fma(a[0], w[1], -(a[1] * w[0]))};
       const AT nn = fma(n[2], n[2], fma(n[1], n[1], n[0] * n[0]));
-      const AT in = (AT)1 / sqrt(nn);
+      const AT in = rsq(nn);
       const AT ez[3] = {n[0] * in, n[1] * in, n[2] * in};
       const AT ey[3] = {fma(ez[1], ex[2], -(ez[2] * ex[1])), fma(ez[2], ex[0], -(ez[0] * ex[2])),
                         fma(ez[0], ex[1], -(ez[1] * ex[0]))};
