@@ -138,19 +138,21 @@ int32_t ens_set_mass_scaling(ens_ctx* ctx, double dt_target);
 int32_t ens_set_viscous(ens_ctx* ctx, double c_d);
 
 /* Geometry update with selective stiffness refresh (Sec. 2.3): for every > 0
- * each sample's element matrices are evaluated on its own deformed
- * geometry x + u_m, where u_m is that sample's displacement at the last
- * refresh; the refresh happens after every `every` steps (u_m = u at steps
- * every, 2 every, ...), and the first interval runs on the reference
- * geometry (u_m = 0, which is also what the starter uses).  The force is
- * K(x + u_m) u_n with the total displacement u_n; masses, the load and the
- * stability bound stay those of the reference geometry.  ens_stress and
- * ens_apply keep the reference geometry.  Needs the FP64 state
+ * each sample's element matrices are evaluated on its own moved geometry
+ * x + u_m, where u_m is that sample's displacement at the last refresh
+ * (steps m = every, 2 every, ...; the first interval is the linear model,
+ * u_0 = 0).  The internal force is carried incrementally:
+ * R_n = R_m + K(x + u_m) (u_n - u_m), and a refresh at step m first moves
+ * the base to R_m = R_m' + K(x + u_m') (u_m - u_m'), so the force does not
+ * jump when the matrix changes.  Masses, the load and the stability bound
+ * stay those of the reference geometry; the starter, ens_stress and
+ * ens_apply use the reference geometry.  Needs the FP64 state
  * (ENS_STATE_F64) and no energy records: ens_step returns ENS_EUNSUPPORTED
  * otherwise, and ens_save / ens_load / ens_batch_create refuse such a
  * context.  0 (the default) turns it off.  Switching it on or off drops the
- * workspace binding (the snapshot takes 24 B per node and padded sample);
- * any change resets the state.  ENS_EINVAL for every < 0. */
+ * workspace binding (the snapshot u_m and the base R_m take 48 B per node
+ * and padded sample); any change resets the state.  ENS_EINVAL for
+ * every < 0. */
 int32_t ens_set_geometry_refresh(ens_ctx* ctx, int32_t every);
 
 /* Ensemble fields: eh[n_el*S] = (E h)_{e,s} (element-wise product of

@@ -16,8 +16,10 @@ added to f_n with the backward difference du/dt ~ (u_n - u_{n-1}) / dt
 (one coefficient c_d per dof, the update stays explicit).
 
 Optional geometry refresh (Sec. 2.3, oracle/geometry.py): with every > 0 the
-matrix is rebuilt from the moved geometry before steps every, 2 every, ...
-through a callable K_at(u_n).
+internal force is carried incrementally, R_n = R_m + K_m (u_n - u_m), and
+before steps m = every, 2 every, ... the base moves to R_m = R_{m'} +
+K_{m'} (u_m - u_{m'}) and the matrix is rebuilt on the moved geometry,
+K_m = K_at(u_m).
 
 Start (the paper does not state one): u_0, v_0 given (zero = at rest) and
 u_{-1} = u_0 - dt v_0 + dt^2/2 (M^-1 (f_0 - K u_0 - c_d v_0) - alpha v_0), the
@@ -66,11 +68,13 @@ def run_sample(K, m_node: np.ndarray, F: np.ndarray, fixed: np.ndarray, dt: floa
                u0: Optional[np.ndarray] = None, v0: Optional[np.ndarray] = None,
                u_prev: Optional[np.ndarray] = None, checkpoints: Sequence[int] = (),
                energy_every: int = 0, c_d: float = 0.0,
-               K_at: Optional[Callable[[np.ndarray], object]] = None, every: int = 0):
+               K_at: Optional[Callable[[np.ndarray], object]] = None, every: int = 0,
+               R_base: Optional[np.ndarray] = None, u_base: Optional[np.ndarray] = None):
     """Step one sample.  K: scipy sparse [n_dof, n_dof]; m_node [n_nodes];
     F [n_dof]; fixed [n_dof] bool.  If u_prev is given it is u_{-1} and the
-    starter is skipped.  With every > 0, K = K_at(u_n) before steps
-    n = every, 2 every, ...  Returns a dict with u (u_N), u_prev (u_{N-1}),
+    starter is skipped.  The internal force is R_base + K (u - u_base)
+    (zero by default); with every > 0, before steps n = every, 2 every, ...
+    R_base += K (u_n - u_base), u_base = u_n, K = K_at(u_n).  Returns a dict with u (u_N), u_prev (u_{N-1}),
     q (peak radial, [n_nodes]), checkpoints {n: u_n}, energy [(n, E_{n+1/2})]."""
     n_dof = K.shape[0]
     minv = np.repeat(1.0 / m_node, 3)
@@ -92,10 +96,15 @@ def run_sample(K, m_node: np.ndarray, F: np.ndarray, fixed: np.ndarray, dt: floa
         cps[0] = u.copy()
     energy = []
     m_dof = np.repeat(m_node, 3)
+    offset = R_base is not None or u_base is not None or every
+    Rb = np.zeros(n_dof) if R_base is None else np.array(R_base, dtype=np.float64)
+    ub = np.zeros(n_dof) if u_base is None else np.array(u_base, dtype=np.float64)
     for n in range(n_steps):
         if every and n > 0 and n % every == 0:
+            Rb = Rb + K @ (u - ub)
+            ub = u.copy()
             K = K_at(u)
-        R = K @ u
+        R = Rb + K @ (u - ub) if offset else K @ u
         f = g(n * dt) * F - c_d * (u - u_prev) / dt
         u_next = (dt * dt * minv * (f - R) + 2.0 * u - (1.0 - a) * u_prev) / (1.0 + a)
         u_next[fixed] = 0.0
@@ -107,7 +116,7 @@ def run_sample(K, m_node: np.ndarray, F: np.ndarray, fixed: np.ndarray, dt: floa
         u_prev, u = u, u_next
         if (n + 1) in checkpoints:
             cps[n + 1] = u.copy()
-    return dict(u=u, u_prev=u_prev, q=q, checkpoints=cps, energy=energy)
+    return dict(u=u, u_prev=u_prev, q=q, checkpoints=cps, energy=energy, R_base=Rb, u_base=ub)
 
 
 def run_ensemble(tri: np.ndarray, khat: np.ndarray, area: np.ndarray, eh: np.ndarray, h: np.ndarray,

@@ -25,7 +25,7 @@ size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
 struct Layout {
   size_t xyz, tri, khat, area, lam, flags, adj_ptr, adj_el, adj_nb, adj_loc, k64, k32, fixed,
-      radial, perm, F, eh64, eh32, h, minv64, minv32, u[2], uh[2], uc, v, usnap, q, qmask, bsr_ptr, bsr_col,
+      radial, perm, F, eh64, eh32, h, minv64, minv32, u[2], uh[2], uc, v, usnap, rbase, q, qmask, bsr_ptr, bsr_col,
       adj_slot, bsr64, bsr32, epart, erec, gtab, base, frame, stress,
       mean, var, aux, total;
 };
@@ -187,8 +187,11 @@ Layout plan(const ens_ctx* c) {
     if (c->state_prec == ENS_STATE_F32_KAHAN) L.uc = take(sizeof(float) * ndof * ld);
     L.v = take(sizeof(float) * ndof * ld);
   }
-  // displacement of the last geometry refresh
-  if (c->geom_every > 0) L.usnap = take(sizeof(double) * ndof * ld);
+  // displacement and internal force at the last geometry refresh
+  if (c->geom_every > 0) {
+    L.usnap = take(sizeof(double) * ndof * ld);
+    L.rbase = take(sizeof(double) * ndof * ld);
+  }
   if (use_shared(c)) {
     const int64_t nb = (int64_t)c->bsr_col.size();
     L.bsr_ptr = take(sizeof(int32_t) * (nn + 1));
@@ -795,8 +798,11 @@ int32_t ens_init_state(ens_ctx* ctx, const double* u0, const double* v0) {
     }
     HIPC(launch_qoi_init((int32_t)ctx->n_nodes, (int32_t)ld, ctx->p<double>(L.radial),
                          ctx->p<double>(L.u[0]), nullptr, nullptr, ctx->p<double>(L.q), st));
-    // the first refresh interval runs on the reference geometry
-    if (ctx->geom_every > 0) HIPC(hipMemset(ctx->p<void>(L.usnap), 0, sizeof(double) * n));
+    // the first refresh interval is the linear model (u_m = 0, R_m = 0)
+    if (ctx->geom_every > 0) {
+      HIPC(hipMemset(ctx->p<void>(L.usnap), 0, sizeof(double) * n));
+      HIPC(hipMemset(ctx->p<void>(L.rbase), 0, sizeof(double) * n));
+    }
   } else {
     float* uc = ctx->state_prec == ENS_STATE_F32_KAHAN ? ctx->p<float>(L.uc) : nullptr;
     if (u0) {
@@ -910,6 +916,7 @@ int32_t ens_step(ens_ctx* ctx, int64_t n_steps, double dt, int32_t force, void* 
   a.a = 0.5 * ctx->alpha * dt;
   if (geom) {
     a.usnap = gptr(ctx->p<double>(L.usnap));
+    a.rbase = gptr(ctx->p<double>(L.rbase));
     a.xyz = gptr(ctx->p<double>(L.xyz));
     a.nu = ctx->nu;
     a.shear_k = ctx->shear_k;
@@ -930,8 +937,15 @@ int32_t ens_step(ens_ctx* ctx, int64_t n_steps, double dt, int32_t force, void* 
       const int64_t n = ctx->steps + j;
       const bool energy = ctx->energy_every > 0 && (n % ctx->energy_every) == 0;
       a.j = j;
+      // geometry refresh at step n: the kernel moves the force base to the
+      // force at u_n, then u_n becomes the snapshot for steps n .. n+every-1
+      const bool refresh = geom && n > 0 && n % ctx->geom_every == 0;
+      a.refresh = refresh ? 1 : 0;
       set_state_ptrs(ctx, a, 0);
       HIPC(launch_step(a, f32, ctx->state_prec, ctx->SB, qoi, energy, use_shared(ctx) && !geom, st));
+      if (refresh)
+        HIPC(launch_copy_f64(3 * ctx->n_nodes * (int64_t)ctx->ld, ctx->p<double>(L.u[ctx->cur]),
+                             ctx->p<double>(L.usnap), st));
       if (energy) {
         const int64_t rec = ctx->energy_records % kEnergyCap;
         HIPC(launch_energy_reduce(ctx->p<double>(L.epart), a.n_nb, ctx->ld, ctx->ld,
@@ -940,10 +954,6 @@ int32_t ens_step(ens_ctx* ctx, int64_t n_steps, double dt, int32_t force, void* 
         ctx->energy_records++;
       }
       ctx->cur = 1 - ctx->cur;
-      // geometry refresh: u_{n+1} becomes the snapshot for steps n+1 .. n+every
-      if (geom && (n + 1) % ctx->geom_every == 0)
-        HIPC(launch_copy_f64(3 * ctx->n_nodes * (int64_t)ctx->ld, ctx->p<double>(L.u[ctx->cur]),
-                             ctx->p<double>(L.usnap), st));
     }
     HIPC(launch_advance(ctx->p<int64_t>(L.base), k, st));
     ctx->steps += k;

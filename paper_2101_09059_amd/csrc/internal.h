@@ -88,10 +88,14 @@ struct StepArgs {
   double dt, a;        // step, alpha dt / 2
   double cd;           // explicit viscous force coefficient (0: none)
   ENS_GLOBAL double* energy_part; // [n_nb][ld] per node-block energy partial sums
-  // Geometry form (usnap non-null): element matrices from x + u_snap.
-  ENS_GLOBAL const double* usnap; // displacement of the last geometry refresh [n_nodes*3][ld]
+  // Geometry form (usnap non-null): force R_m + K(x + u_m) (u_n - u_m)
+  // with u_m the displacement of the last refresh.
+  ENS_GLOBAL const double* usnap; // u_m [n_nodes*3][ld]
+  ENS_GLOBAL double* rbase;       // R_m [n_nodes*3][ld]
   ENS_GLOBAL const double* xyz;   // reference coordinates [n_nodes][3]
   double nu, shear_k;
+  int32_t refresh;                // 1: this step moves the base (R_m <- the force at u_n)
+  int32_t pad_;
 };
 
 // One work item of the batched step: `count` nodes from `node0` of mesh

@@ -260,12 +260,14 @@ __device__ __forceinline__ void gather_blocks(const StepArgs& p, int node, int64
   }
 }
 
-// Geometry form: R for one node from element matrices evaluated on the
-// refreshed geometry x + u_snap of each sample (matrix-free, no stored
-// K^e).  For the element (i, b, c) of the walk, with a = P_b - P_i and
-// w = P_c - P_i: e_x = a/|a|, e_z = a x w/|a x w|, e_y = e_z x e_x; node i
-// sits at the local origin, b at (x2, 0), c at (x3, y3).  The local
-// differences d_b = R (u_b - u_i), d_c = R (u_c - u_i) give the strains
+// Geometry form: K(x + u_m) (u_n - u_m) for one node, with element matrices
+// evaluated on each sample's geometry of the last refresh x + u_m (matrix-
+// free, no stored K^e); the caller adds the force base R_m.  For the
+// element (i, b, c) of the walk, with a = P_b - P_i and w = P_c - P_i:
+// e_x = a/|a|, e_z = a x w/|a x w|, e_y = e_z x e_x; node i sits at the
+// local origin, b at (x2, 0), c at (x3, y3).  With the increments
+// du = u_n - u_m, the local differences d_b = R (du_b - du_i),
+// d_c = R (du_c - du_i) give the strains
 // (the rows of the strain-displacement matrix: du_x/dx, du_y/dy, gamma_xy,
 // du_z/dx, du_z/dy, Sec. 2.2.1), the constitutive matrix per unit (E h)
 // the stresses, and node i's force A B_i^T sigma is rotated back to global
@@ -343,8 +345,9 @@ __device__ __forceinline__ void gather_geom(const StepArgs& p, int node, int64_t
       for (int c = 0; c < 3; ++c) {
         a[c] = (AT)((xb[c] - xi[c]) + (sb[c][i] - si[c][i]));
         w[c] = (AT)((xc[c] - xi[c]) + (sc[c][i] - si[c][i]));
-        db[c] = (AT)(ub[c][i] - ua[c][i]);
-        dc[c] = (AT)(uc[c][i] - ua[c][i]);
+        const double dui = ua[c][i] - si[c][i];
+        db[c] = (AT)((ub[c][i] - sb[c][i]) - dui);
+        dc[c] = (AT)((uc[c][i] - sc[c][i]) - dui);
       }
       // frame
       const AT aa = fma(a[2], a[2], fma(a[1], a[1], a[0] * a[0]));
@@ -455,9 +458,27 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int j, int node, in
   }
   AT r[3][SPL];
   constexpr bool UNI = LPN == 64;
-  if constexpr (GEOM) gather_geom<AT, SPL, UNI>(p, node, ld, s0, U, ua, r);
-  else if constexpr (SHARED) gather_blocks<AT, ST, SPL, UNI>(p, node, ld, s0, U, ua, r);
-  else gather_apply<AT, ST, SPL, UNI>(p, node, ld, s0, U, ua, r);
+  // geometry form: force R_m + K_m (u_n - u_m); a refresh step moves the
+  // base to the force at u_n (own rows only: no other wave reads them)
+  double rf[3][SPL];
+  if constexpr (GEOM) {
+    gather_geom<AT, SPL, UNI>(p, node, ld, s0, U, ua, r);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double rb[SPL];
+      vload<SPL, true>(gen(p.rbase) + (row + c) * ld + s0, rb);
+#pragma unroll
+      for (int i = 0; i < SPL; ++i) rf[c][i] = rb[i] + (double)r[c][i];
+      if (p.refresh) vstore<SPL, true>(gen(p.rbase) + (row + c) * ld + s0, rf[c]);
+    }
+  } else {
+    if constexpr (SHARED) gather_blocks<AT, ST, SPL, UNI>(p, node, ld, s0, U, ua, r);
+    else gather_apply<AT, ST, SPL, UNI>(p, node, ld, s0, U, ua, r);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int i = 0; i < SPL; ++i) rf[c][i] = (double)r[c][i];
+  }
 
   const double g = maybe_uni<UNI>(cst(p.gtab)[j]);
   const unsigned fx = maybe_uni<UNI>((unsigned)cst(p.fixed)[node]);
@@ -496,7 +517,7 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int j, int node, in
       const double fc = g * maybe_uni<UNI>(cst(p.F)[row + c]);
 #pragma unroll
       for (int i = 0; i < SPL; ++i) {
-        double acc = (dt2 * minv[i]) * (fc - (double)r[c][i]);
+        double acc = (dt2 * minv[i]) * (fc - rf[c][i]);
         // explicit viscous force -c_d (u_n - u_{n-1}) / dt
         if (p.cd != 0.0) acc = fma(-(p.dt * minv[i] * p.cd), ua[c][i] - up[i], acc);
         double v = fma(-oma, up[i], fma(2.0, ua[c][i], acc)) * inv1pa;

@@ -62,24 +62,32 @@ def test_patch_test_on_stretched_plate(lam):
     assert abs(0.5 * u @ (K @ u) - expect) <= 1e-12 * expect
 
 
-def test_refresh_schedule_equals_chained_plain_runs():
+def _setup(load):
     cs = small_case(12, 6, 1, seed=5)
     m = cs.mesh
-    F = 40.0 * cs.F.reshape(-1)            # a load large enough to move the geometry
+    F = load * cs.F.reshape(-1)
     fx = m.fixed.reshape(-1).astype(bool)
     mass = assembly.lumped_mass(m.tri, cs.area, cs.h[:, 0], 1.0, m.n_nodes)
     K0 = assembly.assemble_stiffness(m.tri, cs.khat, cs.eh[:, 0], m.n_nodes)
     g = lambda t: stepper.load_factor("sine", t, T_ramp=20 * cs.dt)
     K_at = lambda u: geometry.deformed_stiffness(m.xyz, m.tri, u, cs.eh[:, 0], NU, KS)
+    return cs, F, fx, mass, K0, g, K_at
+
+
+def test_refresh_schedule_equals_chained_plain_runs():
+    cs, F, fx, mass, K0, g, K_at = _setup(0.3)
     every, seg = 5, 4
     ref = stepper.run_sample(K0, mass, F, fx, cs.dt, every * seg, 50.0, g, K_at=K_at, every=every)
-    # chained: `every` plain steps, rebuild, `every` plain steps, ...
+    # chained: `every` plain steps with the force R_b + K (u - u_b), then
+    # R_b += K (u - u_b), u_b = u, K = K(x + u), and again
     K, u, up = K0, None, None
+    Rb, ub = np.zeros(F.size), np.zeros(F.size)
     for k in range(seg):
         t0 = k * every * cs.dt
         r = stepper.run_sample(K, mass, F, fx, cs.dt, every, 50.0, lambda t, t0=t0: g(t + t0),
-                               u0=u, u_prev=up)
+                               u0=u, u_prev=up, R_base=Rb, u_base=ub)
         u, up = r["u"], r["u_prev"]
+        Rb, ub = Rb + K @ (u - ub), u.copy()
         K = K_at(u)
     assert np.max(np.abs(ref["u"] - u)) <= 1e-14 * np.max(np.abs(u))
     plain = stepper.run_sample(K0, mass, F, fx, cs.dt, every * seg, 50.0, g)
@@ -87,3 +95,16 @@ def test_refresh_schedule_equals_chained_plain_runs():
     assert np.linalg.norm(ref["u"] - plain["u"]) > 1e-6 * np.linalg.norm(plain["u"])
     never = stepper.run_sample(K0, mass, F, fx, cs.dt, every * seg, 50.0, g, K_at=K_at, every=10 * every * seg)
     assert np.array_equal(never["u"], plain["u"])
+
+
+def test_vanishing_load_gives_the_linear_run():
+    """The refresh changes the force by O(|u| / element size): scaling the
+    load down by 1e4 brings the refreshed run to the linear one."""
+    diffs = []
+    for load in (1.0, 1e-4):
+        cs, F, fx, mass, K0, g, K_at = _setup(load)
+        ref = stepper.run_sample(K0, mass, F, fx, cs.dt, 200, 50.0, g, K_at=K_at, every=3)
+        plain = stepper.run_sample(K0, mass, F, fx, cs.dt, 200, 50.0, g)
+        diffs.append(np.linalg.norm(ref["u"] - plain["u"]) / np.linalg.norm(plain["u"]))
+    assert diffs[0] > 1e-3
+    assert diffs[1] < 1e-3 * diffs[0]
