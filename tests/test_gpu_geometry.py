@@ -24,23 +24,25 @@ def _oracle(cs, F, n, every, cols):
     return r["u"], r["q"]
 
 
-# (20 x 10, S = 6): 8 lanes per node; (16 x 8, S = 70): a wave per node with
-# a ragged padded tail, three sample columns checked
-@pytest.mark.parametrize("nt,nz,S,cols", [(20, 10, 6, None), (16, 8, 70, [0, 33, 69])])
+# S = 6: 8 lanes per node; S = 70: a wave per node with one sample per lane
+# (block 64) and two (the default block 128), ragged padded tail; S = 256
+# with block 256: four samples per lane; a few sample columns checked
+@pytest.mark.parametrize("nt,nz,S,cols,sb", [(20, 10, 6, None, 0), (16, 8, 70, [0, 33, 69], 64),
+                                             (16, 8, 70, [0, 33, 69], 0), (16, 8, 256, [7, 200], 256)])
 @pytest.mark.parametrize("every", [1, 7])
-def test_geometry_refresh_matches_oracle(nt, nz, S, cols, every):
+def test_geometry_refresh_matches_oracle(nt, nz, S, cols, sb, every):
     cs = small_case(nt, nz, S, seed=21)
     F = LOADF * cs.F
     n = 120 if every == 1 else 300
     ref_u, ref_q = _oracle(cs, F, n, every, cols)
     plain_u, _ = _oracle(cs, F, n, 0, cols)
     moved = rel_l2(plain_u, ref_u)
-    say(f"case: geometry refresh every {every}, {nt}x{nz} S={S}: refresh changes u by {moved:.2e}")
+    say(f"case: geometry refresh every {every}, {nt}x{nz} S={S} block {sb}: refresh changes u by {moved:.2e}")
     assert moved > 1e-3   # the refresh matters at this load
     sel = slice(None) if cols is None else cols
     for mode, tol, kw in [("f64", 1e-10, {}), ("f32 apply", 1e-5, dict(apply_prec=ensfem.F32))]:
         ens = ensfem.setup_case(cs.mesh, cs.eh, cs.h, F, alpha=50.0, kind=ensfem.LOAD_RAMP_SINE,
-                                t_ramp=20 * cs.dt, geom_every=every, **kw)
+                                t_ramp=20 * cs.dt, geom_every=every, sample_block=sb, **kw)
         ens.init_state()
         ens.step(n, cs.dt)
         ens.sync()
