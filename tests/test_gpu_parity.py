@@ -537,3 +537,48 @@ def test_precision_ladder_on_a_fine_mesh():
     assert err["f64"] <= 1e-7
     assert err["kahan"] <= 1e-5 and err["f32"] <= 1e-5
     assert err["kahan"] <= 1.01 * err["f32"]
+
+
+def test_degenerate_sizes():
+    """One free triangle with one sample (a rigid drift under the load plus
+    its membrane modes), zero steps leaving the state alone, and a single
+    sample on a cylinder: FP64 against the oracle."""
+    from oracle import assembly, element
+    xyz = np.array([[0.0, 0.0, 0.0], [1.0, 0.1, 0.0], [0.2, 0.9, 0.1]])
+    tri = np.array([[0, 1, 2]], dtype=np.int32)
+    nrm = np.cross(xyz[1] - xyz[0], xyz[2] - xyz[0])
+    nrm /= np.linalg.norm(nrm)
+    m = inputs.Mesh(xyz=xyz, tri=tri, fixed=np.zeros((3, 3), dtype=np.uint8), radial=np.tile(nrm, (3, 1)),
+                    axial=np.zeros(3), length=1.0, n_theta=3, n_z=1, name="one_triangle")
+    kh, A, _ = element.reference_stiffness(xyz, tri, 0.49, 5.0 / 6.0)
+    eh, h = np.array([[7e5]]), np.array([[0.1]])
+    F = np.array([[1.0, 0.0, 2.0], [0.0, -1.0, 0.5], [0.3, 0.2, -1.0]]) * 1e3
+    dt = cfl.stable_dt(kh, A, eh, h, 1.0, 0.5)
+    say("case: one free triangle, S=1")
+    ens = ensfem.setup_case(m, eh, h, F, alpha=10.0)
+    ens.init_state()
+    u0 = ens.read_state()
+    ens.step(0, dt)
+    assert np.array_equal(ens.read_state(), u0)
+    ens.step(300, dt)
+    u = ens.read_state()
+    q = ens.read_qoi()
+    ens.close()
+    K = assembly.assemble_stiffness(tri, kh, eh[:, 0], 3)
+    mass = assembly.lumped_mass(tri, A, h[:, 0], 1.0, 3)
+    r = stepper.run_sample(K, mass, F.reshape(-1), np.zeros(9, bool), dt, 300, 10.0, lambda t: 1.0,
+                           radial=m.radial)
+    assert rel_l2(u[:, 0], r["u"]) <= 1e-10
+    assert rel_l2(q[:, 0], r["q"]) <= 1e-10
+    # one sample on a cylinder (padded to a block of 8)
+    cs = small_case(18, 9, 1, seed=31)
+    say("case: cylinder 18x9, S=1")
+    ens = ensfem.setup_case(cs.mesh, cs.eh, cs.h, cs.F, alpha=50.0, kind=ensfem.LOAD_RAMP_SINE, t_ramp=5e-3)
+    ens.init_state()
+    ens.step(500, cs.dt)
+    u = ens.read_state()
+    ens.close()
+    g = lambda t: stepper.load_factor("sine", t, 5e-3)
+    ref = stepper.run_ensemble(cs.mesh.tri, cs.khat, cs.area, cs.eh, cs.h, 1.0, cs.F, cs.mesh.fixed,
+                               cs.mesh.radial, cs.dt, 500, 50.0, g)["u"]
+    assert rel_l2(u, ref) <= 1e-10
