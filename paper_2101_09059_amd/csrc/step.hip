@@ -302,7 +302,14 @@ __device__ __forceinline__ void gather_geom(const StepArgs& p, int node, int64_t
   for (int c = 0; c < 3; ++c)
 #pragma unroll
     for (int i = 0; i < SPL; ++i) r[c][i] = AT(0);
-  double ub[3][SPL], uc[3][SPL], sb[3][SPL], sc[3][SPL], xb[3], xc[3];
+  double dui[3][SPL];  // u_n - u_m at node i
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < SPL; ++i) dui[c][i] = ua[c][i] - si[c][i];
+  // edge vector and increment difference to the element's second neighbour,
+  // in the apply precision; a reused first neighbour takes them over
+  AT wc[3][SPL], dcc[3][SPL];
 #pragma unroll 2
   for (int k = kb; k < ke; ++k) {
     const int64_t e = maybe_uni<UNI>(cst(p.adj.el)[k]);
@@ -311,43 +318,53 @@ __device__ __forceinline__ void gather_geom(const StepArgs& p, int node, int64_t
     const int cx = maybe_uni<UNI>(nb[2 * k + 1]);
     AT eh[SPL];
     vload<SPL, false>(EH + e * ld + s0, eh);
+    AT ab[3][SPL], dbb[3][SPL];
     // bx < 0: this element's first neighbour is the previous one's second
     if (bx >= 0) {
       const int64_t rb = (int64_t)bx * 3;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        xb[c] = maybe_uni<UNI>(X[rb + c]);
-        vload<SPL, false>(U + (rb + c) * ld + s0, ub[c]);
-        vload<SPL, false>(US + (rb + c) * ld + s0, sb[c]);
+        const double xb = maybe_uni<UNI>(X[rb + c]);
+        double ub[SPL], sb[SPL];
+        vload<SPL, false>(U + (rb + c) * ld + s0, ub);
+        vload<SPL, false>(US + (rb + c) * ld + s0, sb);
+#pragma unroll
+        for (int i = 0; i < SPL; ++i) {
+          ab[c][i] = (AT)((xb - xi[c]) + (sb[i] - si[c][i]));
+          dbb[c][i] = (AT)((ub[i] - sb[i]) - dui[c][i]);
+        }
       }
     } else {
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        xb[c] = xc[c];
+      for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int i = 0; i < SPL; ++i) {
-          ub[c][i] = uc[c][i];
-          sb[c][i] = sc[c][i];
+          ab[c][i] = wc[c][i];
+          dbb[c][i] = dcc[c][i];
         }
-      }
     }
     const int64_t rc = (int64_t)cx * 3;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      xc[c] = maybe_uni<UNI>(X[rc + c]);
-      vload<SPL, false>(U + (rc + c) * ld + s0, uc[c]);
-      vload<SPL, false>(US + (rc + c) * ld + s0, sc[c]);
+      const double xc = maybe_uni<UNI>(X[rc + c]);
+      double uc[SPL], sc[SPL];
+      vload<SPL, false>(U + (rc + c) * ld + s0, uc);
+      vload<SPL, false>(US + (rc + c) * ld + s0, sc);
+#pragma unroll
+      for (int i = 0; i < SPL; ++i) {
+        wc[c][i] = (AT)((xc - xi[c]) + (sc[i] - si[c][i]));
+        dcc[c][i] = (AT)((uc[i] - sc[i]) - dui[c][i]);
+      }
     }
 #pragma unroll
     for (int i = 0; i < SPL; ++i) {
       AT a[3], w[3], db[3], dc[3];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        a[c] = (AT)((xb[c] - xi[c]) + (sb[c][i] - si[c][i]));
-        w[c] = (AT)((xc[c] - xi[c]) + (sc[c][i] - si[c][i]));
-        const double dui = ua[c][i] - si[c][i];
-        db[c] = (AT)((ub[c][i] - sb[c][i]) - dui);
-        dc[c] = (AT)((uc[c][i] - sc[c][i]) - dui);
+        a[c] = ab[c][i];
+        w[c] = wc[c][i];
+        db[c] = dbb[c][i];
+        dc[c] = dcc[c][i];
       }
       // frame
       const AT aa = fma(a[2], a[2], fma(a[1], a[1], a[0] * a[0]));
