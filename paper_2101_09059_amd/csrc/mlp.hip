@@ -7,8 +7,9 @@
 // moments FP32; activations BF16 between layers, pre-activations FP32.
 //
 // GEMM: C[M x N] = sum_k A(m, k) B(k, n), 128 x 128 block tile, 32-deep
-// K steps staged through LDS (both operands stored K-contiguous there),
-// 4 waves of 64 x 64, each a 4 x 4 grid of 16x16x32 BF16 MFMAs.  The
+// K steps staged through two LDS buffers (both operands stored K-contiguous
+// there; the next step's tiles are fetched while the current one is
+// multiplied), 4 waves of 64 x 64, each a 4 x 4 grid of 16x16x32 BF16 MFMAs.  The
 // operands may be K-contiguous or M/N-contiguous in global memory.
 // Epilogues: bias + GELU (forward hidden), bias (forward output), FP32
 // store with split-K partials (backward data / gradient check), per-column
@@ -68,55 +69,67 @@ __device__ __forceinline__ float gelu_grad_f(float x) {
   return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * expf(-0.5f * x * x) * 0.39894228040143268f;
 }
 
-// Stage a BM x BK (or BN x BK) tile of an operand into LDS [row][k].
+// A BM x BK (or BN x BK) tile of an operand, global -> registers (two
+// 8-element chunks per thread) and registers -> LDS [row][k].
 // KC: the operand is contiguous along k in global memory.
 template <bool KC>
-__device__ __forceinline__ void stage_tile(__bf16 (*S)[LDS_STRIDE], const __bf16* __restrict__ P,
-                                           int64_t s_row, int64_t s_k, int row0, int k0, int rows,
-                                           int kend, bool vec_ok) {
+__device__ __forceinline__ void load_tile(bf16x8 (&v)[2], const __bf16* __restrict__ P, int64_t s_row,
+                                          int64_t s_k, int row0, int k0, int rows, int kend, bool vec_ok) {
   const int t = threadIdx.x;
-  if constexpr (KC) {
-    // 128 rows x 4 chunks of 8 k
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
-      const int c = t + 256 * it;
+  for (int it = 0; it < 2; ++it) {
+    const int c = t + 256 * it;
+    if constexpr (KC) {
+      // 128 rows x 4 chunks of 8 k
       const int r = c >> 2, kc = (c & 3) * 8;
       const int gr = row0 + r, gk = k0 + kc;
-      bf16x8 v;
       if (gr < rows && gk + 8 <= kend && vec_ok) {
-        v = *reinterpret_cast<const bf16x8*>(P + (int64_t)gr * s_row + gk);
+        v[it] = *reinterpret_cast<const bf16x8*>(P + (int64_t)gr * s_row + gk);
       } else {
 #pragma unroll
         for (int e = 0; e < 8; ++e)
-          v[e] = (gr < rows && gk + e < kend) ? P[(int64_t)gr * s_row + (int64_t)(gk + e) * s_k] : (__bf16)0.0f;
+          v[it][e] = (gr < rows && gk + e < kend) ? P[(int64_t)gr * s_row + (int64_t)(gk + e) * s_k] : (__bf16)0.0f;
       }
-      *reinterpret_cast<bf16x8*>(&S[r][kc]) = v;
-    }
-  } else {
-    // 32 k x 16 chunks of 8 rows, transposed into [row][k]
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-      const int c = t + 256 * it;
+    } else {
+      // 32 k x 16 chunks of 8 rows
       const int kk = c >> 4, rc = (c & 15) * 8;
       const int gk = k0 + kk, gr = row0 + rc;
-      bf16x8 v;
       if (gk < kend && gr + 8 <= rows && vec_ok) {
-        v = *reinterpret_cast<const bf16x8*>(P + (int64_t)gk * s_k + gr);
+        v[it] = *reinterpret_cast<const bf16x8*>(P + (int64_t)gk * s_k + gr);
       } else {
 #pragma unroll
         for (int e = 0; e < 8; ++e)
-          v[e] = (gk < kend && gr + e < rows) ? P[(int64_t)(gr + e) * s_row + (int64_t)gk * s_k] : (__bf16)0.0f;
+          v[it][e] = (gk < kend && gr + e < rows) ? P[(int64_t)(gr + e) * s_row + (int64_t)gk * s_k] : (__bf16)0.0f;
       }
-#pragma unroll
-      for (int e = 0; e < 8; ++e) S[rc + e][kk] = v[e];
     }
   }
 }
 
+template <bool KC>
+__device__ __forceinline__ void store_tile(__bf16 (*S)[LDS_STRIDE], const bf16x8 (&v)[2]) {
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const int c = t + 256 * it;
+    if constexpr (KC) {
+      const int r = c >> 2, kc = (c & 3) * 8;
+      *reinterpret_cast<bf16x8*>(&S[r][kc]) = v[it];
+    } else {
+      // transposed into [row][k]
+      const int kk = c >> 4, rc = (c & 15) * 8;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) S[rc + e][kk] = v[it][e];
+    }
+  }
+}
+
+// Two LDS buffers: the next K step's tiles are fetched from global memory
+// into registers while the MFMAs run on the current buffer, then written to
+// the other buffer; one barrier per K step.
 template <bool AK, bool BKC, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-  __shared__ __bf16 As[BM][LDS_STRIDE];
-  __shared__ __bf16 Bs[BN][LDS_STRIDE];
+  __shared__ __bf16 As[2][BM][LDS_STRIDE];
+  __shared__ __bf16 Bs[2][BN][LDS_STRIDE];
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
   const int kbeg = blockIdx.z * g.k_chunk;
   const int kend = min(g.K, kbeg + g.k_chunk);
@@ -127,20 +140,38 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  bf16x8 va[2], vb[2];
+  if (kbeg < kend) {
+    load_tile<AK>(va, g.A, g.a_sm, g.a_sk, m0, kbeg, g.M, kend, g.vec_ok);
+    load_tile<BKC>(vb, g.B, g.b_sn, g.b_sk, n0, kbeg, g.N, kend, g.vec_ok);
+    store_tile<AK>(As[0], va);
+    store_tile<BKC>(Bs[0], vb);
+  }
+  __syncthreads();
+  int buf = 0;
   for (int k0 = kbeg; k0 < kend; k0 += BK) {
-    stage_tile<AK>(As, g.A, g.a_sm, g.a_sk, m0, k0, g.M, kend, g.vec_ok);
-    stage_tile<BKC>(Bs, g.B, g.b_sn, g.b_sk, n0, k0, g.N, kend, g.vec_ok);
-    __syncthreads();
+    const bool more = k0 + BK < kend;
+    if (more) {
+      load_tile<AK>(va, g.A, g.a_sm, g.a_sk, m0, k0 + BK, g.M, kend, g.vec_ok);
+      load_tile<BKC>(vb, g.B, g.b_sn, g.b_sk, n0, k0 + BK, g.N, kend, g.vec_ok);
+    }
     bf16x8 a[4], b[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[wm * 64 + i * 16 + (l & 15)][8 * (l >> 4)]);
+    for (int i = 0; i < 4; ++i)
+      a[i] = *reinterpret_cast<const bf16x8*>(&As[buf][wm * 64 + i * 16 + (l & 15)][8 * (l >> 4)]);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bs[wn * 64 + j * 16 + (l & 15)][8 * (l >> 4)]);
+    for (int j = 0; j < 4; ++j)
+      b[j] = *reinterpret_cast<const bf16x8*>(&Bs[buf][wn * 64 + j * 16 + (l & 15)][8 * (l >> 4)]);
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    if (more) {
+      store_tile<AK>(As[buf ^ 1], va);
+      store_tile<BKC>(Bs[buf ^ 1], vb);
+    }
     __syncthreads();
+    buf ^= 1;
   }
   // lane l of a 16x16 output tile holds rows 4*(l/16) + r, column l % 16
   if constexpr (EPI == EPI_MOMENTS) {
@@ -248,13 +279,13 @@ __global__ void k_gelu_bwd(int64_t n, const float* __restrict__ dH, const float*
 __global__ void k_mse(int64_t n, float scale, const float* __restrict__ Y, const float* __restrict__ T,
                       __bf16* __restrict__ dY16, float* __restrict__ dY32, double* __restrict__ part) {
   __shared__ double red[256];
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double e2 = 0.0;
-  if (t < n) {
+  // grid-stride: one partial per workgroup, at most kLossParts of them
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < n; t += (int64_t)gridDim.x * 256) {
     const float d = Y[t] - T[t];
     dY16[t] = (__bf16)(2.f * scale * d);
     if (dY32) dY32[t] = 2.f * scale * d;
-    e2 = (double)d * (double)d;
+    e2 += (double)d * (double)d;
   }
   red[threadIdx.x] = e2;
   __syncthreads();
@@ -281,13 +312,20 @@ __global__ __launch_bounds__(256) void k_loss_final(int nparts, const double* __
   if (threadIdx.x == 0) *loss = (float)(red[0] * scale);
 }
 
-// column sums of a [rows][cols] FP32 matrix, one thread per column
-__global__ void k_colsum(int rows, int cols, const float* __restrict__ X, float* __restrict__ out) {
-  const int c = blockIdx.x * 256 + threadIdx.x;
-  if (c >= cols) return;
+// column sums of a [rows][cols] FP32 matrix: a workgroup takes 64 columns,
+// its 4 waves sum every 4th row (in order), the 4 sums are added in wave
+// order
+__global__ __launch_bounds__(256) void k_colsum(int rows, int cols, const float* __restrict__ X,
+                                                float* __restrict__ out) {
+  __shared__ float red[256];
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + lane;
   float s = 0.f;
-  for (int r = 0; r < rows; ++r) s += X[(int64_t)r * cols + c];
-  out[c] = s;
+  if (c < cols)
+    for (int r = g; r < rows; r += 4) s += X[(int64_t)r * cols + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  if (g == 0 && c < cols) out[c] = ((red[lane] + red[64 + lane]) + red[128 + lane]) + red[192 + lane];
 }
 
 __global__ void k_adam_vec(int n, const float* __restrict__ g, float* __restrict__ w, float* __restrict__ m1,
@@ -358,6 +396,7 @@ __global__ void k_cv(int64_t n, int N, const double* __restrict__ qH, const doub
 }
 
 inline unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
+constexpr unsigned kLossParts = 2048;  // workgroups (and partial sums) of the loss
 
 }  // namespace
 
@@ -432,7 +471,7 @@ void plan(sur_net* s) {
   s->o_p2 = take(4 * rb * s->n_out);
   s->o_s1 = take(8 * (size_t)s->n_out);
   s->o_s2 = take(8 * (size_t)s->n_out);
-  s->o_lpart = take(8 * (size_t)blocks((int64_t)B * s->n_out));
+  s->o_lpart = take(8 * (size_t)kLossParts);
   s->o_loss = take(4);
   s->total = off;
 }
@@ -565,7 +604,7 @@ int32_t backward(sur_net* s, const float* T, int batch, float* grad, float* loss
                  hipStream_t st) {
   const int L = s->n_hidden;
   const int64_t ny = (int64_t)batch * s->n_out;
-  const unsigned nb = blocks(ny);
+  const unsigned nb = std::min(blocks(ny), kLossParts);
   float* dY32 = s->p<float>(s->o_dz32);  // FP32 dY reuses the dZ32 buffer (sized for n_out)
   SHIPC((k_mse<<<nb, 256, 0, st>>>(ny, 1.0f / (float)ny, s->p<float>(s->o_y), T, s->p<__bf16>(s->o_dy16), dY32,
                                    s->p<double>(s->o_lpart)),
@@ -582,7 +621,7 @@ int32_t backward(sur_net* s, const float* T, int batch, float* grad, float* loss
     const int in = s->fan_in[l], out = s->fan_out[l];
     // bias gradient
     float* db = grad ? grad + s->b_off[l] : s->p<float>(s->o_db);
-    SHIPC((k_colsum<<<blocks(out), 256, 0, st>>>(batch, out, dZf, db), hipGetLastError()));
+    SHIPC((k_colsum<<<(unsigned)((out + 63) / 64), 256, 0, st>>>(batch, out, dZf, db), hipGetLastError()));
     if (!grad) {
       float* m1 = s->p<float>(s->o_m1) + s->b_off[l];
       float* m2 = s->p<float>(s->o_m2) + s->b_off[l];
