@@ -232,6 +232,61 @@ def run_batch_config(args, torch):
     print(json.dumps(out), flush=True)
 
 
+def run_surrogate_kernels(args, torch):
+    """The learned form's kernels at full size on random data: the network
+    128 -> 3 x 1024 GELU -> 200,000 (BF16 MFMA, FP32 accumulate), one Adam
+    training step on a batch of 256, a forward pass of 256 rows, and the
+    per-output sums over 65,536 rows."""
+    from paper_2101_09059_amd import ensfem
+    sizes = [128, 1024, 1024, 1024, 200000]
+    net = ensfem.Surrogate(128, 1024, 3, 200000, 256)
+    rng = np.random.default_rng(9)
+    net.set_params((0.02 * rng.standard_normal(net.n_params)).astype(np.float32))
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(9)
+    X = torch.randn(256, 128, device="cuda", generator=gen)
+    T = torch.randn(256, 200000, device="cuda", generator=gen)
+    Y = torch.empty(256, 200000, device="cuda")
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, n):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(n):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    n = max(1, min(args.steps, 50))
+    ms_train = timed(lambda: net.train_step(X, T, 1e-5), n)
+    ms_fwd = timed(lambda: net.forward(X, out=Y), n)
+    Xl = torch.randn(65536, 128, device="cuda", generator=gen)
+    net.moments(Xl)
+    t0 = time.perf_counter()
+    net.moments(Xl)
+    s_mom = time.perf_counter() - t0
+    flops_fwd = 2.0 * 256 * sum(a * b for a, b in zip(sizes[:-1], sizes[1:]))
+    # at 256 rows the pass is bound by HBM: BF16 weights read once, FP32
+    # biases, the input and the FP32 output (171 flop/B, below the BF16
+    # ridge of ~310 flop/B)
+    bytes_fwd = 2 * (net.n_params - sum(sizes[1:])) + 4 * sum(sizes[1:]) + 4 * 256 * (sizes[0] + sizes[-1])
+    achieved = bytes_fwd / (ms_fwd * 1e-3) / 1e9
+    out = {"metric": "surrogate kernels: Adam training step (batch 256)", "value": ms_train, "unit": "ms",
+           "n_gpus": 1, "steps": n, "higher_is_better": False, "data": "synthetic (random parameters and data)",
+           "dtype": "bf16 mfma / fp32 accumulate",
+           "config": {"workload": "MLP 128 -> 3 x 1024 GELU -> 200,000 (207,231,296 parameters)"},
+           "forward_ms_batch_256": ms_fwd, "moments_65536_rows_s": s_mom,
+           "forward_tflops": flops_fwd / (ms_fwd * 1e-3) / 1e12,
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "forward pass (k_gemm)",
+                        "algorithmic_bytes_per_pass": bytes_fwd}}
+    print(json.dumps(out), flush=True)
+
+
 def run_learned_config(args, torch):
     """Learned form at full size: 200k-node cylinder, 64 + 64 KL inputs,
     MLP 128 -> 3 x 1024 (GELU) -> 200,000, trained on 4,096 solver samples
@@ -429,11 +484,12 @@ def main():
                     help="skip the SPDE field-sampler timing")
     ap.add_argument("--sample-block", type=int, default=0, help="0 = library default")
     ap.add_argument("--sb-inner", action="store_true")
-    ap.add_argument("--config", choices=["c2_cylinder", "c3_curved", "c4_batch", "c5_learned"],
+    ap.add_argument("--config", choices=["c2_cylinder", "c3_curved", "c4_batch", "c5_learned", "c5_kernels"],
                     default="c2_cylinder",
                     help="c2_cylinder: the headline single-mesh workload; c3_curved: the precision form at "
                          "1M nodes x 1,024 samples (about 6 GPU-minutes); c4_batch: the batching form; "
-                         "c5_learned: the learned form (about 12 GPU-minutes)")
+                         "c5_learned: the learned form (about 12 GPU-minutes); c5_kernels: the learned form's "
+                         "kernels at full size on random data (training step, forward, moments)")
     ap.add_argument("--c3-error-steps", type=int, default=20000,
                     help="c3_curved: steps of the error run")
     ap.add_argument("--c3-error-samples", type=int, default=64,
@@ -471,6 +527,9 @@ def main():
         return
     if args.config == "c5_learned":
         run_learned_config(args, torch)
+        return
+    if args.config == "c5_kernels":
+        run_surrogate_kernels(args, torch)
         return
 
     from paper_2101_09059_amd import ensfem, inputs

@@ -45,6 +45,10 @@ int32_t sur_bind_workspace(sur_net* s, void* dptr, size_t bytes);
  * out.  ENS_EINVAL on a non-finite value. */
 int32_t sur_set_params(sur_net* s, const float* host);
 int32_t sur_get_params(sur_net* s, float* host);
+/* Copy of the FP32 parameters (layout above) into a caller-owned device
+ * buffer of n_params floats, enqueued on `stream` (a snapshot during
+ * training without a trip through host memory). */
+int32_t sur_get_params_device(sur_net* s, float* dptr, void* stream);
 /* Y [batch][n_out] = network(X [batch][n_in]), device FP32 buffers. */
 int32_t sur_forward(sur_net* s, const float* X, int32_t batch, float* Y, void* stream);
 /* Gradient of the mean squared error against targets T [batch][n_out]

@@ -755,6 +755,15 @@ int32_t sur_get_params(sur_net* s, float* host) {
   return ENS_OK;
 }
 
+int32_t sur_get_params_device(sur_net* s, float* dptr, void* stream) {
+  if (!s || !dptr) return ENS_EINVAL;
+  if (!s->have_params) return s->fail(ENS_ESTATE, "sur_get_params_device: no parameters");
+  SHIPC(hipSetDevice(s->device));
+  SHIPC(hipMemcpyAsync(dptr, s->p<float>(s->o_p32), 4 * s->n_params, hipMemcpyDeviceToDevice,
+                       static_cast<hipStream_t>(stream)));
+  return ENS_OK;
+}
+
 int32_t sur_forward(sur_net* s, const float* X, int32_t batch, float* Y, void* stream) {
   if (!s || !X || !Y) return ENS_EINVAL;
   if (!s->have_params) return s->fail(ENS_ESTATE, "sur_forward: set the parameters first");

@@ -108,6 +108,7 @@ _SIGS = {
     "sur_bind_workspace": (_I32, [_P, _P, _SZ]),
     "sur_set_params": (_I32, [_P, _P]),
     "sur_get_params": (_I32, [_P, _P]),
+    "sur_get_params_device": (_I32, [_P, _P, _P]),
     "sur_forward": (_I32, [_P, _P, _I32, _P, _P]),
     "sur_gradients": (_I32, [_P, _P, _P, _I32, _P, _P, _P]),
     "sur_set_weight_decay": (_I32, [_P, ctypes.c_float]),
@@ -494,6 +495,15 @@ class Surrogate:
     def get_params(self) -> np.ndarray:
         v = np.empty(self.n_params, np.float32)
         self._check(self._lib.sur_get_params(self._h, _ptr(v)))
+        return v
+
+    def get_params_device(self, out=None, stream=None):
+        """Parameters copied into a device FP32 tensor (no host round trip)."""
+        import torch
+        v = out if out is not None else torch.empty(self.n_params, dtype=torch.float32,
+                                                    device=f"cuda:{self.device}")
+        assert v.dtype == torch.float32 and v.numel() == self.n_params and v.is_contiguous()
+        self._check(self._lib.sur_get_params_device(self._h, v.data_ptr(), _stream_handle(stream)))
         return v
 
     def forward(self, X, out=None, stream=None):

@@ -114,7 +114,6 @@ class Network:
         n_val = int(round(val * N))
         hold, vset, train = perm[:n_hold], perm[n_hold:n_hold + n_val], perm[n_hold + n_val:]
         Qtr = Q[train]
-        Qv, Xv = Q[vset], X[vset]
         self.mu = Qtr.mean(axis=0)
         sd = Qtr.std(axis=0)
         # outputs that never vary (clamped nodes) are predicted by their mean
@@ -126,6 +125,15 @@ class Network:
         Tt = torch.as_tensor((Qtr - self.mu) / scale, dtype=torch.float32, device=dev)
         del Qtr
         n_tr = Xt.shape[0]
+        # validation set on the device: its error and the best parameters
+        # stay there between checks
+        if n_val:
+            Xv = torch.as_tensor(X[vset], dtype=torch.float32, device=dev)
+            Qv = torch.as_tensor(Q[vset], dtype=torch.float64, device=dev)
+            qv_norm = float(torch.linalg.vector_norm(Qv))
+            mu_t = torch.as_tensor(self.mu, dtype=torch.float64, device=dev)
+            sd_t = torch.as_tensor(self.sd, dtype=torch.float64, device=dev)
+            best_dev = torch.empty(self.net.n_params, dtype=torch.float32, device=dev)
         steps_per_epoch = int(math.ceil(n_tr / batch))
         total = epochs * steps_per_epoch
         hist = []
@@ -145,15 +153,20 @@ class Network:
                 step += 1
             hist.append(float(loss.item()))
             if n_val and ((ep + 1) % eval_every == 0 or ep + 1 == epochs):
-                pv = self.predict(Xv)
-                e = float(np.linalg.norm(pv - Qv) / np.linalg.norm(Qv))
+                sq = 0.0
+                for r0 in range(0, Xv.shape[0], self.max_batch):
+                    y = self.net.forward(Xv[r0:r0 + self.max_batch]).double()
+                    d = mu_t + sd_t * y - Qv[r0:r0 + self.max_batch]
+                    sq += float(torch.sum(d * d))
+                e = math.sqrt(sq) / qv_norm
                 self.val_history.append((ep + 1, e))
                 if e < best[0]:
-                    best = (e, self.net.get_params(), ep + 1)
+                    self.net.get_params_device(best_dev)
+                    best = (e, best_dev, ep + 1)
                 if progress:
                     progress(f"  epoch {ep + 1}/{epochs}: loss {hist[-1]:.3e}, validation rel RMSE {e:.4f}")
         if best[1] is not None:
-            self.net.set_params(best[1])
+            self.net.set_params(best[1].cpu().numpy())
         self.best_epoch = best[2] if best[1] is not None else epochs
         torch.cuda.synchronize()
         self.train_seconds += time.perf_counter() - t0
