@@ -42,10 +42,11 @@ def step_kernel_bytes(n_nodes: int, n_el: int, S: int, apply_f32: bool, state: s
     (3 x 8 B); FP32-Kahan reads and writes u, its compensation and the
     velocity (6 x 4 B); plain FP32 reads and writes u and the velocity
     (4 x 4 B).  Plus (E h) per element and sample and 1/m per node and
-    sample (4 B in the FP32 apply, 8 B in FP64), the at-max bit of the
+    sample (4 B in the FP32 apply, 8 B in FP64), the rising bit of the
     running peak read and written (1/8 B each per node and sample; the
-    stored peak itself is only touched where the radial displacement turns,
-    so it is not counted), and the per-mesh arrays read once per launch
+    stored peak itself is only touched at local maxima of the radial
+    displacement, so it is not counted), and the per-mesh arrays read once
+    per launch
     (adjacency and 3x6 stiffness blocks, load, radial directions, clamp
     bits)."""
     w = 4 if apply_f32 else 8

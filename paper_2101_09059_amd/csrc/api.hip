@@ -869,7 +869,7 @@ int32_t run_starter(ens_ctx* ctx, double dt, hipStream_t st) {
   return ENS_OK;
 }
 
-// Fold the at-max bits into q so q holds every sample's running peak.
+// Fold the open rises into q so q holds every sample's running peak.
 int32_t resolve_qoi(ens_ctx* ctx) {
   const Layout& L = ctx->L;
   if (ctx->state_prec == ENS_STATE_F64)

@@ -78,9 +78,10 @@ struct StepArgs {
   ENS_GLOBAL float* uc;           // Kahan compensation (in place)
   ENS_GLOBAL float* v;            // velocity v_{n-1/2} -> v_{n+1/2} (in place)
   ENS_GLOBAL double* q;           // running peak radial displacement [n_nodes][ld]
-  // At-max bits (wave-per-node kernels): bit set <=> the running peak equals
-  // the current radial displacement, which is then not stored in q.
-  // Per node ceil(ld/64) words; sample s in word s/64, bit s%64.
+  // Rising bits (wave-per-node kernels): bit set <=> the last step raised
+  // the sample's radial displacement; q holds the maximum of the initial
+  // value and every completed rise's top, an open rise is folded in at
+  // read-back.  Per node ceil(ld/64) words; sample s in word s/64, bit s%64.
   ENS_GLOBAL uint64_t* qmask;
   int32_t qwords;
   ENS_GLOBAL const double* gtab;  // load factors of the current chunk

@@ -414,7 +414,7 @@ __device__ __forceinline__ void gather_geom(const StepArgs& p, int node, int64_t
   }
 }
 
-// At-max bits use a sample-indexed layout, independent of the lane mapping:
+// Rising bits use a sample-indexed layout, independent of the lane mapping:
 // per node ld/64 words, sample s in word s/64, bit s%64.  With SPL samples
 // per lane, lane l holds samples SPL*l + i of its block: word
 // (SPL*l + i)/64, bit SPL*(l % (64/SPL)) + i.
@@ -606,9 +606,10 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int j, int node, in
     const double e1 = maybe_uni<UNI>(cst(p.radial)[row + 1]);
     const double e2 = maybe_uni<UNI>(cst(p.radial)[row + 2]);
     if constexpr (LPN == 64) {
-      // q is only touched where the radial displacement turns: a rise that
-      // continues from the running peak keeps the at-max bit, a fall from it
-      // writes the peak, a rise below it compares with the stored peak.
+      // q is only touched at local maxima: the bit records that the last
+      // step raised the radial displacement; when a rise ends, its top
+      // (the current value) is compared with q and kept if larger.  A rise
+      // still open is folded in at read-back.
       constexpr int LPW = 64 / SPL;  // lanes per mask word
       uint64_t* __restrict__ mw = gen(p.qmask) + (int64_t)node * p.qwords + base / 64;
       uint64_t words[SPL];
@@ -621,17 +622,13 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int j, int node, in
       uint64_t ballots[SPL];
 #pragma unroll
       for (int i = 0; i < SPL; ++i) {
-        const bool at = (mine >> (SPL * (lane % LPW) + i)) & 1ull;
+        const bool rose = (mine >> (SPL * (lane % LPW) + i)) & 1ull;
         const double rc = fma(e2, uo[2][i], fma(e1, uo[1][i], e0 * uo[0][i]));
         const double rn = fma(e2, un[2][i], fma(e1, un[1][i], e0 * un[0][i]));
-        bool nbit = false;
-        if (at) {
-          nbit = rn >= rc;
-          if (!nbit) __builtin_nontemporal_store(rc, gen(p.q) + ms + i);
-        } else if (rn > rc) {
-          nbit = rn > __builtin_nontemporal_load(gen(p.q) + ms + i);
-        }
-        ballots[i] = __ballot(nbit);
+        const bool rises = rn > rc;
+        if (rose && !rises && rc > __builtin_nontemporal_load(gen(p.q) + ms + i))
+          __builtin_nontemporal_store(rc, gen(p.q) + ms + i);
+        ballots[i] = __ballot(rises);
       }
 #pragma unroll
       for (int w = 0; w < SPL; ++w) {
@@ -876,8 +873,9 @@ __global__ __launch_bounds__(256) void k_qoi_init(int32_t n_nodes, int32_t ld,
   q[t] = acc;
 }
 
-// Fold the at-max bits into q: where a bit is set, store the current radial
-// displacement (same operation order as the step kernel).  Idempotent.
+// Fold the open rises into q: where a bit is set, q = max(q, the current
+// radial displacement) (same operation order as the step kernel).
+// Idempotent.
 __global__ __launch_bounds__(256) void k_qoi_resolve(int32_t n_nodes, int32_t ld,
                                                      const double* __restrict__ radial,
                                                      const double* __restrict__ u,
@@ -899,7 +897,8 @@ __global__ __launch_bounds__(256) void k_qoi_resolve(int32_t n_nodes, int32_t ld
     else x[c] = (double)uh[idx] - (uc ? (double)uc[idx] : 0.0);
   }
   const double* e = radial + node * 3;
-  q[t] = fma(e[2], x[2], fma(e[1], x[1], e[0] * x[0]));
+  const double r = fma(e[2], x[2], fma(e[1], x[1], e[0] * x[0]));
+  if (r > q[t]) q[t] = r;
 }
 
 __global__ __launch_bounds__(256) void k_combine_f32(int64_t n, const float* __restrict__ uh,
