@@ -217,12 +217,13 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       }
     }
   } else {
+    // j innermost: consecutive accesses cover 64 consecutive columns of a row
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+      for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
+        for (int j = 0; j < 4; ++j) {
           const int m = m0 + wm * 64 + i * 16 + 4 * (l >> 4) + r;
           const int n = n0 + wn * 64 + j * 16 + (l & 15);
           if (m >= g.M || n >= g.N) continue;
