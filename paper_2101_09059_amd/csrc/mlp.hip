@@ -130,7 +130,14 @@ template <bool AK, bool BKC, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   __shared__ __bf16 As[2][BM][LDS_STRIDE];
   __shared__ __bf16 Bs[2][BN][LDS_STRIDE];
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  // Tile order: workgroup L runs on XCD L mod 8; each XCD takes every 8th
+  // column tile and walks all row tiles of one column tile back to back, so
+  // the row tiles that share a B tile read it through one L2.
+  const int mt = (g.M + BM - 1) / BM;
+  const int xcd = (int)(blockIdx.x & 7), idx = (int)(blockIdx.x >> 3);
+  const int mtile = idx % mt, ntile = (idx / mt) * 8 + xcd;
+  const int m0 = mtile * BM, n0 = ntile * BN;
+  if (n0 >= g.N) return;  // column tiles padded to a multiple of 8 (whole workgroup)
   const int kbeg = blockIdx.z * g.k_chunk;
   const int kend = min(g.K, kbeg + g.k_chunk);
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -212,8 +219,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     if (threadIdx.x < BN) {
       const int n = n0 + threadIdx.x;
       if (n < g.N) {
-        g.P1[(int64_t)blockIdx.y * g.N + n] = red1[0][threadIdx.x] + red1[1][threadIdx.x];
-        g.P2[(int64_t)blockIdx.y * g.N + n] = red2[0][threadIdx.x] + red2[1][threadIdx.x];
+        g.P1[(int64_t)mtile * g.N + n] = red1[0][threadIdx.x] + red1[1][threadIdx.x];
+        g.P2[(int64_t)mtile * g.N + n] = red2[0][threadIdx.x] + red2[1][threadIdx.x];
       }
     }
   } else {
@@ -479,7 +486,8 @@ void plan(sur_net* s) {
 
 template <bool AK, bool BKC, int EPI>
 hipError_t gemm(GemmArgs g, int splits, hipStream_t st) {
-  dim3 grid((g.N + BN - 1) / BN, (g.M + BM - 1) / BM, splits);
+  const unsigned mt = (unsigned)((g.M + BM - 1) / BM), nt = (unsigned)((g.N + BN - 1) / BN);
+  dim3 grid(mt * ((nt + 7) / 8 * 8), 1, splits);
   k_gemm<AK, BKC, EPI><<<grid, 256, 0, st>>>(g);
   return hipGetLastError();
 }
