@@ -582,3 +582,29 @@ def test_degenerate_sizes():
     ref = stepper.run_ensemble(cs.mesh.tri, cs.khat, cs.area, cs.eh, cs.h, 1.0, cs.F, cs.mesh.fixed,
                                cs.mesh.radial, cs.dt, 500, 50.0, g)["u"]
     assert rel_l2(u, ref) <= 1e-10
+
+
+@pytest.mark.parametrize("sb", [64, 128, 256])
+def test_peak_tracking_through_many_turns(sb):
+    """Undamped oscillation from a sudden load: the radial displacement
+    turns many times and later tops stay below the first.  The peak is read
+    back mid-run (while rises are open) and at the end, against the oracle's
+    running maximum, at one, two and four samples per lane."""
+    S = 70 if sb == 64 else 200
+    cs = small_case(16, 8, S, seed=17)
+    say(f"case: peak tracking, 16x8 S={S} block {sb}")
+    ens = ensfem.setup_case(cs.mesh, cs.eh, cs.h, cs.F, alpha=0.0, sample_block=sb)
+    ens.init_state()
+    ens.step(337, cs.dt)
+    q_mid = ens.read_qoi()
+    ens.step(663, cs.dt)
+    q_end = ens.read_qoi()
+    ens.close()
+    g = lambda t: 1.0
+    cols = [0, S // 2, S - 1]
+    r_mid = stepper.run_ensemble(cs.mesh.tri, cs.khat, cs.area, cs.eh, cs.h, 1.0, cs.F, cs.mesh.fixed,
+                                 cs.mesh.radial, cs.dt, 337, 0.0, g, samples=cols)
+    r_end = stepper.run_ensemble(cs.mesh.tri, cs.khat, cs.area, cs.eh, cs.h, 1.0, cs.F, cs.mesh.fixed,
+                                 cs.mesh.radial, cs.dt, 1000, 0.0, g, samples=cols)
+    assert rel_l2(q_mid[:, cols], r_mid["q"]) <= 1e-10
+    assert rel_l2(q_end[:, cols], r_end["q"]) <= 1e-10
