@@ -151,8 +151,8 @@ int32_t ens_set_viscous(ens_ctx* ctx, double c_d);
  * otherwise, and ens_save / ens_load / ens_batch_create refuse such a
  * context.  0 (the default) turns it off.  Switching it on or off drops the
  * workspace binding (the snapshot u_m and the base R_m take 48 B per node
- * and padded sample); any change resets the state.  ENS_EINVAL for
- * every < 0. */
+ * and padded sample); any change resets the state (the same value again
+ * changes nothing).  ENS_EINVAL for every < 0. */
 int32_t ens_set_geometry_refresh(ens_ctx* ctx, int32_t every);
 
 /* Ensemble fields: eh[n_el*S] = (E h)_{e,s} (element-wise product of

@@ -625,6 +625,7 @@ int32_t ens_set_mass_scaling(ens_ctx* ctx, double dt_target) {
 int32_t ens_set_geometry_refresh(ens_ctx* ctx, int32_t every) {
   if (!ctx) return ENS_EINVAL;
   if (every < 0) return ctx->fail(ENS_EINVAL, "ens_set_geometry_refresh: need every >= 0");
+  if (every == ctx->geom_every) return ENS_OK;  // unchanged: the state stays
   ctx->gen++;
   if ((every > 0) != (ctx->geom_every > 0)) ctx->bound = false;  // the snapshot buffer comes or goes
   ctx->geom_every = every;
