@@ -25,15 +25,43 @@ Pins (tests/test_oracle_geometry.py): the matrix of a rigidly rotated
 geometry is the rotated matrix, a translated or uniformly scaled geometry
 gives the same matrix, the patch test holds on a stretched geometry (strain
 energy of a linear field = area x the constitutive form of its strains, on
-the stretched area), a run with refreshes equals plain runs of the stepper
-chained segment by segment with the force base and the matrix moved in
-between, and at a vanishing load the run tends to the linear one.
+the stretched area), a flat plate stretched uniformly in k refreshed
+increments carries on its edge the sum of the increments' homogeneous
+edge tractions, each on the plate as stretched before it (closed form,
+which the total-displacement form K_m u_n misses), a run with refreshes
+equals plain runs of the stepper chained segment by segment with the force
+base and the matrix moved in between, and at a vanishing load the run
+tends to the linear one.
 """
 from __future__ import annotations
 
 import numpy as np
 
 from . import assembly, element
+
+
+class IncrementalForce:
+    """Internal force carried across stiffness refreshes.
+
+    force(u) = R_m + K_m (u - u_m); refresh(u) first moves the base to the
+    force at u, R_m <- R_m + K_m (u - u_m), u_m <- u, and then rebuilds the
+    matrix on the moved geometry, K_m <- K_at(u).  Without a refresh it is
+    the linear force K u (R_m = 0, u_m = 0 by default)."""
+
+    def __init__(self, K, K_at=None, R_base=None, u_base=None):
+        n = K.shape[0]
+        self.K = K
+        self.K_at = K_at
+        self.R_base = np.zeros(n) if R_base is None else np.array(R_base, dtype=np.float64)
+        self.u_base = np.zeros(n) if u_base is None else np.array(u_base, dtype=np.float64)
+
+    def force(self, u: np.ndarray) -> np.ndarray:
+        return self.R_base + self.K @ (u - self.u_base)
+
+    def refresh(self, u: np.ndarray) -> None:
+        self.R_base = self.force(u)
+        self.u_base = np.array(u, dtype=np.float64)
+        self.K = self.K_at(self.u_base)
 
 
 def deformed_stiffness(xyz: np.ndarray, tri: np.ndarray, u: np.ndarray, eh_col: np.ndarray, nu: float,

@@ -44,6 +44,7 @@ from typing import Callable, Optional, Sequence
 import numpy as np
 
 from . import assembly
+from .geometry import IncrementalForce
 
 
 def load_factor(kind: str, t: float, T_ramp: float = 0.0, period: float = 1.0, pulse_amp: float = 0.0) -> float:
@@ -97,14 +98,11 @@ def run_sample(K, m_node: np.ndarray, F: np.ndarray, fixed: np.ndarray, dt: floa
     energy = []
     m_dof = np.repeat(m_node, 3)
     offset = R_base is not None or u_base is not None or every
-    Rb = np.zeros(n_dof) if R_base is None else np.array(R_base, dtype=np.float64)
-    ub = np.zeros(n_dof) if u_base is None else np.array(u_base, dtype=np.float64)
+    force = IncrementalForce(K, K_at, R_base, u_base)
     for n in range(n_steps):
         if every and n > 0 and n % every == 0:
-            Rb = Rb + K @ (u - ub)
-            ub = u.copy()
-            K = K_at(u)
-        R = Rb + K @ (u - ub) if offset else K @ u
+            force.refresh(u)
+        R = force.force(u) if offset else K @ u
         f = g(n * dt) * F - c_d * (u - u_prev) / dt
         u_next = (dt * dt * minv * (f - R) + 2.0 * u - (1.0 - a) * u_prev) / (1.0 + a)
         u_next[fixed] = 0.0
@@ -116,7 +114,8 @@ def run_sample(K, m_node: np.ndarray, F: np.ndarray, fixed: np.ndarray, dt: floa
         u_prev, u = u, u_next
         if (n + 1) in checkpoints:
             cps[n + 1] = u.copy()
-    return dict(u=u, u_prev=u_prev, q=q, checkpoints=cps, energy=energy, R_base=Rb, u_base=ub)
+    return dict(u=u, u_prev=u_prev, q=q, checkpoints=cps, energy=energy, R_base=force.R_base,
+                u_base=force.u_base)
 
 
 def run_ensemble(tri: np.ndarray, khat: np.ndarray, area: np.ndarray, eh: np.ndarray, h: np.ndarray,

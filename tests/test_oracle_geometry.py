@@ -108,3 +108,53 @@ def test_vanishing_load_gives_the_linear_run():
         diffs.append(np.linalg.norm(ref["u"] - plain["u"]) / np.linalg.norm(plain["u"]))
     assert diffs[0] > 1e-3
     assert diffs[1] < 1e-3 * diffs[0]
+
+
+@pytest.mark.parametrize("k", [1, 4, 16])
+def test_stretch_in_refreshed_increments_carries_the_sum_of_edge_tractions(k):
+    """Flat 1 x 1 plate (z = 0, unit E h) stretched along x from 1 to 1.6 in
+    k equal increments, the matrix rebuilt on the stretched plate after each.
+    Increment j is a homogeneous strain eps_j = dlam / lam_{j-1} of the plate
+    as stretched before it (width lam_{j-1}), so its nodal forces are the
+    edge tractions of sigma = C eps_j: zero inside, sigma_xx eps_j / (1 -
+    nu^2) on the right edge (height 1), nu eps_j / (1 - nu^2) lam_{j-1} on
+    the top edge.  The carried force is the sum over the increments; the
+    total form K_{k-1} u_k would put (lam_k - 1) / lam_{k-1} on the edge."""
+    n = 7
+    g = np.linspace(0.0, 1.0, n)
+    X, Y = np.meshgrid(g, g)
+    xyz = np.stack([X.ravel(), Y.ravel(), np.zeros(n * n)], 1)
+    tri = []
+    for j in range(n - 1):
+        for i in range(n - 1):
+            a = j * n + i
+            if (i + j) % 2:
+                tri += [(a, a + 1, a + n + 1), (a, a + n + 1, a + n)]
+            else:
+                tri += [(a, a + 1, a + n), (a + 1, a + n + 1, a + n)]
+    tri = np.array(tri, dtype=np.int32)
+    ones = np.ones(len(tri))
+    K_at = lambda u: geometry.deformed_stiffness(xyz, tri, u, ones, NU, KS)
+    lam = np.linspace(1.0, 1.6, k + 1)
+    path = [((l - 1.0) * xyz * np.array([1.0, 0.0, 0.0])).ravel() for l in lam]
+    force = geometry.IncrementalForce(K_at(path[0]), K_at)
+    for j in range(1, k):
+        force.refresh(path[j])
+    R = force.force(path[k]).reshape(-1, 3)
+    eps = np.diff(lam) / lam[:-1]
+    fx_right = np.sum(eps) / (1.0 - NU * NU)
+    fy_top = np.sum(NU * eps * lam[:-1]) / (1.0 - NU * NU)
+    right = np.isclose(xyz[:, 0], 1.0)
+    top = np.isclose(xyz[:, 1], 1.0)
+    inner = ~(right | top | np.isclose(xyz[:, 0], 0.0) | np.isclose(xyz[:, 1], 0.0))
+    scale = fx_right
+    assert abs(R[right, 0].sum() - fx_right) <= 1e-12 * scale
+    assert abs(R[top, 1].sum() - fy_top) <= 1e-12 * scale
+    # each right-edge node carries its share of the edge (corners half)
+    share = np.where(np.isclose(xyz[right, 1], 0.0) | np.isclose(xyz[right, 1], 1.0), 0.5, 1.0) / (n - 1)
+    assert np.max(np.abs(R[right, 0] - fx_right * share)) <= 1e-12 * scale
+    assert np.max(np.abs(R[inner])) <= 1e-12 * scale
+    assert np.max(np.abs(R[:, 2])) <= 1e-12 * scale
+    if k > 1:
+        total = (lam[-1] - 1.0) / lam[-2] / (1.0 - NU * NU)
+        assert abs(total - fx_right) > 1e-2 * fx_right

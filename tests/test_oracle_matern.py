@@ -58,3 +58,24 @@ def test_circulant_lattice_sampler_matches_matern():
     Sig = matern.covariance(d, 0.2, 1.0, 2.0)
     se = np.sqrt((Sig ** 2 + np.outer(np.diag(Sig), np.diag(Sig))) / N)
     assert np.mean(np.abs(C - Sig) / se) < 1.2
+
+
+def test_lognormal_fields_log_means_and_spread():
+    """4,096 draws on a 12 x 6 cylinder: per element, the sample means of
+    log E = log((E h) / h) and of log h lie within 5 standard errors
+    (0.2 / sqrt(S)) of log 7e6 and log 0.1, their variances within 5
+    standard errors of 0.2^2, and log E and log h are uncorrelated
+    (independent draws)."""
+    m = inputs.cylinder(1.0, 10.0, 12, 6)
+    S = 4096
+    eh, h = matern.lognormal_fields(m.xyz, m.tri, S, seed=31)
+    lE, lh = np.log(eh / h), np.log(h)
+    se_mean = 0.2 / math.sqrt(S)
+    se_var = 0.04 * math.sqrt(2.0 / (S - 1))
+    for lf, mu in ((lE, math.log(7.0e6)), (lh, math.log(0.1))):
+        assert np.max(np.abs(lf.mean(axis=1) - mu)) < 5.0 * se_mean
+        assert abs(lf.mean() - mu) < 5.0 * se_mean
+        assert np.max(np.abs(lf.var(axis=1, ddof=1) - 0.04)) < 5.0 * se_var
+    cE, ch = lE - lE.mean(axis=1, keepdims=True), lh - lh.mean(axis=1, keepdims=True)
+    corr = np.sum(cE * ch, axis=1) / np.sqrt(np.sum(cE * cE, axis=1) * np.sum(ch * ch, axis=1))
+    assert np.max(np.abs(corr)) < 5.0 / math.sqrt(S)
