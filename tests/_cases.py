@@ -55,3 +55,26 @@ def oracle_apply(cs, U):
         K = assembly.assemble_stiffness(cs.mesh.tri, cs.khat, cs.eh[:, s], cs.mesh.n_nodes)
         out[:, s] = K @ U[:, s]
     return out
+
+
+def per_sample_max_rel(a, b):
+    """Largest per-column relative L2 error (a column is one sample)."""
+    num = np.linalg.norm(a - b, axis=0)
+    den = np.linalg.norm(b, axis=0)
+    return float(np.max(num / den))
+
+
+def c2_oracle_column(args):
+    """Oracle run of one sample column of the full-size steady cylinder
+    (400 x 500 nodes, S = 256): returns (u_N, q_N) of that column.  Runs in a
+    worker process of its own (CPU only)."""
+    col, n_steps = args
+    c = inputs.CONFIGS["c2_cylinder"]
+    m = inputs.cylinder(c["R"], c["L"], c["n_theta"], c["n_z"])
+    eh, h = inputs.lognormal_fields(m, c["S"], c["seed"])
+    F = inputs.traction_load(m, c["p0"])
+    kh, A, _ = element.reference_stiffness(m.xyz, m.tri, c["nu"], c["shear_k"])
+    dt = cfl.stable_dt(kh, A, eh, h, c["rho"], c["safety"])
+    r = stepper.run_ensemble(m.tri, kh, A, eh, h, c["rho"], F, m.fixed, m.radial, dt, n_steps, c["alpha"],
+                             lambda t: 1.0, samples=[col])
+    return r["u"][:, 0], r["q"][:, 0]

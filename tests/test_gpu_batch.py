@@ -1,13 +1,14 @@
 """Batching form on the GPU: several meshes of uneven size and ensemble
 width stepped by one launch per step (graph-captured loop); every mesh must
 match its solo run bitwise, across graph replays, remainders, parity flips
-and an autotuner pass."""
+and an autotuner pass, and sampled columns of every member must match the
+FP64 oracle (1e-10 for the FP64 apply, 1e-5 for the FP32 apply)."""
 import numpy as np
 import pytest
 
 from paper_2101_09059_amd import ensfem, inputs
-from oracle import cfl, element
-from tests._cases import say
+from oracle import cfl, element, stepper
+from tests._cases import say, rel_l2, per_sample_max_rel
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -15,15 +16,24 @@ pytestmark = pytest.mark.gpu
 SPECS = [(12, 8, 64), (30, 21, 128), (47, 40, 192), (17, 9, 256), (64, 33, 64)]
 
 
+T_RAMP = 0.003
+
+
+def _member_inputs(i):
+    nt, nz, S = SPECS[i]
+    m = inputs.cylinder(0.5 + 0.1 * i, 3.0 + i, nt, nz)
+    eh, h = inputs.lognormal_fields(m, S, seed=40 + i)
+    F = inputs.traction_load(m, 1.33e5)
+    kh, A, _ = element.reference_stiffness(m.xyz, m.tri, 0.49, 5.0 / 6.0)
+    dt = cfl.stable_dt(kh, A, eh, h, 1.0, 0.9)
+    return m, eh, h, F, kh, A, dt
+
+
 def _members(apply_prec, state_prec):
     out = []
     for i, (nt, nz, S) in enumerate(SPECS):
-        m = inputs.cylinder(0.5 + 0.1 * i, 3.0 + i, nt, nz)
-        eh, h = inputs.lognormal_fields(m, S, seed=40 + i)
-        F = inputs.traction_load(m, 1.33e5)
-        kh, A, _ = element.reference_stiffness(m.xyz, m.tri, 0.49, 5.0 / 6.0)
-        dt = cfl.stable_dt(kh, A, eh, h, 1.0, 0.9)
-        kw = dict(alpha=50.0, kind=ensfem.LOAD_RAMP_SINE, t_ramp=0.003, apply_prec=apply_prec,
+        m, eh, h, F, kh, A, dt = _member_inputs(i)
+        kw = dict(alpha=50.0, kind=ensfem.LOAD_RAMP_SINE, t_ramp=T_RAMP, apply_prec=apply_prec,
                   state_prec=state_prec, sample_block=64)
         a = ensfem.setup_case(m, eh, h, F, **kw)
         b = ensfem.setup_case(m, eh, h, F, **kw)
@@ -103,3 +113,35 @@ def test_batch_rejects_incompatible_members():
         ensfem.Batch([a, c])
     for e in (a, b, c):
         e.close()
+
+
+@pytest.mark.parametrize("apply_prec,tol", [(ensfem.F64, 1e-10), (ensfem.F32, 1e-5)])
+def test_batch_members_match_oracle(apply_prec, tol):
+    """After an autotuner pass, 301 batched steps (graph replays plus an odd
+    remainder; both lane classes: widths 64 and 192 have a last block of 64
+    samples): the first, a middle and the last sample column of every member
+    against the oracle's per-sample run."""
+    say(f"case: batch vs oracle apply={apply_prec}")
+    pairs = _members(apply_prec, ensfem.STATE_F64)
+    _start(pairs)
+    batch = ensfem.Batch([b for _, b, _ in pairs])
+    batch.autotune(2)
+    say(f"  tuned: {batch.info()}")
+    _start(pairs)
+    n = 301
+    batch.step(n)
+    g = lambda t: stepper.load_factor("sine", t, T_RAMP)
+    for i, (a, b, dt) in enumerate(pairs):
+        m, eh, h, F, kh, A, dt_o = _member_inputs(i)
+        assert dt_o == dt
+        S = SPECS[i][2]
+        cols = [0, S // 2 + 1, S - 1]
+        u, q = b.read_state()[:, cols], b.read_qoi()[:, cols]
+        ref = stepper.run_ensemble(m.tri, kh, A, eh, h, 1.0, F, m.fixed, m.radial, dt, n, 50.0, g, samples=cols)
+        eu, es, eq = rel_l2(u, ref["u"]), per_sample_max_rel(u, ref["u"]), rel_l2(q, ref["q"])
+        say(f"  member {i} ({m.n_nodes} nodes, S={S}): rel L2 u {eu:.2e} (per-sample max {es:.2e}), q {eq:.2e}")
+        assert eu <= tol and es <= tol and eq <= tol
+    batch.close()
+    for a, b, _ in pairs:
+        a.close()
+        b.close()

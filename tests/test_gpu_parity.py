@@ -11,7 +11,7 @@ import pytest
 
 from oracle import stats, stepper, cfl
 from paper_2101_09059_amd import ensfem, inputs
-from tests._cases import c1_case, small_case, say, rel_l2, oracle_apply
+from tests._cases import c1_case, small_case, say, rel_l2, oracle_apply, per_sample_max_rel
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -81,7 +81,9 @@ def test_c1_fp64_2000_steps_vs_oracle():
                                checkpoints=tuple(range(200, 2001, 200)))
     for n, u in cps.items():
         assert rel_l2(u, ref["checkpoints"][n]) <= 1e-10, n
+        assert per_sample_max_rel(u, ref["checkpoints"][n]) <= 1e-10, n
     assert rel_l2(q, ref["q"]) <= 1e-10
+    assert per_sample_max_rel(q, ref["q"]) <= 1e-10
     m_ref, v_ref = stats.moments(ref["q"])
     assert rel_l2(mean, m_ref) <= 1e-10
     assert rel_l2(var, v_ref) <= 1e-9
@@ -97,9 +99,13 @@ def test_c1_100k_steps_vs_golden(mode, tol):
     say(f"case: C1 100k steps {mode}")
     cps, q, _, _ = _run_gpu(cs, 100_000, 10_000, **kw)
     errs = [rel_l2(cps[int(n)], g["u"][i]) for i, n in enumerate(g["steps"])]
+    worst = [per_sample_max_rel(cps[int(n)], g["u"][i]) for i, n in enumerate(g["steps"])]
     say(f"  {mode}: rel L2 per checkpoint {['%.2e' % e for e in errs]}")
+    say(f"  {mode}: per-sample max per checkpoint {['%.2e' % e for e in worst]}")
     assert max(errs) <= tol
+    assert max(worst) <= tol
     assert rel_l2(q, g["q"]) <= tol
+    assert per_sample_max_rel(q, g["q"]) <= tol
 
 
 def test_c1_plain_fp32_state_is_worse_than_kahan():
@@ -323,33 +329,45 @@ def test_error_paths():
     ens.close()
 
 
-@pytest.mark.parametrize("apply_prec", [ensfem.F64, ensfem.F32])
-def test_c2_full_size_sampled_columns(apply_prec):
+def test_c2_full_size_sampled_columns():
     """The bench workload (400 x 500 cylinder, S = 256) in the bench's launch
-    configuration, 40 steps, two sample columns checked against the oracle."""
+    configuration, FP64 and FP32 apply, 2,000 steps (about 2.7 periods of
+    the wall's breathing mode, past the starter transient), three sample
+    columns checked against the oracle, which runs them in three CPU worker
+    processes while the GPU steps."""
+    import multiprocessing as mp
+    from tests._cases import c2_oracle_column
     c = inputs.CONFIGS["c2_cylinder"]
-    say(f"case: C2 full size, apply_prec={apply_prec}")
+    n, cols = 2000, [0, 137, 255]
+    say(f"case: C2 full size, {n} steps, oracle columns {cols} in worker processes")
+    pool = mp.get_context("spawn").Pool(len(cols))
+    pending = pool.map_async(c2_oracle_column, [(col, n) for col in cols])
+    pool.close()
     m = inputs.cylinder(c["R"], c["L"], c["n_theta"], c["n_z"])
     eh, h = inputs.lognormal_fields(m, c["S"], c["seed"])
     F = inputs.traction_load(m, c["p0"])
-    from oracle import element, assembly
+    from oracle import element
     kh, A, _ = element.reference_stiffness(m.xyz, m.tri, c["nu"], c["shear_k"])
     dt = cfl.stable_dt(kh, A, eh, h, c["rho"], c["safety"])
-    ens = ensfem.setup_case(m, eh, h, F, alpha=c["alpha"], apply_prec=apply_prec)
-    assert abs(ens.cfl_dt(0.9) / dt - 1) < 1e-12
-    ens.init_state()
-    n = 40
-    ens.step(n, dt)
-    u = ens.read_state()
-    q = ens.read_qoi()
-    ens.close()
-    g = lambda t: 1.0
-    cols = [0, 137, 255]
-    ref = stepper.run_ensemble(m.tri, kh, A, eh, h, c["rho"], F, m.fixed, m.radial, dt, n, c["alpha"], g,
-                               samples=cols)
-    tol = 1e-10 if apply_prec == ensfem.F64 else 1e-5
-    assert rel_l2(u[:, cols], ref["u"]) <= tol
-    assert rel_l2(q[:, cols], ref["q"]) <= tol
+    got = {}
+    for apply_prec in (ensfem.F64, ensfem.F32):
+        say(f"  GPU run apply_prec={apply_prec}")
+        ens = ensfem.setup_case(m, eh, h, F, alpha=c["alpha"], apply_prec=apply_prec)
+        assert abs(ens.cfl_dt(0.9) / dt - 1) < 1e-12
+        ens.init_state()
+        ens.step(n, dt)
+        got[apply_prec] = (ens.read_state()[:, cols], ens.read_qoi()[:, cols])
+        ens.close()
+    say("  waiting for the oracle columns")
+    res = pending.get(timeout=600)
+    pool.join()
+    ref_u = np.stack([r[0] for r in res], axis=1)
+    ref_q = np.stack([r[1] for r in res], axis=1)
+    for apply_prec, tol in ((ensfem.F64, 1e-10), (ensfem.F32, 1e-5)):
+        u, q = got[apply_prec]
+        eu, es, eq = rel_l2(u, ref_u), per_sample_max_rel(u, ref_u), rel_l2(q, ref_q)
+        say(f"  apply_prec={apply_prec}: rel L2 u {eu:.2e} (per-sample max {es:.2e}), q {eq:.2e}")
+        assert eu <= tol and es <= tol and eq <= tol
 
 
 @pytest.mark.parametrize("sb", [64, 128, 256])
@@ -608,3 +626,37 @@ def test_peak_tracking_through_many_turns(sb):
                                  cs.mesh.radial, cs.dt, 1000, 0.0, g, samples=cols)
     assert rel_l2(q_mid[:, cols], r_mid["q"]) <= 1e-10
     assert rel_l2(q_end[:, cols], r_end["q"]) <= 1e-10
+
+
+@pytest.mark.parametrize("mode,tol", [("f64", 1e-10), ("f32_apply_f64_state", 1e-5), ("f32_kahan", 1e-5)])
+def test_curved_tapered_tube_pulsatile_shear_vs_oracle(mode, tol):
+    """The precision form's own workload at small size: the curved tapered
+    tube (centreline arc of radius 8 cm, 20 cm long, radius 1.2 -> 0.6 cm) on
+    a 24 x 96 node lattice, S = 16, the sine-ramped pulsatile pressure with
+    the axial taper and the seeded 1 % wall shear (the workload's own load
+    parameters), 2,000 steps, every sample column against the oracle."""
+    c = inputs.CONFIGS["c3_curved"]
+    m = inputs.curved_tube(24, 96)
+    S = 16
+    eh, h = inputs.lognormal_fields(m, S, c["seed"], radius=0.9)
+    F = inputs.traction_load(m, c["p0"], axial_taper=c["axial_taper"], shear_frac=c["shear_frac"], seed=c["seed"])
+    from oracle import element
+    kh, A, _ = element.reference_stiffness(m.xyz, m.tri, c["nu"], c["shear_k"])
+    dt = cfl.stable_dt(kh, A, eh, h, c["rho"], c["safety"])
+    n = 2000
+    kw = dict(f64={}, f32_apply_f64_state=dict(apply_prec=ensfem.F32),
+              f32_kahan=dict(apply_prec=ensfem.F32, state_prec=ensfem.STATE_F32_KAHAN))[mode]
+    say(f"case: curved tapered tube 24x96, S={S}, C3 load, {n} steps, {mode}")
+    ens = ensfem.setup_case(m, eh, h, F, nu=c["nu"], shear_k=c["shear_k"], rho=c["rho"], alpha=c["alpha"],
+                            kind=ensfem.LOAD_PULSATILE, t_ramp=c["T_ramp"], amp=c["pulse_amp"],
+                            period=c["period"], **kw)
+    assert abs(ens.cfl_dt(c["safety"]) / dt - 1) < 1e-12
+    ens.init_state()
+    ens.step(n, dt)
+    u, q = ens.read_state(), ens.read_qoi()
+    ens.close()
+    g = lambda t: stepper.load_factor(c["ramp"], t, c["T_ramp"], c["period"], c["pulse_amp"])
+    ref = stepper.run_ensemble(m.tri, kh, A, eh, h, c["rho"], F, m.fixed, m.radial, dt, n, c["alpha"], g)
+    eu, es, eq = rel_l2(u, ref["u"]), per_sample_max_rel(u, ref["u"]), rel_l2(q, ref["q"])
+    say(f"  rel L2 u {eu:.2e} (per-sample max {es:.2e}), q {eq:.2e}")
+    assert eu <= tol and es <= tol and eq <= tol
