@@ -70,6 +70,20 @@ int32_t sur_train_step(sur_net* s, const float* X, const float* T, int32_t batch
  * host FP64 arrays [n_out].  Synchronizes. */
 int32_t sur_moments(sur_net* s, const float* X, int64_t M, double* sum_host, double* sumsq_host,
                     void* stream);
+/* Squared error of the physical-unit predictions against targets:
+ * *acc (device FP64 scalar) += sum over the batch rows and outputs j of
+ * (mu[j] + sd[j] y[r][j] - Q[r][j])^2, with y = network(X [batch][n_in])
+ * and Q [batch][n_out], mu, sd [n_out] device FP64 (the targets'
+ * standardization).  Summation order is fixed.  Enqueued on `stream`;
+ * ENS_EINVAL for a batch outside 1 .. max_batch. */
+int32_t sur_sq_error(sur_net* s, const float* X, int32_t batch, const double* Q, const double* mu, const double* sd,
+                     double* acc, void* stream);
+/* Row gather for minibatches: dst[r][:] = src[idx[r]][:] for r < n_rows,
+ * FP32 rows of n_cols values, idx device int32 (each in range of src, which
+ * the caller guarantees).  ENS_EINVAL for n_cols < 1 or n_rows outside
+ * 0 .. 65535.  Enqueued on `stream`. */
+int32_t sur_gather_rows(const float* src, int64_t n_cols, const int32_t* idx, int32_t n_rows, float* dst,
+                        void* stream);
 /* Control-variate combination per row (device FP64 arrays):
  * qH, qL [n][N] paired high / low fidelity values, sumL / sumsqL [n] sums
  * of the low-fidelity values and squares over M independent inputs.

@@ -361,6 +361,52 @@ __global__ void k_moment_accumulate(int rb, int N, const float* __restrict__ P1,
   S2[n] += b;
 }
 
+// Squared error of the physical-unit predictions mu + sd y against Q over
+// [rows][n_out] (FP64): per-workgroup partials in a fixed order.
+__global__ __launch_bounds__(256) void k_sq_error(int64_t n, int n_out, const float* __restrict__ y,
+                                                  const double* __restrict__ Q, const double* __restrict__ mu,
+                                                  const double* __restrict__ sd, double* __restrict__ part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const int j = (int)(i % n_out);
+    const double d = fma(sd[j], (double)y[i], mu[j]) - Q[i];
+    acc = fma(d, d, acc);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// *acc += the sum of the partials (fixed order, one workgroup)
+__global__ __launch_bounds__(256) void k_parts_add(int nparts, const double* __restrict__ part,
+                                                   double* __restrict__ acc) {
+  __shared__ double red[256];
+  double v = 0.0;
+  for (int i = threadIdx.x; i < nparts; i += 256) v += part[i];
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *acc += red[0];
+}
+
+// dst[r][:] = src[idx[r]][:] for FP32 rows of n_cols values.
+__global__ __launch_bounds__(256) void k_gather_rows(int64_t n_cols, const int32_t* __restrict__ idx,
+                                                     const float* __restrict__ src, float* __restrict__ dst) {
+  const int64_t r = blockIdx.y;
+  const float* from = src + (int64_t)idx[r] * n_cols;
+  float* to = dst + r * n_cols;
+  for (int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x; c < n_cols; c += (int64_t)gridDim.x * 256)
+    to[c] = from[c];
+}
+
 // Control-variate combination per node (FP64), see sur_cv_moments.
 __global__ void k_cv(int64_t n, int N, const double* __restrict__ qH, const double* __restrict__ qL,
                      const double* __restrict__ sL, const double* __restrict__ sL2, double M,
@@ -844,6 +890,35 @@ int32_t sur_moments(sur_net* s, const float* X, int64_t M, double* sum_host, dou
   SHIPC(hipMemcpy(sum_host, S1, 8 * (size_t)s->n_out, hipMemcpyDeviceToHost));
   SHIPC(hipMemcpy(sumsq_host, S2, 8 * (size_t)s->n_out, hipMemcpyDeviceToHost));
   return ENS_OK;
+}
+
+int32_t sur_sq_error(sur_net* s, const float* X, int32_t batch, const double* Q, const double* mu, const double* sd,
+                     double* acc, void* stream) {
+  if (!s || !X || !Q || !mu || !sd || !acc) return ENS_EINVAL;
+  if (!s->have_params) return s->fail(ENS_ESTATE, "sur_sq_error: set the parameters first");
+  if (batch < 1 || batch > s->max_batch) return s->fail(ENS_EINVAL, "sur_sq_error: batch out of range");
+  SHIPC(hipSetDevice(s->device));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int32_t rc = forward_hidden(s, X, batch, st);
+  if (rc != ENS_OK) return rc;
+  GemmArgs g = output_gemm(s, batch);
+  g.C32 = s->p<float>(s->o_y);
+  SHIPC((gemm<true, true, EPI_BIAS_F32>(g, 1, st)));
+  const int64_t n = (int64_t)batch * s->n_out;
+  const unsigned nb = std::min(blocks(n), kLossParts);
+  SHIPC((k_sq_error<<<nb, 256, 0, st>>>(n, s->n_out, s->p<float>(s->o_y), Q, mu, sd, s->p<double>(s->o_lpart)),
+         hipGetLastError()));
+  SHIPC((k_parts_add<<<1, 256, 0, st>>>((int)nb, s->p<double>(s->o_lpart), acc), hipGetLastError()));
+  return ENS_OK;
+}
+
+int32_t sur_gather_rows(const float* src, int64_t n_cols, const int32_t* idx, int32_t n_rows, float* dst,
+                        void* stream) {
+  if (!src || !idx || !dst || n_cols < 1 || n_rows < 0 || n_rows > 65535) return ENS_EINVAL;
+  if (n_rows == 0) return ENS_OK;
+  const unsigned gx = (unsigned)std::min<int64_t>((n_cols + 255) / 256, 1024);
+  k_gather_rows<<<dim3(gx, (unsigned)n_rows), 256, 0, static_cast<hipStream_t>(stream)>>>(n_cols, idx, src, dst);
+  return hipGetLastError() == hipSuccess ? ENS_OK : ENS_EDEVICE;
 }
 
 int32_t sur_cv_moments(const double* qH, const double* qL, int64_t n, int32_t N, const double* sumL,

@@ -16,7 +16,9 @@
 //
 // or, for the FP32 states, its velocity form
 //   v_{n+1/2} = ((1 - a) v_{n-1/2} + dt m^-1 (g F - R)) / (1 + a),
-//   u_{n+1}   = u_n + dt v_{n+1/2}   (Kahan-compensated in F32_KAHAN).
+//   u_{n+1}   = u_n + dt v_{n+1/2}
+// formed in FP64 from the stored FP32 values (F32_KAHAN stores u as a
+// compensated pair u_hi - u_lo).
 // Clamped dofs are written as zero.  Optional outputs in the same pass:
 // running peak radial displacement and the per-sample discrete energy.
 #include "internal.h"
@@ -555,45 +557,51 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int j, int node, in
       }
     }
   } else {
+    // FP32 storage, FP64 arithmetic: the stored pair (or single value) and
+    // velocity are widened, the velocity-form update is formed in FP64
+    // with the exact coefficients, and the results are rounded once on the
+    // way out.  F32_KAHAN keeps the rounding of u in the low part:
+    // u_hi = fl32(u), u_lo = fl32(u_hi - u), so u = u_hi - u_lo carries
+    // every increment's rounding (compensated summation, the increment
+    // itself held exactly).
     float minv[SPL];
     vload<SPL, true>(static_cast<const float*>(gen(p.minv)) + ms, minv);
-    const float dtf = (float)p.dt;
-    const float inv1pa = (float)(1.0 / (1.0 + p.a));
-    const float oma = (float)(1.0 - p.a);
+    const double inv1pa = 1.0 / (1.0 + p.a);
+    const double oma = 1.0 - p.a;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int64_t idx = (row + c) * ld + s0;
-      const float fc = (float)(g * maybe_uni<UNI>(cst(p.F)[row + c]));
+      const double fc = g * maybe_uni<UNI>(cst(p.F)[row + c]);
       float vel[SPL], cc[SPL], uh[SPL];
       vload<SPL, true>(gen(p.v) + idx, vel);
       if constexpr (MODE == kStateF32Kahan) vload<SPL, true>(gen(p.uc) + idx, cc);
 #pragma unroll
       for (int i = 0; i < SPL; ++i) {
-        if constexpr (MODE == kStateF32Kahan) uo[c][i] = (double)ua[c][i] - (double)cc[i];
-        else uo[c][i] = (double)ua[c][i];
-        float acc = minv[i] * (fc - (float)r[c][i]);
+        double u0 = (double)ua[c][i];
+        if constexpr (MODE == kStateF32Kahan) u0 -= (double)cc[i];
+        uo[c][i] = u0;
+        const double m = (double)minv[i];
+        const double v0 = (double)vel[i];
+        double acc = m * (fc - (double)r[c][i]);
         // explicit viscous force -c_d v_{n-1/2}
-        if (p.cd != 0.0) acc = fmaf(-(minv[i] * (float)p.cd), vel[i], acc);
-        vel[i] = fmaf(dtf, acc, oma * vel[i]) * inv1pa;
-        uh[i] = ua[c][i];
-        if constexpr (MODE == kStateF32Kahan) {
-          const float y = fmaf(dtf, vel[i], -cc[i]);
-          const float t = uh[i] + y;
-          cc[i] = (t - uh[i]) - y;
-          uh[i] = t;
-        } else {
-          cc[i] = 0.0f;
-          uh[i] = fmaf(dtf, vel[i], uh[i]);
-        }
+        if (p.cd != 0.0) acc = fma(-(m * p.cd), v0, acc);
+        const double vn = fma(p.dt, acc, oma * v0) * inv1pa;
+        const double un_ = fma(p.dt, vn, u0);
+        float hi = (float)un_;
+        float lo = 0.0f;
+        if constexpr (MODE == kStateF32Kahan) lo = (float)((double)hi - un_);
+        float vf = (float)vn;
         if (fx & (1u << c)) {
-          uh[i] = 0.0f;
-          cc[i] = 0.0f;
-          vel[i] = 0.0f;
+          hi = 0.0f;
+          lo = 0.0f;
+          vf = 0.0f;
         }
-        un[c][i] = (double)uh[i] - (double)cc[i];
+        uh[i] = hi;
+        cc[i] = lo;
+        vel[i] = vf;
+        un[c][i] = (double)hi - (double)lo;
         if constexpr (ENERGY) {
-          e_loc[i] += 0.5 / (double)minv[i] * (double)vel[i] * (double)vel[i] +
-                      0.5 * un[c][i] * (double)r[c][i];
+          e_loc[i] += 0.5 / m * (double)vf * (double)vf + 0.5 * un[c][i] * (double)r[c][i];
         }
       }
       vstore<SPL, true>(gen(p.uh_next) + idx, uh);

@@ -115,6 +115,8 @@ _SIGS = {
     "sur_train_step": (_I32, [_P, _P, _P, _I32, ctypes.c_float, _P, _P]),
     "sur_moments": (_I32, [_P, _P, _I64, _P, _P, _P]),
     "sur_cv_moments": (_I32, [_P, _P, _I64, _I32, _P, _P, _I64, _P, _P, _P, _P]),
+    "sur_sq_error": (_I32, [_P, _P, _I32, _P, _P, _P, _P, _P]),
+    "sur_gather_rows": (_I32, [_P, _I64, _P, _I32, _P, _P]),
     "spde_create": (_I32, [_I32, _P]),
     "spde_destroy": (_I32, [_P]),
     "spde_last_error": (ctypes.c_char_p, [_P]),
@@ -529,6 +531,28 @@ class Surrogate:
         self._check(self._lib.sur_train_step(self._h, X.data_ptr(), T.data_ptr(), X.shape[0], float(lr),
                                              self._loss.data_ptr(), _stream_handle(stream)))
         return self._loss
+
+    def sq_error(self, X, Q, mu, sd, acc, stream=None):
+        """acc (device FP64 scalar) += sum of (mu + sd y - Q)^2 over the rows
+        of X (device FP32) and the outputs; Q device FP64 [rows, n_out], mu,
+        sd device FP64 [n_out]."""
+        import torch
+        assert Q.dtype == torch.float64 and mu.dtype == torch.float64 and sd.dtype == torch.float64
+        assert acc.dtype == torch.float64 and Q.shape == (X.shape[0], self.n_out)
+        self._check(self._lib.sur_sq_error(self._h, X.contiguous().data_ptr(), X.shape[0], Q.contiguous().data_ptr(),
+                                           mu.data_ptr(), sd.data_ptr(), acc.data_ptr(), _stream_handle(stream)))
+
+    def gather_rows(self, src, idx, out, stream=None):
+        """out[r] = src[idx[r]] (device FP32 rows, idx device int32)."""
+        import torch
+        assert src.dtype == torch.float32 and out.dtype == torch.float32 and idx.dtype == torch.int32
+        assert src.is_contiguous() and out.is_contiguous() and idx.is_contiguous()
+        assert out.shape[0] >= idx.numel() and out.shape[1:] == src.shape[1:]
+        rc = self._lib.sur_gather_rows(src.data_ptr(), src[0].numel(), idx.data_ptr(), idx.numel(), out.data_ptr(),
+                                       _stream_handle(stream))
+        if rc != ENS_OK:
+            raise EnsfemError(rc, "sur_gather_rows failed")
+        return out[:idx.numel()]
 
     def moments(self, X, stream=None):
         s1 = np.empty(self.n_out)

@@ -130,10 +130,13 @@ class Network:
         if n_val:
             Xv = torch.as_tensor(X[vset], dtype=torch.float32, device=dev)
             Qv = torch.as_tensor(Q[vset], dtype=torch.float64, device=dev)
-            qv_norm = float(torch.linalg.vector_norm(Qv))
+            qv_norm = float(np.linalg.norm(Q[vset]))
             mu_t = torch.as_tensor(self.mu, dtype=torch.float64, device=dev)
             sd_t = torch.as_tensor(self.sd, dtype=torch.float64, device=dev)
+            sq_t = torch.zeros(1, dtype=torch.float64, device=dev)
             best_dev = torch.empty(self.net.n_params, dtype=torch.float32, device=dev)
+        xb = torch.empty((batch, Xt.shape[1]), dtype=torch.float32, device=dev)
+        tb = torch.empty((batch, Tt.shape[1]), dtype=torch.float32, device=dev)
         steps_per_epoch = int(math.ceil(n_tr / batch))
         total = epochs * steps_per_epoch
         hist = []
@@ -143,22 +146,20 @@ class Network:
         t0 = time.perf_counter()
         step = 0
         for ep in range(epochs):
-            order = torch.as_tensor(rng.permutation(n_tr), device=dev)
+            order = torch.as_tensor(rng.permutation(n_tr).astype(np.int32), device=dev)
             for b0 in range(0, n_tr, batch):
                 idx = order[b0:b0 + batch]
-                xb = Xt.index_select(0, idx).contiguous()
-                tb = Tt.index_select(0, idx).contiguous()
+                xs = self.net.gather_rows(Xt, idx, xb)
+                ts = self.net.gather_rows(Tt, idx, tb)
                 lr_t = 0.5 * lr * (1.0 + math.cos(math.pi * step / total))
-                loss = self.net.train_step(xb, tb, lr_t)
+                loss = self.net.train_step(xs, ts, lr_t)
                 step += 1
             hist.append(float(loss.item()))
             if n_val and ((ep + 1) % eval_every == 0 or ep + 1 == epochs):
-                sq = 0.0
+                sq_t.zero_()
                 for r0 in range(0, Xv.shape[0], self.max_batch):
-                    y = self.net.forward(Xv[r0:r0 + self.max_batch]).double()
-                    d = mu_t + sd_t * y - Qv[r0:r0 + self.max_batch]
-                    sq += float(torch.sum(d * d))
-                e = math.sqrt(sq) / qv_norm
+                    self.net.sq_error(Xv[r0:r0 + self.max_batch], Qv[r0:r0 + self.max_batch], mu_t, sd_t, sq_t)
+                e = math.sqrt(float(sq_t.item())) / qv_norm
                 self.val_history.append((ep + 1, e))
                 if e < best[0]:
                     self.net.get_params_device(best_dev)
@@ -180,7 +181,7 @@ class Network:
         out = []
         Xt = torch.as_tensor(X, dtype=torch.float32, device="cuda")
         for r0 in range(0, X.shape[0], self.max_batch):
-            out.append(self.net.forward(Xt[r0:r0 + self.max_batch]).double().cpu().numpy())
+            out.append(self.net.forward(Xt[r0:r0 + self.max_batch]).cpu().numpy().astype(np.float64))
         Y = np.concatenate(out)
         return self.mu + self.sd * Y
 

@@ -117,7 +117,9 @@ def test_c1_plain_fp32_state_is_worse_than_kahan():
     e_plain = rel_l2(cps[100_000], g["u"][-1])
     e_kahan = rel_l2(cpk[100_000], g["u"][-1])
     say(f"  plain FP32 state {e_plain:.3e}  Kahan {e_kahan:.3e}")
-    assert np.isfinite(e_plain) and e_kahan <= e_plain
+    # on this coarse mesh the FP32 apply's own error (a few 1e-7) is the
+    # floor of both states; the compensation still has to show
+    assert np.isfinite(e_plain) and e_kahan <= 0.75 * e_plain
 
 
 def test_nonzero_initial_state_and_pulsatile_load():
@@ -536,8 +538,9 @@ def test_precision_ladder_on_a_fine_mesh():
     """Precision modes against the FP64 path on a fine mesh (28,800 nodes,
     element size ~0.026 cm on a 1 cm radius), 4,000 steps of a ramped load:
     the FP32 apply with an FP64 state stays within 1e-7; both FP32 states
-    (their error is dominated by the FP32 velocity, which the Kahan update of
-    u does not touch) within 1e-5, the Kahan one no worse than the plain."""
+    within 1e-5, and the compensated pair at most half the plain FP32
+    state's error (the update is formed in FP64 for both, so the difference
+    is the compensation of u's rounding)."""
     say("case: fine cylinder 240x120, S=8, 4000 steps, precision modes")
     cs = small_case(240, 120, 8, seed=21, R=1.0, L=2.0)
     out = {}
@@ -554,7 +557,7 @@ def test_precision_ladder_on_a_fine_mesh():
     say(f"  against FP64: " + ", ".join(f"{k} {v:.2e}" for k, v in err.items()))
     assert err["f64"] <= 1e-7
     assert err["kahan"] <= 1e-5 and err["f32"] <= 1e-5
-    assert err["kahan"] <= 1.01 * err["f32"]
+    assert err["kahan"] <= 0.5 * err["f32"]
 
 
 def test_degenerate_sizes():

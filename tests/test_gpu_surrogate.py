@@ -154,3 +154,37 @@ def test_control_variate_kernel_matches_oracle():
     assert np.allclose(mean, ref["mean"], rtol=1e-12, atol=0)
     assert np.allclose(var, ref["var"], rtol=1e-10, atol=1e-14)
     assert np.allclose(rho, ref["rho"], rtol=1e-12, atol=0)
+
+
+def test_squared_error_and_row_gather():
+    """sur_sq_error: the physical-unit squared error of the network's own
+    forward output, accumulated over two batches, against numpy in FP64 on
+    that output (1e-12); sur_gather_rows: rows copied exactly."""
+    sizes, rows = [16, 64, 64, 300], 70
+    say("case: surrogate squared error and row gather")
+    params = _net(sizes, seed=3)
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((rows, sizes[0]))
+    net = ensfem.Surrogate(sizes[0], sizes[1], len(sizes) - 2, sizes[-1], max_batch=40)
+    net.set_params(ensfem.flatten_params(params))
+    Xd = torch.as_tensor(X, dtype=torch.float32, device="cuda")
+    mu = rng.standard_normal(sizes[-1])
+    sd = np.abs(rng.standard_normal(sizes[-1]))
+    sd[::7] = 0.0
+    Q = rng.standard_normal((rows, sizes[-1]))
+    mu_d, sd_d = torch.as_tensor(mu, device="cuda"), torch.as_tensor(sd, device="cuda")
+    Q_d = torch.as_tensor(Q, device="cuda")
+    acc = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ref = 0.0
+    for r0 in (0, 40):
+        net.sq_error(Xd[r0:r0 + 40], Q_d[r0:r0 + 40], mu_d, sd_d, acc)
+        y = net.forward(Xd[r0:r0 + 40]).cpu().numpy().astype(np.float64)
+        ref += float(np.sum((mu + sd * y - Q[r0:r0 + 40]) ** 2))
+    torch.cuda.synchronize()
+    assert abs(float(acc.item()) - ref) <= 1e-12 * ref
+    idx = torch.as_tensor(rng.permutation(rows)[:33].astype(np.int32), device="cuda")
+    out = torch.full((40, sizes[0]), float("nan"), dtype=torch.float32, device="cuda")
+    got = net.gather_rows(Xd, idx, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), Xd.cpu().numpy()[idx.cpu().numpy()])
+    net.close()
