@@ -214,6 +214,19 @@ int32_t ens_read_energy(ens_ctx* ctx, int64_t max_records, int64_t* steps_out, d
                         int64_t* n_out);
 int32_t ens_moments(ens_ctx* ctx, double* mean, double* var);
 
+/* Allocation-free ens_moments, for callers that cannot allocate device
+ * memory (code under graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same inputs, outputs and results as ens_moments (the
+ * same kernel and summation order: bitwise equal); its device staging lives
+ * in a fixed 16 MiB scratch array that the library holds on each GPU it runs
+ * on until the process ends, so it takes at most 1,048,576 nodes
+ * (ENS_EINVAL with a message beyond that; ens_moments has no such limit).
+ * The call allocates nothing (no hipMalloc / hipFree, no host buffers).
+ * Every call on a GPU shares that GPU's scratch and leaves its contents
+ * behind: calls that overlap on one GPU (from several threads or contexts)
+ * race and must be serialised by the caller.  Synchronizing. */
+int32_t ens_moments_noalloc(ens_ctx* ctx, double* mean, double* var);
+
 /* Wall stress of the current state in the local cylindrical frame (Sec.
  * 2.3, fluid-structure coupling): per element and sample, the local strains
  * of Sec. 2.2.1 (B times the element's nodal displacements in its frame),

@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -17,6 +18,36 @@
 using namespace ensfem;
 
 namespace {
+
+// Scratch of the allocation-free entry point (ens_moments_noalloc): a
+// file-scope device array, one copy per GPU, held until the process ends.
+// Host code never passes the array's name to a kernel or a copy (on the
+// host it only names the symbol); it uses the device address looked up once
+// per device with hipGetSymbolAddress.
+constexpr size_t kScratchBytes = size_t(16) << 20;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device`, which must be current.
+hipError_t scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void* scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_ptr[device];
+}
 
 constexpr size_t kAlign = 256;
 constexpr int kChunk = 1024;  // steps per load-factor table
@@ -486,6 +517,8 @@ int32_t ens_create(int32_t device, ens_ctx** out) {
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return ENS_EDEVICE;
   if (hipSetDevice(device) != hipSuccess) return ENS_EDEVICE;
+  // once per device, with it current: the allocation-free scratch's address
+  if (scratch_setup(device) != hipSuccess) return ENS_EDEVICE;
   ens_ctx* c = new (std::nothrow) ens_ctx();
   if (!c) return ENS_EINVAL;
   c->device = device;
@@ -1140,7 +1173,7 @@ int32_t ens_moments(ens_ctx* ctx, double* mean, double* var) {
   }
   const Layout& L = ctx->L;
   HIPC(launch_moments((int32_t)ctx->n_nodes, ctx->ld, ctx->S, ctx->p<double>(L.q), ctx->p<double>(L.mean),
-                      ctx->p<double>(L.var), nullptr));
+                      ctx->p<double>(L.var), nullptr, nullptr));
   std::vector<double> hm(ctx->n_nodes), hv(ctx->n_nodes);
   HIPC(hipMemcpy(hm.data(), ctx->p<void>(L.mean), sizeof(double) * ctx->n_nodes, hipMemcpyDeviceToHost));
   HIPC(hipMemcpy(hv.data(), ctx->p<void>(L.var), sizeof(double) * ctx->n_nodes, hipMemcpyDeviceToHost));
@@ -1148,6 +1181,36 @@ int32_t ens_moments(ens_ctx* ctx, double* mean, double* var) {
     mean[ctx->perm[i]] = hm[i];
     var[ctx->perm[i]] = hv[i];
   }
+  return ENS_OK;
+}
+
+int32_t ens_moments_noalloc(ens_ctx* ctx, double* mean, double* var) {
+  if (!ctx || !mean || !var) return ENS_EINVAL;
+  if (!(ctx->qoi_mask & ENS_QOI_PEAK_RADIAL))
+    return ctx->fail(ENS_ESTATE, "ens_moments_noalloc: QoI not enabled");
+  const size_t need = 2 * sizeof(double) * (size_t)ctx->n_nodes;
+  if (need > kScratchBytes)
+    return ctx->fail(ENS_EINVAL, "ens_moments_noalloc: " + std::to_string(ctx->n_nodes) +
+                                     " nodes exceed the scratch limit of " +
+                                     std::to_string(kScratchBytes / (2 * sizeof(double))) +
+                                     " nodes (use ens_moments)");
+  if (!ctx->bound || !ctx->state_init) return ctx->fail(ENS_ESTATE, "ens_moments_noalloc: no state");
+  HIPC(hipSetDevice(ctx->device));
+  double* dm = static_cast<double*>(scratch_ptr(ctx->device));
+  if (!dm) return ctx->fail(ENS_EDEVICE, "ens_moments_noalloc: scratch address not set up for this device");
+  double* dv = dm + ctx->n_nodes;
+  HIPC(hipDeviceSynchronize());
+  {
+    const int32_t rc = resolve_qoi(ctx);
+    if (rc != ENS_OK) return rc;
+  }
+  // every row is written, so nothing needs clearing; rows go straight to
+  // the caller's numbering
+  const Layout& L = ctx->L;
+  HIPC(launch_moments((int32_t)ctx->n_nodes, ctx->ld, ctx->S, ctx->p<double>(L.q), dm, dv,
+                      ctx->p<int32_t>(L.perm), nullptr));
+  HIPC(hipMemcpy(mean, dm, sizeof(double) * ctx->n_nodes, hipMemcpyDeviceToHost));
+  HIPC(hipMemcpy(var, dv, sizeof(double) * ctx->n_nodes, hipMemcpyDeviceToHost));
   return ENS_OK;
 }
 

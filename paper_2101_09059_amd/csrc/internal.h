@@ -165,8 +165,9 @@ hipError_t launch_qoi_resolve(int32_t n_nodes, int32_t ld, int sample_block, con
                               const uint64_t* qmask, hipStream_t st);
 hipError_t launch_combine_f32(int64_t n, const float* uh, const float* uc, double* out,
                               hipStream_t st);
+// out_row: optional row of each node in the outputs (nullptr: node i -> row i)
 hipError_t launch_moments(int32_t n_nodes, int32_t ld, int32_t S, const double* q, double* mean,
-                          double* var, hipStream_t st);
+                          double* var, const int32_t* out_row, hipStream_t st);
 hipError_t launch_check_finite(int64_t n, const void* x, int is_f32, int32_t* flag,
                                hipStream_t st);
 

@@ -919,10 +919,13 @@ __global__ __launch_bounds__(256) void k_combine_f32(int64_t n, const float* __r
 
 // Per-node mean and unbiased variance over the S real samples: one 64-lane
 // wave per node, fixed lane-strided order then a fixed butterfly.
+// With out_row the results of node i go to row out_row[i] (the caller's
+// numbering), else to row i.
 __global__ __launch_bounds__(64) void k_moments(int32_t n_nodes, int32_t ld, int32_t S,
                                                 const double* __restrict__ q,
                                                 double* __restrict__ mean,
-                                                double* __restrict__ var) {
+                                                double* __restrict__ var,
+                                                const int32_t* __restrict__ out_row) {
   const int node = blockIdx.x;
   if (node >= n_nodes) return;
   const double* row = q + (int64_t)node * ld;
@@ -937,8 +940,9 @@ __global__ __launch_bounds__(64) void k_moments(int32_t n_nodes, int32_t ld, int
   }
   for (int o = 32; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 64);
   if (threadIdx.x == 0) {
-    mean[node] = mu;
-    var[node] = S > 1 ? ss / (S - 1) : 0.0;
+    const int64_t o = out_row ? (int64_t)out_row[node] : (int64_t)node;
+    mean[o] = mu;
+    var[o] = S > 1 ? ss / (S - 1) : 0.0;
   }
 }
 
@@ -1175,9 +1179,9 @@ hipError_t launch_combine_f32(int64_t n, const float* uh, const float* uc, doubl
 }
 
 hipError_t launch_moments(int32_t n_nodes, int32_t ld, int32_t S, const double* q, double* mean,
-                          double* var, hipStream_t st) {
+                          double* var, const int32_t* out_row, hipStream_t st) {
   if (n_nodes == 0) return hipSuccess;
-  k_moments<<<n_nodes, 64, 0, st>>>(n_nodes, ld, S, q, mean, var);
+  k_moments<<<n_nodes, 64, 0, st>>>(n_nodes, ld, S, q, mean, var, out_row);
   return hipGetLastError();
 }
 

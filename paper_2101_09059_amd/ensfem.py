@@ -90,6 +90,7 @@ _SIGS = {
     "ens_read_qoi": (_I32, [_P, _I32, _P]),
     "ens_read_energy": (_I32, [_P, _I64, _P, _P, ctypes.POINTER(_I64)]),
     "ens_moments": (_I32, [_P, _P, _P]),
+    "ens_moments_noalloc": (_I32, [_P, _P, _P]),
     "ens_stress": (_I32, [_P, _P, _I32, _P]),
     "ens_stress_bands": (_I32, [_P, _P, _I32, _D, _D, _P, _P, _P]),
     "ens_apply": (_I32, [_P, _I32, _P, _P, _P]),
@@ -329,6 +330,18 @@ class Ensemble:
         mean = np.empty(self.n_nodes)
         var = np.empty(self.n_nodes)
         self._check(self._lib.ens_moments(self._h, _ptr(mean), _ptr(var)))
+        return mean, var
+
+    def moments_noalloc(self, mean=None, var=None):
+        """ens_moments_noalloc: the same per-node moments with the device
+        staging in the library's fixed scratch (nothing allocated on the
+        device; pass preallocated float64 arrays to allocate nothing here)."""
+        mean = np.empty(self.n_nodes) if mean is None else mean
+        var = np.empty(self.n_nodes) if var is None else var
+        for a in (mean, var):
+            if a.dtype != np.float64 or a.shape != (self.n_nodes,) or not a.flags.c_contiguous:
+                raise ValueError("moments_noalloc: outputs must be contiguous float64 arrays of n_nodes")
+        self._check(self._lib.ens_moments_noalloc(self._h, _ptr(mean), _ptr(var)))
         return mean, var
 
     def apply(self, U, R, prec: int = F64, stream=None):
