@@ -66,8 +66,13 @@ int32_t sur_set_weight_decay(sur_net* s, float wd);
 int32_t sur_train_step(sur_net* s, const float* X, const float* T, int32_t batch, float lr, float* loss,
                        void* stream);
 /* Sums of y and y^2 per output over M input rows X [M][n_in] (device),
- * evaluated in batches, never storing the M x n_out outputs; results to
- * host FP64 arrays [n_out].  Synchronizes. */
+ * results to host FP64 arrays [n_out]; the M x n_out outputs are never
+ * formed.  The output layer is linear (y = W h + b), so the rows only pass
+ * through the hidden layers (4,096 at a time), whose last activations give
+ * s = sum_r h_r and G = sum_r h_r h_r^T; then per output j
+ * sum y = w_j . s + M b_j and sum y^2 = w_j^T G w_j + 2 b_j w_j . s + M b_j^2
+ * (the same sums as a forward pass of every row, up to rounding).
+ * Synchronizes. */
 int32_t sur_moments(sur_net* s, const float* X, int64_t M, double* sum_host, double* sumsq_host,
                     void* stream);
 /* Squared error of the physical-unit predictions against targets:

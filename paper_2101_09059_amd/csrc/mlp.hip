@@ -12,9 +12,18 @@
 // multiplied), 4 waves of 64 x 64, each a 4 x 4 grid of 16x16x32 BF16 MFMAs.  The
 // operands may be K-contiguous or M/N-contiguous in global memory.
 // Epilogues: bias + GELU (forward hidden), bias (forward output), FP32
-// store with split-K partials (backward data / gradient check), per-column
-// sums of y and y^2 (moments over many draws without storing them), fused
+// store with split-K partials (backward data / gradient check, Gram
+// matrix), per-row quadratic form sum_n C(m, n) A(m, n) (moments), fused
 // Adam update (backward weights).  All reductions run in a fixed order.
+//
+// Moments over many draws: the output layer is linear, y_r = W h_r + b, so
+// per output j
+//   sum_r y_rj   = w_j . s + M b_j,                     s = sum_r h_r
+//   sum_r y_rj^2 = w_j^T G w_j + 2 b_j w_j . s + M b_j^2, G = sum_r h_r h_r^T
+// with h_r the last hidden layer's (BF16) activations: the draws only pass
+// through the hidden layers, and the output layer enters once, as the
+// product W G (G split into two BF16 parts for the matrix cores) and the
+// product W s in FP64.
 #include "ensfem.h"
 #include "ensfem_surrogate.h"
 
@@ -34,7 +43,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int BM = 128, BN = 128, BK = 32, LDS_STRIDE = BK + 8;
 
-enum Epi { EPI_F32 = 0, EPI_BIAS_GELU = 1, EPI_BIAS_F32 = 2, EPI_MOMENTS = 3, EPI_ADAM = 4 };
+enum Epi { EPI_F32 = 0, EPI_BIAS_GELU = 1, EPI_BIAS_F32 = 2, EPI_QUAD = 3, EPI_ADAM = 4 };
 
 struct GemmArgs {
   int M, N, K;
@@ -51,8 +60,7 @@ struct GemmArgs {
   const float* bias;
   float* Z32;
   __bf16* H16;
-  float* P1;
-  float* P2;  // [gridDim.y][N] per-row-block column sums
+  float* Q;  // EPI_QUAD: [column tiles][M] per-row partial sums
   float* W32;
   float* M1;
   float* M2;
@@ -181,47 +189,34 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     buf ^= 1;
   }
   // lane l of a 16x16 output tile holds rows 4*(l/16) + r, column l % 16
-  if constexpr (EPI == EPI_MOMENTS) {
-    __shared__ float red1[2][BN], red2[2][BN];
-    float s1[4], s2[4];
+  if constexpr (EPI == EPI_QUAD) {
+    // per row m: sum over this tile's columns n of C(m, n) A(m, n) (A the
+    // left operand itself, read again from global memory); lanes with the
+    // same l / 16 share rows, a fixed butterfly adds their columns, then the
+    // two column halves are added in wave order
+    __shared__ float redq[2][BM];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int n = n0 + wn * 64 + j * 16 + (l & 15);
-      const float bn = (n < g.N) ? g.bias[n] : 0.f;
-      float a1 = 0.f, a2 = 0.f;
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int r = 0; r < 4; ++r) {
+        const int ml = wm * 64 + i * 16 + 4 * (l >> 4) + r;
+        const int m = m0 + ml;
+        float a = 0.f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int m = m0 + wm * 64 + i * 16 + 4 * (l >> 4) + r;
-          if (m < g.M) {
-            const float y = acc[i][j][r] + bn;
-            a1 += y;
-            a2 = fmaf(y, y, a2);
-          }
+        for (int j = 0; j < 4; ++j) {
+          const int n = n0 + wn * 64 + j * 16 + (l & 15);
+          if (m < g.M && n < g.N) a = fmaf(acc[i][j][r], (float)g.A[(int64_t)m * g.a_sm + (int64_t)n * g.a_sk], a);
         }
-      // fixed butterfly over the 4 lane groups holding this column
-      a1 += __shfl_xor(a1, 16, 64);
-      a2 += __shfl_xor(a2, 16, 64);
-      a1 += __shfl_xor(a1, 32, 64);
-      a2 += __shfl_xor(a2, 32, 64);
-      s1[j] = a1;
-      s2[j] = a2;
-    }
-    if (l < 16) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        red1[wm][wn * 64 + j * 16 + l] = s1[j];
-        red2[wm][wn * 64 + j * 16 + l] = s2[j];
+        a += __shfl_xor(a, 1, 64);
+        a += __shfl_xor(a, 2, 64);
+        a += __shfl_xor(a, 4, 64);
+        a += __shfl_xor(a, 8, 64);
+        if ((l & 15) == 0) redq[wn][ml] = a;
       }
-    }
     __syncthreads();
-    if (threadIdx.x < BN) {
-      const int n = n0 + threadIdx.x;
-      if (n < g.N) {
-        g.P1[(int64_t)mtile * g.N + n] = red1[0][threadIdx.x] + red1[1][threadIdx.x];
-        g.P2[(int64_t)mtile * g.N + n] = red2[0][threadIdx.x] + red2[1][threadIdx.x];
-      }
+    if (threadIdx.x < BM) {
+      const int m = m0 + threadIdx.x;
+      if (m < g.M) g.Q[(int64_t)(n0 / BN) * g.M + m] = redq[0][threadIdx.x] + redq[1][threadIdx.x];
     }
   } else {
     // j innermost: consecutive accesses cover 64 consecutive columns of a row
@@ -240,7 +235,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
             g.C32[blockIdx.z * g.split_stride + idx] = v;
           } else if constexpr (EPI == EPI_BIAS_GELU) {
             const float z = v + g.bias[n];
-            g.Z32[idx] = z;
+            if (g.Z32) g.Z32[idx] = z;  // pre-activations are kept for training only
             g.H16[idx] = (__bf16)gelu_f(z);
           } else if constexpr (EPI == EPI_BIAS_F32) {
             g.C32[idx] = v + g.bias[n];
@@ -347,18 +342,81 @@ __global__ void k_adam_vec(int n, const float* __restrict__ g, float* __restrict
   w[t] = w[t] - lr * (a * c1) / (sqrtf(b * c2) + eps);
 }
 
-// moments partials [rb][N] -> running FP64 totals, row blocks in order
-__global__ void k_moment_accumulate(int rb, int N, const float* __restrict__ P1, const float* __restrict__ P2,
-                                    double* __restrict__ S1, double* __restrict__ S2) {
-  const int n = blockIdx.x * 256 + threadIdx.x;
-  if (n >= N) return;
-  double a = 0.0, b = 0.0;
-  for (int r = 0; r < rb; ++r) {
-    a += (double)P1[(int64_t)r * N + n];
-    b += (double)P2[(int64_t)r * N + n];
-  }
-  S1[n] += a;
-  S2[n] += b;
+__global__ void k_zero64(int64_t n, double* __restrict__ x) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t < n) x[t] = 0.0;
+}
+
+// Gram matrix update G += sum of the split-K partials [splits][n] (split
+// order), in FP64.
+__global__ void k_gram_acc(int64_t n, int splits, const float* __restrict__ part, double* __restrict__ G) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n) return;
+  double a = 0.0;
+  for (int z = 0; z < splits; ++z) a += (double)part[z * n + t];
+  G[t] += a;
+}
+
+// Column sums of H (BF16 [rows][cols]) in kColGroups row groups:
+// part[g][c] = sum over the rows of group g (in order).
+constexpr int kColGroups = 16;
+__global__ void k_colsum_part(int rows, int cols, const __bf16* __restrict__ H, double* __restrict__ part) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  const int g = blockIdx.y;
+  if (c >= cols) return;
+  const int per = (rows + kColGroups - 1) / kColGroups;
+  const int r1 = min(rows, (g + 1) * per);
+  double a = 0.0;
+  for (int r = g * per; r < r1; ++r) a += (double)(float)H[(int64_t)r * cols + c];
+  part[(int64_t)g * cols + c] = a;
+}
+
+// s[c] += the kColGroups partials of column c (group order).
+__global__ void k_colsum_acc(int cols, const double* __restrict__ part, double* __restrict__ s) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= cols) return;
+  double a = 0.0;
+  for (int g = 0; g < kColGroups; ++g) a += part[(int64_t)g * cols + c];
+  s[c] += a;
+}
+
+// G (FP64) = hi + lo with hi = bf16(G) and lo = bf16(G - hi).
+__global__ void k_split_hilo(int64_t n, const double* __restrict__ G, __bf16* __restrict__ hi,
+                             __bf16* __restrict__ lo) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n) return;
+  const __bf16 h = (__bf16)(float)G[t];
+  hi[t] = h;
+  lo[t] = (__bf16)(float)(G[t] - (double)(float)h);
+}
+
+// ws[j] = sum_k W[j][k] s[k] in FP64 (W BF16 [rows][K]); one wave per row,
+// lane-strided sums then a fixed butterfly.
+__global__ __launch_bounds__(256) void k_rowdot64(int rows, int K, const __bf16* __restrict__ W,
+                                                  const double* __restrict__ sv, double* __restrict__ ws) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int l = threadIdx.x & 63;
+  if (row >= rows) return;
+  const __bf16* w = W + (int64_t)row * K;
+  double a = 0.0;
+  for (int k = l; k < K; k += 64) a = fma((double)(float)w[k], sv[k], a);
+  for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+  if (l == 0) ws[row] = a;
+}
+
+// Output-layer moments from the hidden-layer sums: S1 = W s + M b,
+// S2 = w^T G w + 2 b (W s) + M b^2, the quadratic forms from the per-tile
+// partials of W G_hi and W G_lo (tile order).
+__global__ void k_moments_final(int n_out, int tiles, double M, const float* __restrict__ qhi,
+                                const float* __restrict__ qlo, const double* __restrict__ ws,
+                                const float* __restrict__ bias, double* __restrict__ S1, double* __restrict__ S2) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= n_out) return;
+  double q = 0.0;
+  for (int t = 0; t < tiles; ++t) q += (double)qhi[(int64_t)t * n_out + j] + (double)qlo[(int64_t)t * n_out + j];
+  const double b = (double)bias[j];
+  S1[j] = fma(M, b, ws[j]);
+  S2[j] = fma(M * b, b, fma(2.0 * b, ws[j], q));
 }
 
 // Squared error of the physical-unit predictions mu + sd y against Q over
@@ -451,6 +509,8 @@ __global__ void k_cv(int64_t n, int N, const double* __restrict__ qH, const doub
 
 inline unsigned blocks(int64_t n) { return (unsigned)((n + 255) / 256); }
 constexpr unsigned kLossParts = 2048;  // workgroups (and partial sums) of the loss
+constexpr int kMomRows = 4096;         // rows per pass of the moments
+constexpr int kGramSplits = 4;         // split-K partials of the Gram matrix
 
 }  // namespace
 
@@ -466,7 +526,8 @@ struct sur_net {
   char* ws = nullptr;
   size_t ws_bytes = 0;
   size_t o_p32 = 0, o_m1 = 0, o_m2 = 0, o_w16 = 0, o_h0 = 0, o_z = 0, o_h = 0, o_y = 0, o_dy16 = 0,
-         o_dh = 0, o_dz32 = 0, o_dz16 = 0, o_split = 0, o_db = 0, o_p1 = 0, o_p2 = 0, o_s1 = 0, o_s2 = 0,
+         o_dh = 0, o_dz32 = 0, o_dz16 = 0, o_split = 0, o_db = 0, o_mx = 0, o_ma = 0, o_mb = 0, o_gpart = 0,
+         o_g64 = 0, o_s64 = 0, o_cpart = 0, o_ghl = 0, o_qp = 0, o_ws = 0, o_s1 = 0, o_s2 = 0,
          o_lpart = 0, o_loss = 0, total = 0;
   int splits_max = 64;
   float wd = 0.0f;  // decoupled weight decay (weight matrices only)
@@ -520,9 +581,20 @@ void plan(sur_net* s) {
   s->o_dz16 = take(2 * B * W);
   s->o_split = take(4 * (size_t)s->splits_max * B * W);
   s->o_db = take(4 * std::max<size_t>(W, s->n_out));
-  const size_t rb = (B + BM - 1) / BM;
-  s->o_p1 = take(4 * rb * s->n_out);
-  s->o_p2 = take(4 * rb * s->n_out);
+  // moments: kMomRows rows per pass through the hidden layers (BF16 input
+  // and two activation buffers), the Gram matrix as split-K partials and in
+  // FP64, its BF16 halves, the quadratic-form partials of both halves, W s
+  const size_t C = kMomRows, nt = (W + BN - 1) / BN;
+  s->o_mx = take(2 * C * s->n_in);
+  s->o_ma = take(2 * C * W);
+  s->o_mb = take(2 * C * W);
+  s->o_gpart = take(4 * (size_t)kGramSplits * W * W);
+  s->o_g64 = take(8 * W * W);
+  s->o_s64 = take(8 * W);
+  s->o_cpart = take(8 * (size_t)kColGroups * W);
+  s->o_ghl = take(2 * 2 * W * W);
+  s->o_qp = take(4 * 2 * nt * (size_t)s->n_out);
+  s->o_ws = take(8 * (size_t)s->n_out);
   s->o_s1 = take(8 * (size_t)s->n_out);
   s->o_s2 = take(8 * (size_t)s->n_out);
   s->o_lpart = take(8 * (size_t)kLossParts);
@@ -870,25 +942,87 @@ int32_t sur_moments(sur_net* s, const float* X, int64_t M, double* sum_host, dou
   if (!s->have_params) return s->fail(ENS_ESTATE, "sur_moments: set the parameters first");
   SHIPC(hipSetDevice(s->device));
   hipStream_t st = static_cast<hipStream_t>(stream);
+  const int Wd = s->width, L = s->n_hidden, n_out = s->n_out;
+  const int64_t WW = (int64_t)Wd * Wd;
+  double* G = s->p<double>(s->o_g64);
+  double* sv = s->p<double>(s->o_s64);
+  SHIPC((k_zero64<<<blocks(WW), 256, 0, st>>>(WW, G), hipGetLastError()));
+  SHIPC((k_zero64<<<blocks(Wd), 256, 0, st>>>(Wd, sv), hipGetLastError()));
+  __bf16* buf[2] = {s->p<__bf16>(s->o_ma), s->p<__bf16>(s->o_mb)};
+  for (int64_t r0 = 0; r0 < M; r0 += kMomRows) {
+    const int rows = (int)std::min<int64_t>(kMomRows, M - r0);
+    // hidden layers (no pre-activations kept)
+    __bf16* X16 = s->p<__bf16>(s->o_mx);
+    SHIPC((k_to_bf16<<<blocks((int64_t)rows * s->n_in), 256, 0, st>>>((int64_t)rows * s->n_in,
+                                                                      X + r0 * s->n_in, X16),
+           hipGetLastError()));
+    const __bf16* Hin = X16;
+    for (int l = 0; l < L; ++l) {
+      const int in = s->fan_in[l], out = s->fan_out[l];
+      GemmArgs g = base_gemm(rows, out, in);
+      g.A = Hin;
+      g.a_sm = in;
+      g.a_sk = 1;
+      g.B = s->W16(l);
+      g.b_sk = 1;
+      g.b_sn = in;
+      g.vec_ok = (in % 8 == 0) && aligned16(g.A) && aligned16(g.B);
+      g.ldc = out;
+      g.bias = s->B32(l);
+      g.Z32 = nullptr;
+      g.H16 = buf[l & 1];
+      SHIPC((gemm<true, true, EPI_BIAS_GELU>(g, 1, st)));
+      Hin = g.H16;
+    }
+    // G += H^T H (split-K partials, then FP64 in split order), s += column sums
+    GemmArgs g = base_gemm(Wd, Wd, rows);
+    g.A = Hin;
+    g.a_sm = 1;
+    g.a_sk = Wd;
+    g.B = Hin;
+    g.b_sk = Wd;
+    g.b_sn = 1;
+    g.vec_ok = (Wd % 8 == 0) && aligned16(g.A);
+    g.k_chunk = ((rows + kGramSplits - 1) / kGramSplits + BK - 1) / BK * BK;
+    const int splits = (rows + g.k_chunk - 1) / g.k_chunk;
+    g.ldc = Wd;
+    g.split_stride = WW;
+    g.C32 = s->p<float>(s->o_gpart);
+    SHIPC((gemm<false, false, EPI_F32>(g, splits, st)));
+    SHIPC((k_gram_acc<<<blocks(WW), 256, 0, st>>>(WW, splits, g.C32, G), hipGetLastError()));
+    double* cpart = s->p<double>(s->o_cpart);
+    SHIPC((k_colsum_part<<<dim3(blocks(Wd), kColGroups), 256, 0, st>>>(rows, Wd, Hin, cpart), hipGetLastError()));
+    SHIPC((k_colsum_acc<<<blocks(Wd), 256, 0, st>>>(Wd, cpart, sv), hipGetLastError()));
+  }
+  // output layer: W G (both BF16 halves of G) as per-row quadratic forms,
+  // W s in FP64, then the sums
+  __bf16* Ghi = s->p<__bf16>(s->o_ghl);
+  __bf16* Glo = Ghi + WW;
+  SHIPC((k_split_hilo<<<blocks(WW), 256, 0, st>>>(WW, G, Ghi, Glo), hipGetLastError()));
+  const int nt = (Wd + BN - 1) / BN;
+  float* qp = s->p<float>(s->o_qp);
+  for (int half = 0; half < 2; ++half) {
+    GemmArgs g = base_gemm(n_out, Wd, Wd);
+    g.A = s->W16(L);
+    g.a_sm = Wd;
+    g.a_sk = 1;
+    g.B = half ? Glo : Ghi;  // symmetric: B(k, n) = G[n][k]
+    g.b_sk = 1;
+    g.b_sn = Wd;
+    g.vec_ok = (Wd % 8 == 0) && aligned16(g.A) && aligned16(g.B);
+    g.Q = qp + (int64_t)half * nt * n_out;
+    SHIPC((gemm<true, true, EPI_QUAD>(g, 1, st)));
+  }
+  double* ws = s->p<double>(s->o_ws);
+  SHIPC((k_rowdot64<<<(unsigned)((n_out + 3) / 4), 256, 0, st>>>(n_out, Wd, s->W16(L), sv, ws), hipGetLastError()));
   double* S1 = s->p<double>(s->o_s1);
   double* S2 = s->p<double>(s->o_s2);
-  SHIPC(hipMemsetAsync(S1, 0, 8 * (size_t)s->n_out, st));
-  SHIPC(hipMemsetAsync(S2, 0, 8 * (size_t)s->n_out, st));
-  for (int64_t r0 = 0; r0 < M; r0 += s->max_batch) {
-    const int batch = (int)std::min<int64_t>(s->max_batch, M - r0);
-    int32_t rc = forward_hidden(s, X + r0 * s->n_in, batch, st);
-    if (rc != ENS_OK) return rc;
-    GemmArgs g = output_gemm(s, batch);
-    g.P1 = s->p<float>(s->o_p1);
-    g.P2 = s->p<float>(s->o_p2);
-    SHIPC((gemm<true, true, EPI_MOMENTS>(g, 1, st)));
-    const int rb = (batch + BM - 1) / BM;
-    SHIPC((k_moment_accumulate<<<blocks(s->n_out), 256, 0, st>>>(rb, s->n_out, g.P1, g.P2, S1, S2),
-           hipGetLastError()));
-  }
+  SHIPC((k_moments_final<<<blocks(n_out), 256, 0, st>>>(n_out, nt, (double)M, qp, qp + (int64_t)nt * n_out, ws,
+                                                        s->B32(L), S1, S2),
+         hipGetLastError()));
   SHIPC(hipStreamSynchronize(st));
-  SHIPC(hipMemcpy(sum_host, S1, 8 * (size_t)s->n_out, hipMemcpyDeviceToHost));
-  SHIPC(hipMemcpy(sumsq_host, S2, 8 * (size_t)s->n_out, hipMemcpyDeviceToHost));
+  SHIPC(hipMemcpy(sum_host, S1, 8 * (size_t)n_out, hipMemcpyDeviceToHost));
+  SHIPC(hipMemcpy(sumsq_host, S2, 8 * (size_t)n_out, hipMemcpyDeviceToHost));
   return ENS_OK;
 }
 

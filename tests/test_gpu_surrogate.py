@@ -107,7 +107,7 @@ def test_adam_step_matches_oracle(wd):
     net.close()
 
 
-def test_moments_epilogue_matches_explicit_forward():
+def test_moments_match_explicit_forward():
     sizes = [128, 128, 128, 777]
     params = _net(sizes, seed=5)
     rng = np.random.default_rng(4)
@@ -119,6 +119,29 @@ def test_moments_epilogue_matches_explicit_forward():
     Y = torch.cat([net.forward(X[i:i + 256]) for i in range(0, M, 256)]).double().cpu().numpy()
     assert np.allclose(s1, Y.sum(0), rtol=1e-5, atol=1e-5 * np.abs(Y).sum(0).max())
     assert np.allclose(s2, (Y * Y).sum(0), rtol=1e-5)
+    net.close()
+
+
+@pytest.mark.parametrize("sizes,M", [([24, 72, 72, 150], 5000), ([128, 256, 256, 256, 1000], 4500),
+                                     ([16, 60, 130], 300)])
+def test_moments_match_oracle(sizes, M):
+    """sur_moments (hidden layers per pass of 4,096 rows, the output layer
+    through the first and second moments of the last hidden layer) against
+    the oracle's explicit forward of every row, summed in FP64: two passes
+    with a ragged tail, ragged tiles, a width that is not a multiple of 8."""
+    say(f"case: surrogate moments sizes={sizes} M={M}")
+    params = _net(sizes, seed=len(sizes) + M)
+    rng = np.random.default_rng(12)
+    X = bf16_round(rng.standard_normal((M, sizes[0])))
+    net = ensfem.Surrogate(sizes[0], sizes[1], len(sizes) - 2, sizes[-1], max_batch=64)
+    net.set_params(ensfem.flatten_params(params))
+    s1, s2 = net.moments(torch.as_tensor(X, dtype=torch.float32, device="cuda"))
+    Y, _ = mlp.forward([(W, b.astype(np.float32).astype(np.float64)) for W, b in params], X)
+    r1, r2, a1 = Y.sum(0), (Y * Y).sum(0), np.abs(Y).sum(0)
+    e1 = np.linalg.norm(s1 - r1) / np.linalg.norm(a1)
+    e2 = np.linalg.norm(s2 - r2) / np.linalg.norm(r2)
+    say(f"  sum y: err {e1:.2e} of the sum of |y|; sum y^2: rel err {e2:.2e}")
+    assert e1 < 2e-2 and e2 < 4e-2
     net.close()
 
 
