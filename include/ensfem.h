@@ -193,7 +193,9 @@ int32_t ens_cfl_dt(ens_ctx* ctx, double safety, double* dt_out);
  * first ens_step, when dt is known. */
 int32_t ens_init_state(ens_ctx* ctx, const double* u0, const double* v0);
 
-/* Enqueue n_steps explicit steps of size dt on `stream` (hipStream_t).  dt
+/* Enqueue n_steps explicit steps of size dt on `stream` (hipStream_t); runs
+ * without energy records or geometry refresh go in replays of a captured
+ * graph of 64 steps (same kernels, same results as direct launches).  dt
  * is fixed by the first call after ens_init_state (which also forms the
  * starter, even with n_steps = 0); later calls must pass the same value
  * (ENS_EINVAL otherwise).  ENS_EUNSTABLE if dt exceeds the
@@ -201,7 +203,14 @@ int32_t ens_init_state(ens_ctx* ctx, const double* u0, const double* v0);
  * mesh, ensemble, load, state or workspace is missing. */
 int32_t ens_step(ens_ctx* ctx, int64_t n_steps, double dt, int32_t force, void* stream);
 
-/* Wait for the context's work; ENS_ENONFINITE if the state holds NaN/Inf. */
+/* Wait for the context's work; ENS_ENONFINITE if the state holds NaN/Inf.
+ * With energy records on (energy_every > 0) every record also runs the
+ * energy watchdog: the discrete energy of a stable central-difference step
+ * is at least (1 - s^2) times its kinetic part, s = dt omega_hat / 2 from
+ * the stability bound (capped at 0.999 for a forced step), in any state; a
+ * record that breaks this marks the run unstable and ens_sync returns
+ * ENS_EUNSTABLE (until ens_init_state or ens_load).  Nothing is checked
+ * without energy records. */
 int32_t ens_sync(ens_ctx* ctx);
 
 /* Read-backs into caller-owned host buffers (synchronizing):
@@ -287,6 +296,8 @@ typedef struct {
   int32_t grid;             /* persistent workgroups per launch, 0 = one
                                workgroup per tile                        */
   int32_t graph_steps;      /* steps per captured graph                  */
+  int32_t launches_per_step; /* 1, or 2 when the two lane classes are
+                                launched separately                      */
   double tuned_ms_per_step; /* best autotuner trial, 0 before autotune   */
 } ens_batch_info_t;
 
@@ -299,8 +310,11 @@ int32_t ens_batch_info(ens_batch* b, ens_batch_info_t* out);
  * bitwise those of stepping each context alone. */
 int32_t ens_batch_step(ens_batch* b, int64_t n_steps, void* stream);
 /* Times trial_steps steps for each candidate tiling (samples per lane 1 or
- * 2, 4/8/16 nodes per tile, 4 or 8 persistent workgroups per compute unit
- * or one workgroup per tile) and keeps the fastest.  The trial steps ADVANCE every context's state: re-init the
+ * 2 -- with 2, a mesh whose padded width is an odd multiple of 64 has a
+ * last block of 64 samples, run on half waves in the same launch or in a
+ * second launch per step --, 4/8/16 nodes per tile, 4 or 8 persistent
+ * workgroups per compute unit or one workgroup per tile) and keeps the
+ * fastest.  The trial steps ADVANCE every context's state: re-init the
  * states afterwards to restart from the initial condition. */
 int32_t ens_batch_autotune(ens_batch* b, int32_t trial_steps);
 

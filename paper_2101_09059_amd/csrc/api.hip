@@ -51,6 +51,8 @@ void* scratch_ptr(int device) {
 
 constexpr size_t kAlign = 256;
 constexpr int kChunk = 1024;  // steps per load-factor table
+constexpr int kGraphSteps = 64;  // steps per captured graph (even: keeps the state parity)
+static_assert(kGraphSteps % 2 == 0 && kGraphSteps <= kChunk, "graph chunk");
 
 size_t align_up(size_t x) { return (x + kAlign - 1) & ~(kAlign - 1); }
 
@@ -64,6 +66,8 @@ struct Layout {
 struct Flags {  // small device scalars
   int32_t bad;
   int32_t nonfinite;
+  int32_t unstable;  // energy watchdog fired since the state was set
+  int32_t pad_;
   unsigned long long omega2_bits;
 };
 
@@ -121,6 +125,24 @@ struct ens_ctx {
   std::vector<int64_t> energy_steps;
   hipStream_t last_stream = nullptr;
   uint64_t gen = 0;  // bumped by every change a captured step graph depends on
+  // captured chunk of kGraphSteps plain steps (no energy records, reference
+  // geometry), valid for the generation and state parity it was taken at
+  hipStream_t cap_st = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t graph_gen = 0;
+  int graph_cur = -1;
+
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
+  ~ens_ctx() {
+    drop_graph();
+    if (cap_st) (void)hipStreamDestroy(cap_st);
+  }
 
   template <class T>
   T* p(size_t off) const { return reinterpret_cast<T*>(ws + off); }
@@ -203,6 +225,7 @@ Layout plan(const ens_ctx* c) {
   L.fixed = take(nn);
   L.radial = take(sizeof(double) * 3 * nn);
   L.perm = take(sizeof(int32_t) * nn);
+
   L.F = take(sizeof(double) * 3 * nn);
   L.eh64 = take(sizeof(double) * ne * ld);
   L.eh32 = take(sizeof(float) * ne * ld);
@@ -234,7 +257,9 @@ Layout plan(const ens_ctx* c) {
   L.q = take(sizeof(double) * nn * ld);
   L.qmask = take(sizeof(uint64_t) * nn * ((ld + 63) / 64));
   const int64_t n_nb = (nn + nodes_per_block(c->SB) - 1) / nodes_per_block(c->SB);
-  L.epart = take(sizeof(double) * (n_nb + 256) * ld);
+  // energy partials, then the second-level rows of the energy and of the
+  // kinetic energy (256 each) and the kinetic energy row of the watchdog
+  L.epart = take(sizeof(double) * (n_nb + 2 * 256 + 1) * ld);
   L.erec = take(sizeof(double) * kEnergyCap * ld);
   L.gtab = take(sizeof(double) * kChunk);
   L.base = take(sizeof(int64_t));
@@ -246,6 +271,36 @@ Layout plan(const ens_ctx* c) {
   if (c->qoi_mask & ENS_QOI_STRESS) L.stress = take(sizeof(double) * (ne * ld + 6 * ne));
   L.total = off;
   return L;
+}
+
+// Block rows for the shared-stiffness variant: per node the sorted distinct
+// neighbours, and per adjacency entry the block slots of its b and c.
+void build_block_rows(ens_ctx* c) {
+  const int64_t nn = c->n_nodes, ne = c->n_el;
+  c->bsr_ptr.assign(nn + 1, 0);
+  c->bsr_col.clear();
+  c->adj_slot.resize(3 * ne);
+  std::vector<int32_t> cols;
+  for (int64_t i = 0; i < nn; ++i) {
+    cols.clear();
+    for (int32_t k = c->adj_ptr[i]; k < c->adj_ptr[i + 1]; ++k) {
+      const int2 v = c->adj_nb[k];
+      cols.push_back(v.x < 0 ? ~v.x : v.x);
+      cols.push_back(v.y);
+    }
+    std::sort(cols.begin(), cols.end());
+    cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
+    const int32_t base = (int32_t)c->bsr_col.size();
+    c->bsr_col.insert(c->bsr_col.end(), cols.begin(), cols.end());
+    c->bsr_ptr[i + 1] = (int32_t)c->bsr_col.size();
+    for (int32_t k = c->adj_ptr[i]; k < c->adj_ptr[i + 1]; ++k) {
+      const int2 v = c->adj_nb[k];
+      const int32_t b = v.x < 0 ? ~v.x : v.x;
+      const int32_t sb = base + (int32_t)(std::lower_bound(cols.begin(), cols.end(), b) - cols.begin());
+      const int32_t sc = base + (int32_t)(std::lower_bound(cols.begin(), cols.end(), v.y) - cols.begin());
+      c->adj_slot[k] = make_int2(sb, sc);
+    }
+  }
 }
 
 // Node-gather adjacency.  Each node's incident elements are ordered as a
@@ -315,29 +370,16 @@ void build_adjacency(ens_ctx* c) {
     }
   }
   // block rows for the shared-stiffness variant: sorted distinct neighbours
-  c->bsr_ptr.assign(nn + 1, 0);
-  c->bsr_col.clear();
-  c->adj_slot.resize(3 * ne);
-  std::vector<int32_t> cols;
-  for (int64_t i = 0; i < nn; ++i) {
-    cols.clear();
-    for (int32_t k = c->adj_ptr[i]; k < c->adj_ptr[i + 1]; ++k) {
-      const int2 v = c->adj_nb[k];
-      cols.push_back(v.x < 0 ? ~v.x : v.x);
-      cols.push_back(v.y);
-    }
-    std::sort(cols.begin(), cols.end());
-    cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
-    const int32_t base = (int32_t)c->bsr_col.size();
-    c->bsr_col.insert(c->bsr_col.end(), cols.begin(), cols.end());
-    c->bsr_ptr[i + 1] = (int32_t)c->bsr_col.size();
-    for (int32_t k = c->adj_ptr[i]; k < c->adj_ptr[i + 1]; ++k) {
-      const int2 v = c->adj_nb[k];
-      const int32_t b = v.x < 0 ? ~v.x : v.x;
-      const int32_t sb = base + (int32_t)(std::lower_bound(cols.begin(), cols.end(), b) - cols.begin());
-      const int32_t sc = base + (int32_t)(std::lower_bound(cols.begin(), cols.end(), v.y) - cols.begin());
-      c->adj_slot[k] = make_int2(sb, sc);
-    }
+  build_block_rows(c);
+  // an entry that closes a node's fan (its second neighbour is the first
+  // entry's first one, the walk having reused every neighbour in between)
+  // names it as ~c: the kernel takes it from registers
+  for (int64_t i = 0; i < nn && ENSFEM_CLOSE_REUSE; ++i) {
+    const int32_t b0 = c->adj_ptr[i], b1 = c->adj_ptr[i + 1];
+    if (b1 - b0 < 3) continue;
+    bool chain = true;
+    for (int32_t t = b0 + 1; t < b1; ++t) chain = chain && c->adj_nb[t].x < 0;
+    if (chain && c->adj_nb[b1 - 1].y == c->adj_nb[b0].x) c->adj_nb[b1 - 1].y = ~c->adj_nb[b1 - 1].y;
   }
 }
 
@@ -465,6 +507,7 @@ int32_t upload_all(ens_ctx* ctx) {
   HIPC(hipMemcpy(ctx->p<void>(L.fixed), ctx->fixed.data(), nn, hipMemcpyHostToDevice));
   HIPC(hipMemcpy(ctx->p<void>(L.radial), ctx->radial.data(), sizeof(double) * 3 * nn, hipMemcpyHostToDevice));
   HIPC(hipMemcpy(ctx->p<void>(L.perm), ctx->perm.data(), sizeof(int32_t) * nn, hipMemcpyHostToDevice));
+
   if (ctx->have_load)
     HIPC(hipMemcpy(ctx->p<void>(L.F), ctx->F.data(), sizeof(double) * 3 * nn, hipMemcpyHostToDevice));
   else
@@ -809,6 +852,7 @@ int32_t ens_init_state(ens_ctx* ctx, const double* u0, const double* v0) {
   GUARD_BEGIN
   if (!ctx->bound) return ctx->fail(ENS_EWORKSPACE, "ens_init_state: bind a workspace first");
   const Layout& L = ctx->L;
+  HIPC(hipMemset(&ctx->p<Flags>(L.flags)->unstable, 0, sizeof(int32_t)));
   const int64_t ndof = 3 * ctx->n_nodes, ld = ctx->ld, n = ndof * ld;
   std::vector<double> buf;
   hipStream_t st = nullptr;
@@ -964,6 +1008,41 @@ int32_t ens_step(ens_ctx* ctx, int64_t n_steps, double dt, int32_t force, void* 
     ctx->gen++;
   }
   int64_t left = n_steps;
+  // plain steps go in replays of a captured graph of kGraphSteps steps
+  // (load-factor table, the steps, the step counter): the same kernels with
+  // the same arguments as the direct launches below
+  if (!geom && ctx->energy_every == 0 && left >= kGraphSteps) {
+    if (ctx->exec && (ctx->graph_gen != ctx->gen || ctx->graph_cur != ctx->cur)) ctx->drop_graph();
+    if (!ctx->exec) {
+      if (!ctx->cap_st) HIPC(hipStreamCreateWithFlags(&ctx->cap_st, hipStreamNonBlocking));
+      HIPC(hipStreamBeginCapture(ctx->cap_st, hipStreamCaptureModeThreadLocal));
+      hipError_t e = launch_schedule(ctx->p<double>(L.gtab), ctx->p<int64_t>(L.base), kGraphSteps, dt,
+                                     ctx->sched, ctx->cap_st);
+      for (int j = 0; j < kGraphSteps && e == hipSuccess; ++j) {
+        a.j = j;
+        a.refresh = 0;
+        set_state_ptrs(ctx, a, j & 1);
+        e = launch_step(a, f32, ctx->state_prec, ctx->SB, qoi, false, use_shared(ctx), ctx->cap_st);
+      }
+      if (e == hipSuccess) e = launch_advance(ctx->p<int64_t>(L.base), kGraphSteps, ctx->cap_st);
+      hipGraph_t g = nullptr;
+      const hipError_t e2 = hipStreamEndCapture(ctx->cap_st, &g);
+      if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return ctx->fail(ENS_EDEVICE, std::string("ens_step: graph capture: ") +
+                                          hipGetErrorString(e != hipSuccess ? e : e2));
+      }
+      ctx->graph = g;
+      HIPC(hipGraphInstantiate(&ctx->exec, ctx->graph, nullptr, nullptr, 0));
+      ctx->graph_gen = ctx->gen;
+      ctx->graph_cur = ctx->cur;
+    }
+    while (left >= kGraphSteps) {
+      HIPC(hipGraphLaunch(ctx->exec, st));
+      ctx->steps += kGraphSteps;
+      left -= kGraphSteps;
+    }
+  }
   while (left > 0) {
     const int k = (int)std::min<int64_t>(left, kChunk);
     HIPC(launch_schedule(ctx->p<double>(L.gtab), ctx->p<int64_t>(L.base), k, dt, ctx->sched, st));
@@ -984,6 +1063,26 @@ int32_t ens_step(ens_ctx* ctx, int64_t n_steps, double dt, int32_t force, void* 
         const int64_t rec = ctx->energy_records % kEnergyCap;
         HIPC(launch_energy_reduce(ctx->p<double>(L.epart), a.n_nb, ctx->ld, ctx->ld,
                                   ctx->p<double>(L.erec) + rec * ctx->ld, st));
+        // watchdog: with omega_hat the stability bound's frequency and
+        // s = omega_hat dt / 2 < 1, the discrete energy E_{n+1/2} is at least
+        // (1 - s^2) times its kinetic part in any state (per mode
+        // E = m/(2 dt^2) [(1 - W^2/4)(u_{n+1} - u_n)^2 + (W^2/4)(u_{n+1} + u_n)^2],
+        // W = omega dt <= 2 s); a step that is not stable lets the kinetic
+        // part grow while E stays bounded
+        const double s_bound = std::min(0.5 * dt * std::sqrt(ctx->omega2), 0.999);
+        const double coef = (1.0 - s_bound * s_bound) / 1.01;
+        double* epart = ctx->p<double>(L.epart);
+        double* ktmp = epart + (int64_t)(a.n_nb + 256) * ctx->ld;
+        double* krow = epart + (int64_t)(a.n_nb + 512) * ctx->ld;
+        Flags* fl = ctx->p<Flags>(L.flags);
+        if (ctx->state_prec == ENS_STATE_F64)
+          HIPC(launch_kinetic((int32_t)ctx->n_nodes, ctx->ld, ctx->S, ctx->p<double>(L.u[1 - ctx->cur]),
+                              ctx->p<double>(L.u[ctx->cur]), nullptr, ctx->p<double>(L.minv64), dt, ktmp, krow,
+                              ctx->p<double>(L.erec) + rec * ctx->ld, coef, &fl->unstable, st));
+        else
+          HIPC(launch_kinetic((int32_t)ctx->n_nodes, ctx->ld, ctx->S, nullptr, nullptr, ctx->p<float>(L.v),
+                              ctx->p<double>(L.minv64), dt, ktmp, krow, ctx->p<double>(L.erec) + rec * ctx->ld,
+                              coef, &fl->unstable, st));
         ctx->energy_steps[rec] = n;
         ctx->energy_records++;
       }
@@ -1010,9 +1109,12 @@ int32_t ens_sync(ens_ctx* ctx) {
     HIPC(launch_check_finite(n, ctx->p<double>(L.u[ctx->cur]), 0, &fl->nonfinite, nullptr));
   else
     HIPC(launch_check_finite(n, ctx->p<float>(L.uh[ctx->cur]), 1, &fl->nonfinite, nullptr));
-  int32_t bad = 0;
-  HIPC(hipMemcpy(&bad, &fl->nonfinite, sizeof(int32_t), hipMemcpyDeviceToHost));
-  if (bad) return ctx->fail(ENS_ENONFINITE, "ens_sync: non-finite values in the displacement state");
+  int32_t flags[2] = {0, 0};  // nonfinite, unstable
+  HIPC(hipMemcpy(flags, &fl->nonfinite, sizeof flags, hipMemcpyDeviceToHost));
+  if (flags[1])
+    return ctx->fail(ENS_EUNSTABLE, "ens_sync: energy watchdog: the kinetic energy of a sample exceeded what a "
+                                    "stable step allows for its discrete energy (the step is unstable)");
+  if (flags[0]) return ctx->fail(ENS_ENONFINITE, "ens_sync: non-finite values in the displacement state");
   return ENS_OK;
 }
 
@@ -1331,6 +1433,7 @@ int32_t ens_load(ens_ctx* ctx, const void* host, size_t bytes) {
   HIPC(hipMemcpy(ctx->p<void>(L.q), o, sizeof(double) * nq, hipMemcpyHostToDevice));
   HIPC(hipMemcpy(ctx->p<void>(L.base), &hd.steps, sizeof(int64_t), hipMemcpyHostToDevice));
   HIPC(hipMemset(ctx->p<void>(L.qmask), 0, sizeof(uint64_t) * ctx->n_nodes * ((ctx->ld + 63) / 64)));
+  HIPC(hipMemset(&ctx->p<Flags>(L.flags)->unstable, 0, sizeof(int32_t)));
   HIPC(hipDeviceSynchronize());
   ctx->steps = hd.steps;
   ctx->started = hd.started != 0;
@@ -1389,6 +1492,7 @@ struct ens_batch {
   BatchTile* d_tiles = nullptr;
   int32_t n_tiles = 0, n_wide = 0;  // tiles [0, n_wide) have 2 samples per lane
   bool one_per_tile = false;        // grid = one workgroup per tile
+  bool split = false;               // spl = 2: one launch per lane class instead of one per step
   size_t tiles_cap = 0;
   StepArgs* d_desc = nullptr;
   std::vector<int> desc_cur;
@@ -1494,14 +1598,21 @@ int32_t enqueue_steps(ens_batch* b, int64_t k_total) {
     const int k = (int)std::min<int64_t>(k_total - done, kChunk);
     for (ens_ctx* c : b->ctx)
       BHIPC(launch_schedule(c->p<double>(c->L.gtab), c->p<int64_t>(c->L.base), k, c->dt, c->sched, b->st));
-    for (int j = 0; j < k; ++j)
-      for (int cls = 0; cls < 2; ++cls) {
-        const int32_t first = cls == 0 ? 0 : b->n_wide;
-        const int32_t count = cls == 0 ? b->n_wide : b->n_tiles - b->n_wide;
-        const int grid = b->one_per_tile ? (int)((count + 7) / 8 * 8) : b->grid;
-        BHIPC(launch_batch_step(b->d_tiles + first, count, cls == 0 ? 2 : 1, b->d_desc, j, b->apply_f32,
-                                b->mode, b->qoi, grid, b->st));
+    // one launch per step covers both lane classes (the 64-sample blocks on
+    // half waves), or, split, one launch per class
+    auto grid_of = [&](int32_t n) { return b->one_per_tile ? (int)((n + 7) / 8 * 8) : b->grid; };
+    const int32_t n_narrow = b->n_tiles - b->n_wide;
+    for (int j = 0; j < k; ++j) {
+      if (b->split && b->n_wide > 0 && n_narrow > 0) {
+        BHIPC(launch_batch_step(b->d_tiles, b->n_wide, b->n_wide, 2, b->d_desc, j, b->apply_f32, b->mode, b->qoi,
+                                grid_of(b->n_wide), b->st));
+        BHIPC(launch_batch_step(b->d_tiles + b->n_wide, n_narrow, 0, 1, b->d_desc, j, b->apply_f32, b->mode,
+                                b->qoi, grid_of(n_narrow), b->st));
+      } else {
+        BHIPC(launch_batch_step(b->d_tiles, b->n_tiles, b->n_wide, b->n_wide > 0 ? 2 : 1, b->d_desc, j,
+                                b->apply_f32, b->mode, b->qoi, grid_of(b->n_tiles), b->st));
       }
+    }
     for (ens_ctx* c : b->ctx) BHIPC(launch_advance(c->p<int64_t>(c->L.base), k, b->st));
     done += k;
   }
@@ -1602,6 +1713,7 @@ int32_t ens_batch_info(ens_batch* b, ens_batch_info_t* out) {
   out->tile_nodes = b->tile_nodes;
   out->grid = b->one_per_tile ? 0 : b->grid;
   out->graph_steps = b->graph_k;
+  out->launches_per_step = (b->split && b->n_wide > 0 && b->n_wide < b->n_tiles) ? 2 : 1;
   out->tuned_ms_per_step = b->tuned_ms;
   return ENS_OK;
 }
@@ -1625,7 +1737,7 @@ int32_t ens_batch_step(ens_batch* b, int64_t n_steps, void* stream) {
     }
     std::vector<uint64_t> gen(b->ctx.size());
     for (size_t m = 0; m < b->ctx.size(); ++m) gen[m] = b->ctx[m]->gen;
-    const int sig[3] = {b->spl, b->tile_nodes, b->one_per_tile ? -1 : b->grid};
+    const int sig[3] = {b->spl * (b->split ? -1 : 1), b->tile_nodes, b->one_per_tile ? -1 : b->grid};
     if (b->exec && (gen != b->graph_gen || std::memcmp(sig, b->graph_sig, sizeof sig) != 0)) drop_graph(b);
     int64_t left = n_steps;
     if (left >= b->graph_k) {
@@ -1676,10 +1788,12 @@ int32_t ens_batch_autotune(ens_batch* b, int32_t trial_steps) {
     BHIPC(hipEventCreate(&e1));
     double best = 1e300;
     int bs = b->spl, bt = b->tile_nodes, bg = b->grid;
-    int bone = b->one_per_tile ? 1 : 0;
-    for (int spl : {1, 2}) {
+    int bone = b->one_per_tile ? 1 : 0, bsplit = b->split ? 1 : 0;
+    for (int mode : {1, 2, 3}) {  // 1: one sample per lane; 2: two, one launch; 3: two, a launch per class
+      const int spl = mode == 1 ? 1 : 2;
       for (int tn : {4, 8, 16}) {
         for (int gm : {0, 4, 8}) {  // 0: one workgroup per tile
+          b->split = mode == 3;
           b->spl = spl;
           b->tile_nodes = tn;
           b->one_per_tile = gm == 0;
@@ -1704,6 +1818,7 @@ int32_t ens_batch_autotune(ens_batch* b, int32_t trial_steps) {
             bt = tn;
             bg = b->grid;
             bone = gm == 0 ? 1 : 0;
+            bsplit = mode == 3 ? 1 : 0;
           }
           if (trial_steps & 1) build_desc(b);
         }
@@ -1718,6 +1833,7 @@ int32_t ens_batch_autotune(ens_batch* b, int32_t trial_steps) {
     b->tile_nodes = bt;
     b->grid = bg;
     b->one_per_tile = bone != 0;
+    b->split = bsplit != 0;
     b->tuned_ms = best;
     rc = build_tiles(b);
     if (rc != ENS_OK) return rc;

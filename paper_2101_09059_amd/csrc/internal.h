@@ -12,6 +12,11 @@
 namespace ensfem {
 
 constexpr int kBlock = 256;       // threads per workgroup for the ensemble kernels
+// The element that closes a node's fan takes the walk's first neighbour
+// from registers instead of loading it again (host marking and kernels).
+#ifndef ENSFEM_CLOSE_REUSE
+#define ENSFEM_CLOSE_REUSE 1
+#endif
 constexpr int kEnergyCap = 4096;  // energy records kept (ring)
 
 // Device arrays referenced from argument structs are global memory; the
@@ -34,7 +39,8 @@ struct Schedule {
 // one per incident element e, with the element's other two nodes (b, c) in
 // cyclic order after i and the 3x6 block [Khat_ib | Khat_ic] (global frame).
 // Entries walk around the node; nb.x < 0 (stored as ~b) marks an entry whose
-// b is the previous entry's c.
+// b is the previous entry's c, nb.y < 0 (stored as ~c) the last entry of a
+// closed fan, whose c is the first entry's b.
 struct Adjacency {
   ENS_GLOBAL const int32_t* ptr;
   ENS_GLOBAL const int32_t* el;
@@ -146,6 +152,13 @@ hipError_t launch_schedule(double* gtab, int64_t* base, int32_t k, double dt, Sc
                            hipStream_t st);
 hipError_t launch_copy_f64(int64_t n, const double* src, double* dst, hipStream_t st);
 hipError_t launch_advance(int64_t* base, int32_t k, hipStream_t st);
+// Energy watchdog of one record: T_s = sum over nodes of 1/2 m |v|^2 per
+// sample (v = (u_next - u_cur) / dt for the FP64 state, the stored velocity
+// otherwise), through chunk partials in tmp [256][ld] into krow [S]; then
+// *flag = 1 if coef T_s > E_s + 1e-12 T_s for some sample (E_s = erow[s]).
+hipError_t launch_kinetic(int32_t n_nodes, int32_t ld, int32_t S, const double* u_next, const double* u_cur,
+                          const float* vel, const double* minv, double dt, double* tmp, double* krow,
+                          const double* erow, double coef, int32_t* flag, hipStream_t st);
 hipError_t launch_energy_reduce(const double* part, int32_t n_nb, int32_t ld, int32_t S,
                                 double* out_row, hipStream_t st);
 hipError_t launch_starter_f64(int32_t n_nodes, int32_t ld, const double* R, const double* minv,
@@ -158,8 +171,10 @@ hipError_t launch_starter_f32(int32_t n_nodes, int32_t ld, const float* R, const
 hipError_t launch_split_f32(int64_t n, const double* u0, float* uh, float* uc, hipStream_t st);
 hipError_t launch_qoi_init(int32_t n_nodes, int32_t ld, const double* radial, const double* u_f64,
                            const float* uh, const float* uc, double* q, hipStream_t st);
-hipError_t launch_batch_step(const BatchTile* tiles, int32_t n_tiles, int spl, const StepArgs* desc, int32_t j,
-                             bool apply_f32, int mode, bool qoi, int grid, hipStream_t st);
+// spl samples per lane; with spl = 2, tiles [n_wide, n_tiles) are 64-sample
+// blocks run on half a wave
+hipError_t launch_batch_step(const BatchTile* tiles, int32_t n_tiles, int32_t n_wide, int spl, const StepArgs* desc,
+                             int32_t j, bool apply_f32, int mode, bool qoi, int grid, hipStream_t st);
 hipError_t launch_qoi_resolve(int32_t n_nodes, int32_t ld, int sample_block, const double* radial,
                               const double* u_f64, const float* uh, const float* uc, double* q,
                               const uint64_t* qmask, hipStream_t st);

@@ -29,6 +29,15 @@
 #ifndef ENSFEM_GATHER_UNROLL
 #define ENSFEM_GATHER_UNROLL 2
 #endif
+// Closing-element reuse in the stand-alone apply (its 4 samples per lane
+// already need many registers).
+#ifndef ENSFEM_APPLY_CLOSE
+#define ENSFEM_APPLY_CLOSE 1
+#endif
+// Minimum waves per SIMD the step kernels are compiled for.
+#ifndef ENSFEM_STEP_MIN_WAVES
+#define ENSFEM_STEP_MIN_WAVES 1
+#endif
 // Issue the node's single-use loads (u_{n-1}, 1/m) before the gather so
 // they are in flight during it (FP64 state).
 #ifndef ENSFEM_HOIST_STREAMS
@@ -173,10 +182,14 @@ __device__ __forceinline__ int64_t node_row(const int32_t* __restrict__ map, int
 }
 
 // R for one node and SPL consecutive samples starting at s0.
-template <typename AT, typename ST, int SPL, bool UNI, bool MAP = false>
+// CLOSE: the element that closes a node's fan takes the walk's first
+// neighbour from registers (worth its registers in the FP32 apply of the
+// single-mesh kernels); otherwise the closing entry is loaded again.
+template <typename AT, typename ST, int SPL, bool UNI, bool MAP = false, bool CLOSE = true>
 __device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_t ld, int s0,
                                              const ST* __restrict__ U, const ST (&ua)[3][SPL],
                                              AT (&r)[3][SPL], const int32_t* __restrict__ map = nullptr) {
+  constexpr bool kClose = CLOSE && ENSFEM_CLOSE_REUSE && std::is_same<AT, float>::value;
   const int kb = maybe_uni<UNI>(cst(p.adj.ptr)[node]);
   const int ke = maybe_uni<UNI>(cst(p.adj.ptr)[node + 1]);
   const ConstPtr<AT> KB = (ConstPtr<AT>)cst(p.adj.k);
@@ -186,6 +199,7 @@ __device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_
 #pragma unroll
     for (int i = 0; i < SPL; ++i) r[c][i] = AT(0);
   ST ub[3][SPL], uc[3][SPL];
+  ST u0[kClose ? 3 : 1][kClose ? SPL : 1];  // the walk's first neighbour, for the element that closes the fan
   ENSFEM_UNROLL_GATHER
   for (int k = kb; k < ke; ++k) {
     const int64_t e = maybe_uni<UNI>(cst(p.adj.el)[k]);
@@ -202,15 +216,29 @@ __device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_
       const int64_t rb = node_row<MAP>(map, bc.x);
 #pragma unroll
       for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (rb + c) * ld + s0, ub[c]);
+      if constexpr (kClose)
+        if (k == kb)
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int i = 0; i < SPL; ++i) u0[c][i] = ub[c][i];
     } else {
 #pragma unroll
       for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int i = 0; i < SPL; ++i) ub[c][i] = uc[c][i];
     }
-    const int64_t rc = node_row<MAP>(map, bc.y);
+    // bc.y < 0: this element's second neighbour is the walk's first one
+    if (kClose && bc.y < 0) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (rc + c) * ld + s0, uc[c]);
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int i = 0; i < SPL; ++i) uc[c][i] = u0[kClose ? c : 0][kClose ? i : 0];
+    } else {
+      const int64_t rc = node_row<MAP>(map, bc.y < 0 ? ~bc.y : bc.y);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (rc + c) * ld + s0, uc[c]);
+    }
 #pragma unroll
     for (int i = 0; i < SPL; ++i) {
       const AT d0 = (AT)(ub[0][i] - ua[0][i]);
@@ -317,7 +345,8 @@ __device__ __forceinline__ void gather_geom(const StepArgs& p, int node, int64_t
     const int64_t e = maybe_uni<UNI>(cst(p.adj.el)[k]);
     const ConstPtr<int> nb = (ConstPtr<int>)cst(p.adj.nb);
     const int bx = maybe_uni<UNI>(nb[2 * k]);
-    const int cx = maybe_uni<UNI>(nb[2 * k + 1]);
+    const int cx0 = maybe_uni<UNI>(nb[2 * k + 1]);
+    const int cx = cx0 < 0 ? ~cx0 : cx0;  // a closing entry names the walk's first neighbour
     AT eh[SPL];
     vload<SPL, false>(EH + e * ld + s0, eh);
     AT ab[3][SPL], dbb[3][SPL];
@@ -446,9 +475,12 @@ __device__ __forceinline__ uint64_t spread_bits(uint64_t x) {
 // stiffness apply, central-difference update, QoI and energy terms.
 // `lane` in [0, LPN); samples base + lane*SPL + i (base a multiple of
 // LPN*SPL, and of 64 when LPN = 64).
-template <typename AT, int MODE, int LPN, int SPL, bool QOI, bool ENERGY, bool SHARED, bool GEOM = false>
+// nwords < SPL (batched step only): the wave's upper lanes are idle and only
+// the first nwords rising-bit words belong to this block of samples.
+template <typename AT, int MODE, int LPN, int SPL, bool QOI, bool ENERGY, bool SHARED, bool GEOM = false,
+          bool CLOSE = true>
 __device__ __forceinline__ void step_node(const StepArgs& p, int j, int node, int base, int lane,
-                                          double (&e_loc)[SPL]) {
+                                          double (&e_loc)[SPL], int nwords = SPL) {
   static_assert(!GEOM || (MODE == kStateF64 && !SHARED && !ENERGY), "geometry form: FP64 state only");
   const int s0 = base + lane * SPL;
   const int64_t ld = p.ld;
@@ -492,7 +524,7 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int j, int node, in
     }
   } else {
     if constexpr (SHARED) gather_blocks<AT, ST, SPL, UNI>(p, node, ld, s0, U, ua, r);
-    else gather_apply<AT, ST, SPL, UNI>(p, node, ld, s0, U, ua, r);
+    else gather_apply<AT, ST, SPL, UNI, false, CLOSE>(p, node, ld, s0, U, ua, r);
 #pragma unroll
     for (int c = 0; c < 3; ++c)
 #pragma unroll
@@ -622,7 +654,7 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int j, int node, in
       uint64_t* __restrict__ mw = gen(p.qmask) + (int64_t)node * p.qwords + base / 64;
       uint64_t words[SPL];
 #pragma unroll
-      for (int w = 0; w < SPL; ++w) words[w] = uni(mw[w]);
+      for (int w = 0; w < SPL; ++w) words[w] = w < nwords ? uni(mw[w]) : 0ull;
       uint64_t mine = words[0];
 #pragma unroll
       for (int w = 1; w < SPL; ++w)
@@ -643,7 +675,7 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int j, int node, in
         uint64_t nw = 0;
 #pragma unroll
         for (int i = 0; i < SPL; ++i) nw |= spread_bits<SPL>(ballots[i] >> (w * LPW)) << i;
-        if (nw != words[w] && lane == 0) mw[w] = nw;
+        if (w < nwords && nw != words[w] && lane == 0) mw[w] = nw;
       }
     } else {
       double qo[SPL];
@@ -666,7 +698,7 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int j, int node, in
 // kBlock/LPN nodes times LPN*SPL samples.  With LPN = 64 a wave owns one
 // node, so adjacency and stiffness blocks are wave-uniform (scalar loads).
 template <typename AT, int MODE, int LPN, int SPL, bool QOI, bool ENERGY, bool SHARED, bool GEOM = false>
-__global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
+__global__ __launch_bounds__(kBlock, ENSFEM_STEP_MIN_WAVES) void k_step(StepArgs p) {
   constexpr int NPB = kBlock / LPN;
   int nb, sbk;
   if (!wg_coords(p, nb, sbk)) return;  // uniform over the workgroup
@@ -696,26 +728,26 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
   }
 }
 
-// Batched step: one launch steps every mesh of a batch (per lane width:
-// tiles with 2 samples per lane and, where a padded width leaves a last
-// block of 64, tiles with 1, each class one launch).  Persistent
+// Batched step: one launch per step for every mesh of a batch.  Persistent
 // workgroups walk a list of tiles (mesh, first node, node count, first
 // sample) ordered mesh by mesh and node-fastest; each XCD takes a
 // contiguous eighth of the list and its workgroups sweep it in order, so
 // tiles that share neighbours run close in time on one L2.  Each wave takes
-// every 4th node of a tile with 64 lanes x SPL samples.
+// every 4th node of a tile with 64 lanes x SPL samples; with SPL = 2, tiles
+// from n_wide on hold the 64-sample block that ends an odd multiple of 64
+// and run on the wave's lower 32 lanes (one kernel, one register budget).
 // Per-mesh arguments come from a device table indexed by mesh and by the
 // parity of the step (which state buffer is current).
 template <typename AT, int MODE, int SPL, bool QOI>
 __global__ __launch_bounds__(kBlock) void k_batch_step(const BatchTile* __restrict__ tiles, int32_t n_tiles,
-                                                       const StepArgs* __restrict__ desc, int32_t j) {
+                                                       int32_t n_wide, const StepArgs* __restrict__ desc,
+                                                       int32_t j) {
   const int wave = threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   const int per = gridDim.x >> 3;
   const int x = blockIdx.x & 7, rank = blockIdx.x >> 3;
   const int beg = (int)(((int64_t)n_tiles * x) >> 3);
   const int end = (int)(((int64_t)n_tiles * (x + 1)) >> 3);
-  double e_loc[SPL];
 #pragma nounroll
   for (int t = beg + rank; t < end; t += per) {
     // tile and mesh arguments are uniform: keep them in scalar registers
@@ -725,10 +757,14 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(const BatchTile* __restri
     const int count = __builtin_amdgcn_readfirstlane(tile->count);
     const int sample0 = __builtin_amdgcn_readfirstlane(tile->sample0);
     const StepArgs p = load_args(desc + 2 * mesh + (j & 1));
+    const bool half = SPL == 2 && t >= n_wide;
 #pragma nounroll
     for (int n = wave; n < count; n += kBlock / 64) {
       const int node = __builtin_amdgcn_readfirstlane(node0 + n);
-      step_node<AT, MODE, 64, SPL, QOI, false, false>(p, j, node, sample0, lane, e_loc);
+      double e_loc[SPL];
+      if (!half || lane < 32)
+        step_node<AT, MODE, 64, SPL, QOI, false, false, false, false>(p, j, node, sample0, lane, e_loc,
+                                                                      half ? 1 : SPL);
     }
   }
 }
@@ -753,7 +789,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(StepArgs p, const AT* __restri
   for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (row + c) * ld + s0, ua[c]);
   AT r[3][SPL];
   if constexpr (SHARED) gather_blocks<AT, AT, SPL, (LPN == 64), MAP>(p, node, ld, s0, U, ua, r, map);
-  else gather_apply<AT, AT, SPL, (LPN == 64), MAP>(p, node, ld, s0, U, ua, r, map);
+  else gather_apply<AT, AT, SPL, (LPN == 64), MAP, ENSFEM_APPLY_CLOSE>(p, node, ld, s0, U, ua, r, map);
 #pragma unroll
   for (int c = 0; c < 3; ++c) vstore<SPL, true>(R + (row + c) * ld + s0, r[c]);
 }
@@ -803,6 +839,39 @@ __global__ __launch_bounds__(64) void k_energy_reduce2(const double* __restrict_
   double sum = 0.0;
   for (int c = 0; c < chunks; ++c) sum += tmp[(int64_t)c * ld + s];
   out[s] = sum;
+}
+
+// Kinetic energy per sample in node chunks (fixed order), for the watchdog.
+__global__ __launch_bounds__(64) void k_kinetic_part(int32_t n_nodes, int32_t ld, int32_t chunks,
+                                                     const double* __restrict__ un1, const double* __restrict__ un,
+                                                     const float* __restrict__ vel, const double* __restrict__ minv,
+                                                     double inv_dt, double* __restrict__ tmp) {
+  const int s = blockIdx.x * 64 + threadIdx.x;
+  const int ch = blockIdx.y;
+  if (s >= ld) return;
+  const int per = (n_nodes + chunks - 1) / chunks;
+  const int i0 = ch * per, i1 = min(n_nodes, i0 + per);
+  double sum = 0.0;
+  for (int i = i0; i < i1; ++i) {
+    const double m = 1.0 / minv[(int64_t)i * ld + s];
+    double v2 = 0.0;
+    for (int c = 0; c < 3; ++c) {
+      const int64_t idx = ((int64_t)i * 3 + c) * ld + s;
+      const double v = vel ? (double)vel[idx] : (un1[idx] - un[idx]) * inv_dt;
+      v2 = fma(v, v, v2);
+    }
+    sum = fma(0.5 * m, v2, sum);
+  }
+  tmp[(int64_t)ch * ld + s] = sum;
+}
+
+__global__ __launch_bounds__(64) void k_watch(int32_t S, const double* __restrict__ krow,
+                                              const double* __restrict__ erow, double coef,
+                                              int32_t* __restrict__ flag) {
+  const int s = blockIdx.x * 64 + threadIdx.x;
+  if (s >= S) return;
+  const double T = krow[s], E = erow[s];
+  if (!(coef * T <= E + 1e-12 * T)) *flag = 1;  // also trips on NaN
 }
 
 // Taylor starter, FP64 two-level state: on entry vprev_io holds v_0; on
@@ -1072,20 +1141,20 @@ hipError_t launch_apply(const StepArgs& a, bool f32, int sample_block, bool shar
              : dispatch_apply_map<double, false>(a, sample_block, U, R, map, st);
 }
 
-hipError_t launch_batch_step(const BatchTile* tiles, int32_t n_tiles, int spl, const StepArgs* desc, int32_t j,
-                             bool apply_f32, int mode, bool qoi, int grid, hipStream_t st) {
+hipError_t launch_batch_step(const BatchTile* tiles, int32_t n_tiles, int32_t n_wide, int spl, const StepArgs* desc,
+                             int32_t j, bool apply_f32, int mode, bool qoi, int grid, hipStream_t st) {
   if (n_tiles == 0) return hipSuccess;
   if (grid % 8 != 0 || (spl != 1 && spl != 2)) return hipErrorInvalidValue;
-#define ENSFEM_BATCH(AT, MODE)                                                                           \
-  do {                                                                                                   \
-    if (spl == 2) {                                                                                      \
-      if (qoi) k_batch_step<AT, MODE, 2, true><<<grid, kBlock, 0, st>>>(tiles, n_tiles, desc, j);        \
-      else k_batch_step<AT, MODE, 2, false><<<grid, kBlock, 0, st>>>(tiles, n_tiles, desc, j);           \
-    } else {                                                                                             \
-      if (qoi) k_batch_step<AT, MODE, 1, true><<<grid, kBlock, 0, st>>>(tiles, n_tiles, desc, j);        \
-      else k_batch_step<AT, MODE, 1, false><<<grid, kBlock, 0, st>>>(tiles, n_tiles, desc, j);           \
-    }                                                                                                    \
-    return hipGetLastError();                                                                            \
+#define ENSFEM_BATCH_Q(AT, MODE, SPL)                                                                     \
+  do {                                                                                                    \
+    if (qoi) k_batch_step<AT, MODE, SPL, true><<<grid, kBlock, 0, st>>>(tiles, n_tiles, n_wide, desc, j); \
+    else k_batch_step<AT, MODE, SPL, false><<<grid, kBlock, 0, st>>>(tiles, n_tiles, n_wide, desc, j);   \
+  } while (0)
+#define ENSFEM_BATCH(AT, MODE)                  \
+  do {                                          \
+    if (spl == 2) ENSFEM_BATCH_Q(AT, MODE, 2);  \
+    else ENSFEM_BATCH_Q(AT, MODE, 1);           \
+    return hipGetLastError();                   \
   } while (0)
   if (!apply_f32) {
     if (mode != kStateF64) return hipErrorInvalidValue;
@@ -1095,6 +1164,7 @@ hipError_t launch_batch_step(const BatchTile* tiles, int32_t n_tiles, int spl, c
   if (mode == kStateF32Kahan) ENSFEM_BATCH(float, kStateF32Kahan);
   if (mode == kStateF32) ENSFEM_BATCH(float, kStateF32);
 #undef ENSFEM_BATCH
+#undef ENSFEM_BATCH_Q
   return hipErrorInvalidValue;
 }
 
@@ -1113,6 +1183,17 @@ hipError_t launch_copy_f64(int64_t n, const double* src, double* dst, hipStream_
 
 hipError_t launch_advance(int64_t* base, int32_t k, hipStream_t st) {
   k_advance<<<1, 64, 0, st>>>(base, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_kinetic(int32_t n_nodes, int32_t ld, int32_t S, const double* u_next, const double* u_cur,
+                          const float* vel, const double* minv, double dt, double* tmp, double* krow,
+                          const double* erow, double coef, int32_t* flag, hipStream_t st) {
+  const int chunks = 256;
+  dim3 g1(grid_for(ld, 64), chunks);
+  k_kinetic_part<<<g1, 64, 0, st>>>(n_nodes, ld, chunks, u_next, u_cur, vel, minv, 1.0 / dt, tmp);
+  k_energy_reduce2<<<grid_for(S, 64), 64, 0, st>>>(tmp, chunks, ld, S, krow);
+  k_watch<<<grid_for(S, 64), 64, 0, st>>>(S, krow, erow, coef, flag);
   return hipGetLastError();
 }
 

@@ -59,7 +59,7 @@ class BatchInfo(ctypes.Structure):
     _fields_ = [("n_meshes", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
                 ("samples_per_lane", ctypes.c_int32), ("tile_nodes", ctypes.c_int32),
                 ("grid", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
-                ("tuned_ms_per_step", ctypes.c_double)]
+                ("launches_per_step", ctypes.c_int32), ("tuned_ms_per_step", ctypes.c_double)]
 
 
 _lib = None

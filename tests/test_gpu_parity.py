@@ -237,6 +237,7 @@ def test_energy_conserved_and_matches_oracle():
     ens = ensfem.setup_case(cs.mesh, cs.eh, cs.h, F0, alpha=0.0, energy_every=10)
     ens.init_state(u0)
     ens.step(n, cs.dt)
+    ens.sync()  # the energy watchdog stays quiet on a stable run from a rough start
     steps, E = ens.read_energy()
     ens.close()
     assert len(steps) == n // 10 and steps[0] == 0 and steps[-1] == n - 10
@@ -249,6 +250,36 @@ def test_energy_conserved_and_matches_oracle():
         e_ref = np.array([e for _, e in r["energy"]])
         assert np.max(np.abs(E[:, s] - e_ref)) <= 1e-10 * abs(e_ref[0])
         assert np.max(np.abs(E[:, s] - E[0, s])) <= 1e-11 * abs(E[0, s])
+
+
+@pytest.mark.parametrize("state", [ensfem.STATE_F64, ensfem.STATE_F32_KAHAN])
+def test_energy_watchdog_flags_an_unstable_step(state):
+    """Energy records every 10 steps on the C1 cylinder: at the stable step
+    and at a step forced 5 % past the element bound (still below the
+    assembled system's limit, about 1.2 times the bound here) ens_sync is
+    quiet; forced 1.6 times past the bound the highest modes grow, and
+    ens_sync reports ENS_EUNSTABLE from the watchdog well before the state
+    overflows; a new initial state clears it."""
+    cs = c1_case()
+    kw = dict(kind=ensfem.LOAD_RAMP_SINE, t_ramp=cs.cfg["T_ramp"], energy_every=10, state_prec=state,
+              apply_prec=ensfem.F64 if state == ensfem.STATE_F64 else ensfem.F32)
+    bound = cs.dt / cs.cfg["safety"]
+    for factor, unstable in ((cs.cfg["safety"], False), (1.05, False), (1.6, True)):
+        say(f"case: watchdog state={state} dt = {factor} x bound")
+        ens = ensfem.setup_case(cs.mesh, cs.eh, cs.h, cs.F, **kw)
+        ens.init_state()
+        ens.step(50, factor * bound, force=True)
+        if unstable:
+            with pytest.raises(ensfem.EnsfemError) as ei:
+                ens.sync()
+            assert ei.value.code == ensfem.ENS_EUNSTABLE
+            assert np.all(np.isfinite(ens.read_state()))  # caught before any overflow
+            ens.init_state()
+            ens.step(0, cs.dt)
+            ens.sync()
+        else:
+            ens.sync()
+        ens.close()
 
 
 @pytest.mark.parametrize("state", [ensfem.STATE_F64, ensfem.STATE_F32_KAHAN])
