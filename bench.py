@@ -112,6 +112,27 @@ def _oracle_column(task):
     return t0, time.time()
 
 
+def _oracle_c3_column(task):
+    """Worker of the precision-form check: the oracle on one sample column of
+    the full curved tube (its own element matrices, per-sample CSR stiffness
+    and lumped mass, eq. dynamicsCD step by step) for n_steps steps, with the
+    step size from the oracle's element bound over the whole ensemble
+    (ratio = max over samples of E = (E h) / h per element).  Returns u, q and
+    the step size it used."""
+    eh_col, h_col, ratio, n_steps = task
+    from paper_2101_09059_amd import inputs
+    from oracle import cfl, element, stepper
+    c = inputs.CONFIGS["c3_curved"]
+    m = inputs.curved_tube(c["n_theta"], c["n_z"])
+    F = inputs.traction_load(m, c["p0"], axial_taper=c["axial_taper"], shear_frac=c["shear_frac"], seed=c["seed"])
+    kh, A, _ = element.reference_stiffness(m.xyz, m.tri, c["nu"], c["shear_k"])
+    dt = cfl.stable_dt(kh, A, ratio[:, None], np.ones((m.n_el, 1)), c["rho"], c["safety"])
+    g = lambda t: stepper.load_factor(c["ramp"], t, c["T_ramp"], c["period"], c["pulse_amp"])
+    r = stepper.run_ensemble(m.tri, kh, A, eh_col[:, None], h_col[:, None], c["rho"], F, m.fixed, m.radial, dt,
+                             n_steps, c["alpha"], g)
+    return r["u"][:, 0], r["q"][:, 0], dt
+
+
 def cpu_baseline(mesh, eh, h, F, cfg, dt, budget_s: float = 12.0) -> dict:
     """The oracle as it stands (per-sample CSR assembly + one SpMV and update
     per step) on a bounded sample of the same workload: one process, then one
@@ -288,6 +309,47 @@ def run_surrogate_kernels(args, torch):
     print(json.dumps(out), flush=True)
 
 
+def variance_se_rows(q: np.ndarray) -> np.ndarray:
+    """Per row, the standard error of the sample variance of the columns of
+    q without assuming normality: sqrt((m4 - m2^2) / N) (fourth central
+    moment m4), the estimate's spread for heavy-tailed samples."""
+    N = q.shape[1]
+    d = q - q.mean(axis=1, keepdims=True)
+    m2 = (d * d).mean(axis=1)
+    m4 = (d ** 4).mean(axis=1)
+    return np.sqrt(np.maximum(m4 - m2 * m2, 0.0) / N)
+
+
+def cv_variance_bootstrap_se(qH, qL, sumL, sumsqL, M, n_boot=100, n_nodes=4096, seed=1):
+    """Relative standard error of the control-variate variance estimate,
+    from resampling the N high-fidelity pairs (the M network draws held
+    fixed): on a random subset of varying nodes, the norm of the per-node
+    spread over the replicates divided by the norm of the estimate."""
+    rng = np.random.default_rng(seed)
+    act = np.flatnonzero(qH.var(axis=1) > 0)
+    nodes = rng.choice(act, size=min(n_nodes, act.size), replace=False)
+    H, L = qH[nodes], qL[nodes]
+    mL = (sumL[nodes] / M, sumsqL[nodes] / M)
+    N = H.shape[1]
+
+    def cv_var(h0, l0):
+        est = []
+        for k, (h, l) in enumerate(((h0, l0), (h0 * h0, l0 * l0))):
+            mh, ml = h.mean(1), l.mean(1)
+            cov = ((h - mh[:, None]) * (l - ml[:, None])).sum(1) / (N - 1)
+            vl = l.var(1, ddof=1)
+            beta = np.where(vl > 0, cov / np.where(vl > 0, vl, 1.0), 0.0)
+            est.append(mh - beta * (ml - mL[k]))
+        return est[1] - est[0] ** 2
+
+    base = cv_var(H, L)
+    reps = np.empty((n_boot, nodes.size))
+    for b in range(n_boot):
+        idx = rng.integers(0, N, N)
+        reps[b] = cv_var(H[:, idx], L[:, idx])
+    return float(np.linalg.norm(reps.std(axis=0)) / np.linalg.norm(base))
+
+
 def run_learned_config(args, torch):
     """Learned form at full size: 200k-node cylinder, 64 + 64 KL inputs,
     MLP 128 -> 3 x 1024 (GELU) -> 200,000, trained on 4,096 solver samples
@@ -341,7 +403,13 @@ def run_learned_config(args, torch):
     Nr = qR.shape[1]
     rel = lambda a, b: float(np.linalg.norm(a[act] - b[act]) / np.linalg.norm(b[act]))
     se_mean = float(np.linalg.norm(np.sqrt(ref_v[act] / Nr)) / np.linalg.norm(ref_m[act]))
-    se_var = float(np.sqrt(2.0 / (Nr - 1)))
+    se_var_normal = float(np.sqrt(2.0 / (Nr - 1)))
+    # the QoI is heavy-tailed (lognormal fields): the reference variance's
+    # own error from its fourth moments, aggregated like the error metric
+    se_var = float(np.linalg.norm(variance_se_rows(qR[act])) / np.linalg.norm(ref_v[act]))
+    se_var_cv = cv_variance_bootstrap_se(qH, qL, sumL, sumsqL, c["n_lf"]) if est["used_cv"] else None
+    err_mean, err_var = rel(est["mean"], ref_m), rel(est["var"], ref_v)
+    var_bound = max(0.01, 2.0 * se_var)
     N, M = c["n_hf"], c["n_lf"]
     ratio = 1.0 - est["rho"][act] ** 2 * M / (M + N)
     n_eq = N / float(np.median(ratio))
@@ -352,13 +420,17 @@ def run_learned_config(args, torch):
         "metric": "surrogate-CV QoI rel.err and speedup", "value": t_plain_eq / t_cv,
         "unit": "speedup over the plain ensemble at equal variance (training data excluded)",
         "n_gpus": 1, "higher_is_better": True, "data": "synthetic", "dtype": "bf16 mfma / fp32 accumulate",
-        "config": {"workload": "200k-node clamped cylinder, pulsatile pressure (ramp 0.02 s, window 0.03 s), "
-                               "64+64 KL inputs, MLP 3x1024 GELU -> 200,000, 4,096 training solves, "
-                               "256 high-fidelity + 65,536 low-fidelity, plain reference 4,096"},
-        "mean_rel_err_vs_reference": rel(est["mean"], ref_m),
-        "var_rel_err_vs_reference": rel(est["var"], ref_v),
+        "config": {"workload": f"200k-node clamped cylinder, pulsatile pressure (ramp 0.02 s, peak over the "
+                               f"window t in [0, 0.03 s]), 64+64 KL inputs, MLP 3x1024 GELU -> 200,000, 4,096 "
+                               f"training solves, 256 high-fidelity + 65,536 low-fidelity, plain reference {Nr:,}"},
+        "mean_rel_err_vs_reference": err_mean,
+        "var_rel_err_vs_reference": err_var,
         "plain_256_mean_rel_err": rel(pm, ref_m), "plain_256_var_rel_err": rel(pv, ref_v),
-        "reference_se_mean": se_mean, "reference_se_var": se_var,
+        "reference_se_mean": se_mean, "reference_se_var": se_var, "reference_se_var_if_normal": se_var_normal,
+        "cv_var_se_bootstrap": se_var_cv,
+        "acceptance": {"mean_within_1pct": err_mean <= 0.01, "var_bound_max_1pct_2se_ref": var_bound,
+                       "var_within_bound": err_var <= var_bound,
+                       "var_z_vs_combined_se": err_var / float(np.hypot(se_var, se_var_cv or 0.0))},
         "used_control_variate": est["used_cv"], "rho_median": est["rho_median"],
         "heldout_rel_rmse": rmse, "kl_captured_variance": prob.captured, "kept_epoch": net.best_epoch,
         "equivalent_plain_samples": n_eq,
@@ -425,19 +497,38 @@ def run_precision_config(args, torch):
 
     n_acc, S_acc = args.c3_error_steps, args.c3_error_samples
     e_acc, h_acc = np.ascontiguousarray(eh[:, :S_acc]), np.ascontiguousarray(h[:, :S_acc])
+    # the oracle on the first two sample columns, in worker processes while
+    # the GPU runs below: its step size comes from its own element bound over
+    # the whole ensemble (per element the largest E = (E h) / h)
+    n_or = min(args.c3_oracle_steps, n_acc)
+    oracle_pool = oracle_jobs = None
+    if n_or > 0:
+        ratio = np.concatenate([np.max(eh[i:i + 65536] / h[i:i + 65536], axis=1)
+                                for i in range(0, eh.shape[0], 65536)])
+        import multiprocessing as mp
+        oracle_pool = mp.get_context("spawn").Pool(2)
+        oracle_jobs = oracle_pool.map_async(_oracle_c3_column,
+                                            [(np.ascontiguousarray(e_acc[:, s]), np.ascontiguousarray(h_acc[:, s]),
+                                              ratio, n_or) for s in (0, 1)], chunksize=1)
+        log(f"oracle started on sample columns 0 and 1, {n_or} steps")
     del eh, h
     ref_u = ref_q = None
     err = {}
+    gpu_at = {}  # state and peak of columns 0, 1 after n_or steps, per mode
     for name, ap, st, _ in modes:
         ens = make(e_acc, h_acc, ap, st)
         ens.init_state()
         done = 0
         while done < n_acc:  # in chunks, with a progress line each
             k = min(10000, n_acc - done)
+            if done < n_or:
+                k = min(k, n_or - done)
             ens.step(k, dt, stream=stream)
             ens.sync()
             done += k
             log(f"  {name}: {done}/{n_acc} steps")
+            if done == n_or:
+                gpu_at[name] = (ens.read_state()[:, :2], ens.read_qoi()[:, :2])
         u, q = ens.read_state(), ens.read_qoi()
         ens.close()
         del ens
@@ -449,6 +540,26 @@ def run_precision_config(args, torch):
                          peak_rel_l2=float(np.linalg.norm(q - ref_q) / np.linalg.norm(ref_q)))
         log(f"{name}: after {n_acc} steps, state rel. L2 error {err[name]['state_rel_l2']:.2e}, "
             f"peak {err[name]['peak_rel_l2']:.2e} against FP64")
+    vs_oracle = None
+    if oracle_jobs is not None:
+        waited = 0
+        while not oracle_jobs.ready():  # progress lines while the oracle finishes
+            oracle_jobs.wait(30)
+            waited += 30
+            log(f"  waiting for the oracle ({waited} s)")
+        cols = oracle_jobs.get()
+        oracle_pool.close()
+        ou = np.stack([c[0] for c in cols], axis=1)
+        oq = np.stack([c[1] for c in cols], axis=1)
+        dt_or = cols[0][2]
+        vs_oracle = {"steps": n_or, "samples": [0, 1], "dt_oracle_over_dt_gpu": dt_or / dt}
+        for name, (gu, gq) in gpu_at.items():
+            vs_oracle[name] = dict(
+                state_rel_l2=float(np.linalg.norm(gu - ou) / np.linalg.norm(ou)),
+                state_per_sample_max=float(np.max(np.linalg.norm(gu - ou, axis=0) / np.linalg.norm(ou, axis=0))),
+                peak_rel_l2=float(np.linalg.norm(gq - oq) / np.linalg.norm(oq)))
+            log(f"{name}: after {n_or} steps, state rel. L2 error {vs_oracle[name]['state_rel_l2']:.2e} "
+                f"against the oracle (columns 0, 1)")
     head = thr["f32_apply_f64_state"]
     out = {
         "metric": "ensemble dof*sample*steps/s", "value": head["value"], "unit": "dof*sample*steps/s",
@@ -461,6 +572,7 @@ def run_precision_config(args, torch):
                    "n_dof": mesh.n_dof, "samples": S, "dt": dt, "parallelism": "single GPU"},
         "modes": thr,
         "error_vs_f64": {"steps": n_acc, "samples": S_acc, **err},
+        "error_vs_oracle": vs_oracle,
     }
     print(json.dumps(out), flush=True)
 
@@ -495,6 +607,8 @@ def main():
                     help="c3_curved: steps of the error run")
     ap.add_argument("--c3-error-samples", type=int, default=64,
                     help="c3_curved: sample columns of the error run (the first ones of the ensemble)")
+    ap.add_argument("--c3-oracle-steps", type=int, default=2000,
+                    help="c3_curved: steps of the oracle check on sample columns 0 and 1 (0: skip)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a plain 1 GiB device copy 10 times (counter calibration)")
     args = ap.parse_args()
