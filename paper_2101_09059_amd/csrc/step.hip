@@ -29,15 +29,6 @@
 #ifndef ENSFEM_GATHER_UNROLL
 #define ENSFEM_GATHER_UNROLL 2
 #endif
-// Closing-element reuse in the stand-alone apply (its 4 samples per lane
-// already need many registers).
-#ifndef ENSFEM_APPLY_CLOSE
-#define ENSFEM_APPLY_CLOSE 1
-#endif
-// Minimum waves per SIMD the step kernels are compiled for.
-#ifndef ENSFEM_STEP_MIN_WAVES
-#define ENSFEM_STEP_MIN_WAVES 1
-#endif
 // Issue the node's single-use loads (u_{n-1}, 1/m) before the gather so
 // they are in flight during it (FP64 state).
 #ifndef ENSFEM_HOIST_STREAMS
@@ -181,15 +172,13 @@ __device__ __forceinline__ int64_t node_row(const int32_t* __restrict__ map, int
   else return (int64_t)n * 3;
 }
 
-// R for one node and SPL consecutive samples starting at s0.
-// CLOSE: the element that closes a node's fan takes the walk's first
-// neighbour from registers (worth its registers in the FP32 apply of the
-// single-mesh kernels); otherwise the closing entry is loaded again.
-template <typename AT, typename ST, int SPL, bool UNI, bool MAP = false, bool CLOSE = true>
-__device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_t ld, int s0,
-                                             const ST* __restrict__ U, const ST (&ua)[3][SPL],
-                                             AT (&r)[3][SPL], const int32_t* __restrict__ map = nullptr) {
-  constexpr bool kClose = CLOSE && ENSFEM_CLOSE_REUSE && std::is_same<AT, float>::value;
+// R for one node and SPL consecutive samples starting at s0, in two forms.
+// Rows form (the FP64 apply): the walk's shared neighbour is carried as its
+// loaded row; an entry that closes the fan is loaded again.
+template <typename AT, typename ST, int SPL, bool UNI, bool MAP = false>
+__device__ __forceinline__ void gather_apply_rows(const StepArgs& p, int node, int64_t ld, int s0,
+                                                  const ST* __restrict__ U, const ST (&ua)[3][SPL],
+                                                  AT (&r)[3][SPL], const int32_t* __restrict__ map = nullptr) {
   const int kb = maybe_uni<UNI>(cst(p.adj.ptr)[node]);
   const int ke = maybe_uni<UNI>(cst(p.adj.ptr)[node + 1]);
   const ConstPtr<AT> KB = (ConstPtr<AT>)cst(p.adj.k);
@@ -199,7 +188,6 @@ __device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_
 #pragma unroll
     for (int i = 0; i < SPL; ++i) r[c][i] = AT(0);
   ST ub[3][SPL], uc[3][SPL];
-  ST u0[kClose ? 3 : 1][kClose ? SPL : 1];  // the walk's first neighbour, for the element that closes the fan
   ENSFEM_UNROLL_GATHER
   for (int k = kb; k < ke; ++k) {
     const int64_t e = maybe_uni<UNI>(cst(p.adj.el)[k]);
@@ -216,29 +204,15 @@ __device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_
       const int64_t rb = node_row<MAP>(map, bc.x);
 #pragma unroll
       for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (rb + c) * ld + s0, ub[c]);
-      if constexpr (kClose)
-        if (k == kb)
-#pragma unroll
-          for (int c = 0; c < 3; ++c)
-#pragma unroll
-            for (int i = 0; i < SPL; ++i) u0[c][i] = ub[c][i];
     } else {
 #pragma unroll
       for (int c = 0; c < 3; ++c)
 #pragma unroll
         for (int i = 0; i < SPL; ++i) ub[c][i] = uc[c][i];
     }
-    // bc.y < 0: this element's second neighbour is the walk's first one
-    if (kClose && bc.y < 0) {
+    const int64_t rc = node_row<MAP>(map, bc.y < 0 ? ~bc.y : bc.y);
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
-#pragma unroll
-        for (int i = 0; i < SPL; ++i) uc[c][i] = u0[kClose ? c : 0][kClose ? i : 0];
-    } else {
-      const int64_t rc = node_row<MAP>(map, bc.y < 0 ? ~bc.y : bc.y);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (rc + c) * ld + s0, uc[c]);
-    }
+    for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (rc + c) * ld + s0, uc[c]);
 #pragma unroll
     for (int i = 0; i < SPL; ++i) {
       const AT d0 = (AT)(ub[0][i] - ua[0][i]);
@@ -255,6 +229,100 @@ __device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_
       r[2][i] = fma(eh[i], f2, r[2][i]);
     }
   }
+}
+
+// Differences form (the FP32 apply): the walk's shared neighbour (and, with
+// CLOSE, the fan's first one for the element that closes the fan) is
+// carried as its converted differences u_b - u_a rather than its rows: the
+// same operations in the same order as the rows form, fewer registers.
+template <typename AT, typename ST, int SPL, bool UNI, bool MAP = false, bool CLOSE = true>
+__device__ __forceinline__ void gather_apply_diff(const StepArgs& p, int node, int64_t ld, int s0,
+                                                  const ST* __restrict__ U, const ST (&ua)[3][SPL],
+                                                  AT (&r)[3][SPL], const int32_t* __restrict__ map = nullptr) {
+  constexpr bool kClose = CLOSE && ENSFEM_CLOSE_REUSE;
+  const int kb = maybe_uni<UNI>(cst(p.adj.ptr)[node]);
+  const int ke = maybe_uni<UNI>(cst(p.adj.ptr)[node + 1]);
+  const ConstPtr<AT> KB = (ConstPtr<AT>)cst(p.adj.k);
+  const AT* __restrict__ EH = static_cast<const AT*>(gen(p.eh));
+#pragma unroll
+  for (int c = 0; c < 3; ++c)
+#pragma unroll
+    for (int i = 0; i < SPL; ++i) r[c][i] = AT(0);
+  AT db[3][SPL], dc[3][SPL];
+  AT d0s[kClose ? 3 : 1][kClose ? SPL : 1];  // the walk's first neighbour's differences
+  ENSFEM_UNROLL_GATHER
+  for (int k = kb; k < ke; ++k) {
+    const int64_t e = maybe_uni<UNI>(cst(p.adj.el)[k]);
+    const ConstPtr<int> nb = (ConstPtr<int>)cst(p.adj.nb);
+    const int2 bc0 = make_int2(nb[2 * k], nb[2 * k + 1]);
+    const int2 bc = make_int2(maybe_uni<UNI>(bc0.x), maybe_uni<UNI>(bc0.y));
+    AT kk[18];
+#pragma unroll
+    for (int i = 0; i < 18; ++i) kk[i] = maybe_uni<UNI>(KB[(int64_t)k * 18 + i]);
+    AT eh[SPL];
+    vload<SPL, false>(EH + e * ld + s0, eh);
+    // bc.x < 0: this element's first neighbour is the previous one's second
+    if (bc.x >= 0) {
+      const int64_t rb = node_row<MAP>(map, bc.x);
+      ST ub[3][SPL];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (rb + c) * ld + s0, ub[c]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int i = 0; i < SPL; ++i) db[c][i] = (AT)(ub[c][i] - ua[c][i]);
+      if constexpr (kClose)
+        if (k == kb)
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int i = 0; i < SPL; ++i) d0s[c][i] = db[c][i];
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int i = 0; i < SPL; ++i) db[c][i] = dc[c][i];
+    }
+    // bc.y < 0: this element's second neighbour is the walk's first one
+    if (kClose && bc.y < 0) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int i = 0; i < SPL; ++i) dc[c][i] = d0s[kClose ? c : 0][kClose ? i : 0];
+    } else {
+      const int64_t rc = node_row<MAP>(map, bc.y < 0 ? ~bc.y : bc.y);
+      ST uc[3][SPL];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (rc + c) * ld + s0, uc[c]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int i = 0; i < SPL; ++i) dc[c][i] = (AT)(uc[c][i] - ua[c][i]);
+    }
+#pragma unroll
+    for (int i = 0; i < SPL; ++i) {
+      const AT f0 = row6(kk + 0, db[0][i], db[1][i], db[2][i], dc[0][i], dc[1][i], dc[2][i]);
+      const AT f1 = row6(kk + 6, db[0][i], db[1][i], db[2][i], dc[0][i], dc[1][i], dc[2][i]);
+      const AT f2 = row6(kk + 12, db[0][i], db[1][i], db[2][i], dc[0][i], dc[1][i], dc[2][i]);
+      r[0][i] = fma(eh[i], f0, r[0][i]);
+      r[1][i] = fma(eh[i], f1, r[1][i]);
+      r[2][i] = fma(eh[i], f2, r[2][i]);
+    }
+  }
+}
+
+// CLOSE: the element that closes a node's fan takes the walk's first
+// neighbour from registers (the FP32 single-mesh step kernels).
+template <typename AT, typename ST, int SPL, bool UNI, bool MAP = false, bool CLOSE = true>
+__device__ __forceinline__ void gather_apply(const StepArgs& p, int node, int64_t ld, int s0,
+                                             const ST* __restrict__ U, const ST (&ua)[3][SPL],
+                                             AT (&r)[3][SPL], const int32_t* __restrict__ map = nullptr) {
+  // the FP32 apply carries differences (fewer registers: 70 against 82 for
+  // the headline step, 7 waves per SIMD against 5); the FP64 apply keeps rows
+  if constexpr (std::is_same<AT, float>::value)
+    gather_apply_diff<AT, ST, SPL, UNI, MAP, CLOSE>(p, node, ld, s0, U, ua, r, map);
+  else
+    gather_apply_rows<AT, ST, SPL, UNI, MAP>(p, node, ld, s0, U, ua, r, map);
 }
 
 // Shared stiffness: R_i = sum_j K_ij (u_j - u_i) over the assembled
@@ -698,7 +766,7 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int j, int node, in
 // kBlock/LPN nodes times LPN*SPL samples.  With LPN = 64 a wave owns one
 // node, so adjacency and stiffness blocks are wave-uniform (scalar loads).
 template <typename AT, int MODE, int LPN, int SPL, bool QOI, bool ENERGY, bool SHARED, bool GEOM = false>
-__global__ __launch_bounds__(kBlock, ENSFEM_STEP_MIN_WAVES) void k_step(StepArgs p) {
+__global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
   constexpr int NPB = kBlock / LPN;
   int nb, sbk;
   if (!wg_coords(p, nb, sbk)) return;  // uniform over the workgroup
@@ -789,7 +857,8 @@ __global__ __launch_bounds__(kBlock) void k_apply(StepArgs p, const AT* __restri
   for (int c = 0; c < 3; ++c) vload<SPL, false>(U + (row + c) * ld + s0, ua[c]);
   AT r[3][SPL];
   if constexpr (SHARED) gather_blocks<AT, AT, SPL, (LPN == 64), MAP>(p, node, ld, s0, U, ua, r, map);
-  else gather_apply<AT, AT, SPL, (LPN == 64), MAP, ENSFEM_APPLY_CLOSE>(p, node, ld, s0, U, ua, r, map);
+  // the apply's 4 samples per lane already hold many registers: no fan-closing reuse
+  else gather_apply<AT, AT, SPL, (LPN == 64), MAP, false>(p, node, ld, s0, U, ua, r, map);
 #pragma unroll
   for (int c = 0; c < 3; ++c) vstore<SPL, true>(R + (row + c) * ld + s0, r[c]);
 }

@@ -52,7 +52,12 @@ def test_control_variate_matches_reference_and_gains(setup):
     e_cv = np.linalg.norm(est["mean"][act] - ref_m[act]) / np.linalg.norm(ref_m[act])
     e_plain = np.linalg.norm(s["pm"][act] - ref_m[act]) / np.linalg.norm(ref_m[act])
     e_var = np.linalg.norm(est["var"][act] - ref_v[act]) / np.linalg.norm(ref_v[act])
-    say(f"  mean rel err CV {e_cv:.2e} plain(N={N}) {e_plain:.2e} ref SE {se_m:.2e}; var rel err {e_var:.2e}")
+    # the reference variance's own standard error from its fourth moments
+    d = qR[act] - ref_m[act][:, None]
+    m2, m4 = (d * d).mean(axis=1), (d ** 4).mean(axis=1)
+    se_v = np.linalg.norm(np.sqrt(np.maximum(m4 - m2 * m2, 0.0) / Nr)) / np.linalg.norm(ref_v[act])
+    say(f"  mean rel err CV {e_cv:.2e} plain(N={N}) {e_plain:.2e} ref SE {se_m:.2e}; "
+        f"var rel err {e_var:.2e} ref SE {se_v:.2e}")
     assert e_cv < max(0.01, 3 * se_m)
     assert e_var < 0.05
     # gain: variance ratio of the CV mean to the plain N-sample mean
