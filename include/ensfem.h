@@ -277,14 +277,16 @@ int32_t ens_save(ens_ctx* ctx, void* host, size_t* bytes);
 int32_t ens_load(ens_ctx* ctx, const void* host, size_t bytes);
 
 /* ---- Batching: many meshes per launch ---------------------------------
- * A batch steps several contexts together (one persistent launch per time
- * step whose workgroups walk a list of (mesh, node tile, sample block)
- * tiles; the step loop is captured in a hipGraph and replayed).  Each
+ * A batch steps several contexts together (one launch per time step, or
+ * one per lane class, whose workgroups each take one (mesh, node tile,
+ * sample block) tile of a list; the step loop is captured in a hipGraph and
+ * replayed).  Each
  * context keeps its own mesh, fields, load, dt and state and stays usable
  * on its own between batch calls.  Requirements (ENS_EINVAL otherwise, the
  * message on the offending context): bound workspaces on one device, the
  * same apply / state precision and QoI setting, node-gather variant, no
- * energy records, padded width S_pad a multiple of 64.  The batch owns
+ * energy records, padded width S_pad a multiple of 32 (ens_set_tuning with
+ * a sample block of 32 or more before binding).  The batch owns
  * small device tables (tiles, per-mesh arguments) and a stream of its own;
  * ens_batch_step orders itself after prior work on `stream` and makes
  * `stream` wait for it. */
@@ -292,9 +294,8 @@ typedef struct ens_batch ens_batch;
 typedef struct {
   int32_t n_meshes, n_tiles;
   int32_t samples_per_lane; /* 64 lanes x up to this many samples per tile */
-  int32_t tile_nodes;       /* nodes per tile                            */
-  int32_t grid;             /* persistent workgroups per launch, 0 = one
-                               workgroup per tile                        */
+  int32_t tile_nodes;       /* nodes per tile (4: one per wave)          */
+  int32_t grid;             /* 0: one workgroup per tile (the only form) */
   int32_t graph_steps;      /* steps per captured graph                  */
   int32_t launches_per_step; /* 1, or 2 when the two lane classes are
                                 launched separately                      */
@@ -309,13 +310,13 @@ int32_t ens_batch_info(ens_batch* b, ens_batch_info_t* out);
  * dt fixed (ens_init_state, then ens_step(ctx, 0, dt, ...)).  Results are
  * bitwise those of stepping each context alone. */
 int32_t ens_batch_step(ens_batch* b, int64_t n_steps, void* stream);
-/* Times trial_steps steps for each candidate tiling (samples per lane 1 or
- * 2 -- with 2, a mesh whose padded width is an odd multiple of 64 has a
- * last block of 64 samples, run on half waves in the same launch or in a
- * second launch per step --, 4/8/16 nodes per tile, 4 or 8 persistent
- * workgroups per compute unit or one workgroup per tile) and keeps the
- * fastest.  The trial steps ADVANCE every context's state: re-init the
- * states afterwards to restart from the initial condition. */
+/* Times trial_steps steps for each candidate tiling and keeps the fastest:
+ * samples per lane 1 or 2 (blocks of 64 or 128 samples; the samples left
+ * at the end of a mesh, 64 or 32, form a tail block run on the lower lanes
+ * of a wave) and, with 2, the tail blocks in the same launch or in a second
+ * launch per step.  Every tiling has one workgroup per tile of 4 nodes.
+ * The trial steps ADVANCE every context's state: re-init the states
+ * afterwards to restart from the initial condition. */
 int32_t ens_batch_autotune(ens_batch* b, int32_t trial_steps);
 
 #ifdef __cplusplus

@@ -118,6 +118,9 @@ struct ens_ctx {
   double omega2 = 0.0;
   // state
   bool state_init = false, started = false, u0_zero = true;
+  // rising bits may be set: wave-per-node steps (padded width >= 64) and
+  // batched steps track the peak through them, lane-group steps do not
+  bool mask_live = false;
   int cur = 0;
   double dt = 0.0;
   int64_t steps = 0;
@@ -902,6 +905,7 @@ int32_t ens_init_state(ens_ctx* ctx, const double* u0, const double* v0) {
                          ctx->p<float>(L.uh[0]), uc, ctx->p<double>(L.q), st));
   }
   HIPC(hipMemset(ctx->p<void>(L.qmask), 0, sizeof(uint64_t) * ctx->n_nodes * ((ld + 63) / 64)));
+  ctx->mask_live = false;
   HIPC(hipMemset(ctx->p<void>(L.base), 0, sizeof(int64_t)));
   HIPC(hipDeviceSynchronize());
   ctx->cur = 0;
@@ -950,12 +954,13 @@ int32_t run_starter(ens_ctx* ctx, double dt, hipStream_t st) {
 // Fold the open rises into q so q holds every sample's running peak.
 int32_t resolve_qoi(ens_ctx* ctx) {
   const Layout& L = ctx->L;
+  if (ctx->SB < 64 && !ctx->mask_live) return ENS_OK;  // q is already up to date
   if (ctx->state_prec == ENS_STATE_F64)
-    HIPC(launch_qoi_resolve((int32_t)ctx->n_nodes, ctx->ld, ctx->SB, ctx->p<double>(L.radial),
+    HIPC(launch_qoi_resolve((int32_t)ctx->n_nodes, ctx->ld, ctx->p<double>(L.radial),
                             ctx->p<double>(L.u[ctx->cur]), nullptr, nullptr, ctx->p<double>(L.q),
                             ctx->p<uint64_t>(L.qmask), nullptr));
   else
-    HIPC(launch_qoi_resolve((int32_t)ctx->n_nodes, ctx->ld, ctx->SB, ctx->p<double>(L.radial), nullptr,
+    HIPC(launch_qoi_resolve((int32_t)ctx->n_nodes, ctx->ld, ctx->p<double>(L.radial), nullptr,
                             ctx->p<float>(L.uh[ctx->cur]),
                             ctx->state_prec == ENS_STATE_F32_KAHAN ? ctx->p<float>(L.uc) : nullptr,
                             ctx->p<double>(L.q), ctx->p<uint64_t>(L.qmask), nullptr));
@@ -1006,6 +1011,15 @@ int32_t ens_step(ens_ctx* ctx, int64_t n_steps, double dt, int32_t force, void* 
     ctx->started = true;
     ctx->dt = dt;
     ctx->gen++;
+  }
+  if (qoi && ctx->mask_live && ctx->SB < 64) {
+    // lane-group steps keep q up to date and leave the rising bits alone:
+    // fold in the rises that batched steps left open, then clear the bits
+    HIPC(hipDeviceSynchronize());
+    const int32_t rc = resolve_qoi(ctx);
+    if (rc != ENS_OK) return rc;
+    HIPC(hipMemset(ctx->p<void>(L.qmask), 0, sizeof(uint64_t) * ctx->n_nodes * ((ctx->ld + 63) / 64)));
+    ctx->mask_live = false;
   }
   int64_t left = n_steps;
   // plain steps go in replays of a captured graph of kGraphSteps steps
@@ -1432,6 +1446,7 @@ int32_t ens_load(ens_ctx* ctx, const void* host, size_t bytes) {
   }
   HIPC(hipMemcpy(ctx->p<void>(L.q), o, sizeof(double) * nq, hipMemcpyHostToDevice));
   HIPC(hipMemcpy(ctx->p<void>(L.base), &hd.steps, sizeof(int64_t), hipMemcpyHostToDevice));
+  ctx->mask_live = false;
   HIPC(hipMemset(ctx->p<void>(L.qmask), 0, sizeof(uint64_t) * ctx->n_nodes * ((ctx->ld + 63) / 64)));
   HIPC(hipMemset(&ctx->p<Flags>(L.flags)->unstable, 0, sizeof(int32_t)));
   HIPC(hipDeviceSynchronize());
@@ -1476,8 +1491,9 @@ int32_t ens_set_tuning(ens_ctx* ctx, int32_t sample_block, int32_t sb_inner) {
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-// Batching: several contexts stepped by one persistent launch per step, the
-// step loop captured in a hipGraph, tiling chosen by a timing autotuner.
+// Batching: several contexts stepped by one launch per step (or one per lane
+// class), the step loop captured in a hipGraph, tiling chosen by a timing
+// autotuner.
 // ---------------------------------------------------------------------------
 
 struct ens_batch {
@@ -1486,13 +1502,12 @@ struct ens_batch {
   bool apply_f32 = false, qoi = true;
   int mode = 0;
   // tuning
-  int spl = 1, tile_nodes = 16, grid = 1024;
+  int spl = 1, tile_nodes = 4;  // nodes per tile: one per wave of the workgroup
   double tuned_ms = 0.0;
   // device tables (small, owned)
   BatchTile* d_tiles = nullptr;
-  int32_t n_tiles = 0, n_wide = 0;  // tiles [0, n_wide) have 2 samples per lane
-  bool one_per_tile = false;        // grid = one workgroup per tile
-  bool split = false;               // spl = 2: one launch per lane class instead of one per step
+  int32_t n_tiles = 0, n_wide = 0;  // tiles [0, n_wide) are full blocks of 64 * spl samples
+  bool split = false;               // one launch per lane class (full, tail) instead of one per step
   size_t tiles_cap = 0;
   StepArgs* d_desc = nullptr;
   std::vector<int> desc_cur;
@@ -1528,19 +1543,22 @@ void drop_graph(ens_batch* b) {
   b->graph = nullptr;
 }
 
-// Tiles of `tile_nodes` consecutive nodes times one sample block, mesh by
-// mesh, node-fastest.  With spl = 2 a mesh's samples go in blocks of 128
-// (2 per lane) plus a last block of 64 when S_pad is an odd multiple of 64.
+// Tiles of `tile_nodes` (= 4, one per wave) consecutive nodes times one
+// sample block, mesh by mesh, node-fastest.  With spl = 2 a mesh's samples
+// go in blocks of 128 (2 per lane) while 128 remain, then a tail block of 64
+// or 32; with spl = 1 in blocks of 64 and a last one of 32 when the padded
+// width is an odd multiple of 32.  Tail blocks go after the full ones.
 int32_t build_tiles(ens_batch* b) {
   std::vector<BatchTile> wide, narrow;  // 2 samples per lane, then 1
   for (size_t m = 0; m < b->ctx.size(); ++m) {
     const ens_ctx* c = b->ctx[m];
     for (int s0 = 0; s0 < c->ld;) {
-      const int spl = (b->spl == 2 && s0 + 128 <= c->ld) ? 2 : 1;
+      const int blk = 64 * b->spl;
+      const bool full = s0 + blk <= c->ld;
       for (int64_t n0 = 0; n0 < c->n_nodes; n0 += b->tile_nodes)
-        (spl == 2 ? wide : narrow)
+        (full ? wide : narrow)
             .push_back(BatchTile{(int32_t)m, (int32_t)n0, (int32_t)std::min<int64_t>(b->tile_nodes, c->n_nodes - n0), s0});
-      s0 += 64 * spl;
+      s0 += full ? blk : 64;
     }
   }
   b->n_wide = (int32_t)wide.size();
@@ -1598,19 +1616,19 @@ int32_t enqueue_steps(ens_batch* b, int64_t k_total) {
     const int k = (int)std::min<int64_t>(k_total - done, kChunk);
     for (ens_ctx* c : b->ctx)
       BHIPC(launch_schedule(c->p<double>(c->L.gtab), c->p<int64_t>(c->L.base), k, c->dt, c->sched, b->st));
-    // one launch per step covers both lane classes (the 64-sample blocks on
-    // half waves), or, split, one launch per class
-    auto grid_of = [&](int32_t n) { return b->one_per_tile ? (int)((n + 7) / 8 * 8) : b->grid; };
-    const int32_t n_narrow = b->n_tiles - b->n_wide;
+    // one launch per step covers both lane classes (the tail blocks on the
+    // lower lanes), or, split, one launch for the full blocks and one with a
+    // sample per lane for the tails
+    const int32_t n_tail = b->n_tiles - b->n_wide;
     for (int j = 0; j < k; ++j) {
-      if (b->split && b->n_wide > 0 && n_narrow > 0) {
-        BHIPC(launch_batch_step(b->d_tiles, b->n_wide, b->n_wide, 2, b->d_desc, j, b->apply_f32, b->mode, b->qoi,
-                                grid_of(b->n_wide), b->st));
-        BHIPC(launch_batch_step(b->d_tiles + b->n_wide, n_narrow, 0, 1, b->d_desc, j, b->apply_f32, b->mode,
-                                b->qoi, grid_of(n_narrow), b->st));
+      if (b->split && b->n_wide > 0 && n_tail > 0) {
+        BHIPC(launch_batch_step(b->d_tiles, b->n_wide, b->n_wide, b->spl, b->d_desc, j, b->apply_f32, b->mode,
+                                b->qoi, b->st));
+        BHIPC(launch_batch_step(b->d_tiles + b->n_wide, n_tail, 0, 1, b->d_desc, j, b->apply_f32, b->mode,
+                                b->qoi, b->st));
       } else {
-        BHIPC(launch_batch_step(b->d_tiles, b->n_tiles, b->n_wide, b->n_wide > 0 ? 2 : 1, b->d_desc, j,
-                                b->apply_f32, b->mode, b->qoi, grid_of(b->n_tiles), b->st));
+        BHIPC(launch_batch_step(b->d_tiles, b->n_tiles, b->n_wide, b->spl, b->d_desc, j, b->apply_f32, b->mode,
+                                b->qoi, b->st));
       }
     }
     for (ens_ctx* c : b->ctx) BHIPC(launch_advance(c->p<int64_t>(c->L.base), k, b->st));
@@ -1623,6 +1641,7 @@ void after_steps(ens_batch* b, int64_t n) {
   for (ens_ctx* c : b->ctx) {
     c->steps += n;
     if (n & 1) c->cur ^= 1;
+    if (b->qoi && n > 0) c->mask_live = true;
   }
 }
 
@@ -1637,7 +1656,6 @@ int32_t ens_batch_create(ens_ctx** ctxs, int32_t n, ens_batch** out) {
   if (!b) return ENS_EINVAL;
   b->ctx.assign(ctxs, ctxs + n);
   const ens_ctx* c0 = ctxs[0];
-  bool all128 = true;
   for (int i = 0; i < n; ++i) {
     const ens_ctx* c = ctxs[i];
     std::string why;
@@ -1651,7 +1669,8 @@ int32_t ens_batch_create(ens_ctx** ctxs, int32_t n, ens_batch** out) {
     else if (c->energy_every != 0) why = "energy records are not available in batched stepping";
     else if (c->geom_every != 0) why = "the geometry refresh is not available in batched stepping";
     else if (use_shared(c)) why = "batched stepping uses the element-by-element variant only";
-    else if (c->ld % 64 != 0) why = "padded width must be a multiple of 64 (ens_set_tuning(ctx, 64, 0) before binding)";
+    else if (c->ld % 32 != 0)
+      why = "padded width must be a multiple of 32 (ens_set_tuning(ctx, 32, 0) or wider before binding)";
     for (int j = 0; j < i && why.empty(); ++j)
       if (ctxs[j] == c) why = "context listed twice";
     if (!why.empty()) {
@@ -1659,27 +1678,20 @@ int32_t ens_batch_create(ens_ctx** ctxs, int32_t n, ens_batch** out) {
       if (c) const_cast<ens_ctx*>(c)->err = "ens_batch_create: mesh " + std::to_string(i) + ": " + why;
       return ENS_EINVAL;
     }
-    if (c->ld % 128 != 0) all128 = false;
   }
   b->device = c0->device;
   b->apply_f32 = c0->apply_prec == ENS_F32;
   b->mode = c0->state_prec;
   b->qoi = (c0->qoi_mask & ENS_QOI_PEAK_RADIAL) != 0;
   b->spl = 2;
-  (void)all128;
   b->desc_cur.assign(n, -1);
   b->desc_gen.assign(n, ~0ull);
-  int cus = 256;
-  hipDeviceProp_t prop;
-  if (hipSetDevice(b->device) != hipSuccess || hipGetDeviceProperties(&prop, b->device) != hipSuccess ||
-      hipStreamCreate(&b->st) != hipSuccess || hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+  if (hipSetDevice(b->device) != hipSuccess || hipStreamCreate(&b->st) != hipSuccess || hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess ||
       hipMalloc(&b->d_desc, sizeof(StepArgs) * 2 * n) != hipSuccess) {
     delete b;
     return ENS_EDEVICE;
   }
-  cus = prop.multiProcessorCount;
-  b->grid = 8 * cus;
   if (build_tiles(b) != ENS_OK) {
     delete b;
     return ENS_EDEVICE;
@@ -1711,7 +1723,7 @@ int32_t ens_batch_info(ens_batch* b, ens_batch_info_t* out) {
   out->n_tiles = b->n_tiles;
   out->samples_per_lane = b->spl;
   out->tile_nodes = b->tile_nodes;
-  out->grid = b->one_per_tile ? 0 : b->grid;
+  out->grid = 0;
   out->graph_steps = b->graph_k;
   out->launches_per_step = (b->split && b->n_wide > 0 && b->n_wide < b->n_tiles) ? 2 : 1;
   out->tuned_ms_per_step = b->tuned_ms;
@@ -1737,7 +1749,7 @@ int32_t ens_batch_step(ens_batch* b, int64_t n_steps, void* stream) {
     }
     std::vector<uint64_t> gen(b->ctx.size());
     for (size_t m = 0; m < b->ctx.size(); ++m) gen[m] = b->ctx[m]->gen;
-    const int sig[3] = {b->spl * (b->split ? -1 : 1), b->tile_nodes, b->one_per_tile ? -1 : b->grid};
+    const int sig[3] = {b->spl * (b->split ? -1 : 1), b->tile_nodes, 0};
     if (b->exec && (gen != b->graph_gen || std::memcmp(sig, b->graph_sig, sizeof sig) != 0)) drop_graph(b);
     int64_t left = n_steps;
     if (left >= b->graph_k) {
@@ -1780,59 +1792,47 @@ int32_t ens_batch_autotune(ens_batch* b, int32_t trial_steps) {
     int32_t rc = check_ready(b);
     if (rc != ENS_OK) return rc;
     BHIPC(hipSetDevice(b->device));
-    hipDeviceProp_t prop;
-    BHIPC(hipGetDeviceProperties(&prop, b->device));
-    const int cus = prop.multiProcessorCount;
     hipEvent_t e0, e1;
     BHIPC(hipEventCreate(&e0));
     BHIPC(hipEventCreate(&e1));
     double best = 1e300;
-    int bs = b->spl, bt = b->tile_nodes, bg = b->grid;
-    int bone = b->one_per_tile ? 1 : 0, bsplit = b->split ? 1 : 0;
+    int bs = b->spl;
+    int bsplit = b->split ? 1 : 0;
     for (int mode : {1, 2, 3}) {  // 1: one sample per lane; 2: two, one launch; 3: two, a launch per class
       const int spl = mode == 1 ? 1 : 2;
-      for (int tn : {4, 8, 16}) {
-        for (int gm : {0, 4, 8}) {  // 0: one workgroup per tile
-          b->split = mode == 3;
-          b->spl = spl;
-          b->tile_nodes = tn;
-          b->one_per_tile = gm == 0;
-          b->grid = (gm ? gm : 8) * cus;
-          rc = build_tiles(b);
-          if (rc == ENS_OK) rc = build_desc(b);
-          if (rc != ENS_OK) break;
-          rc = enqueue_steps(b, 2);  // warm-up, even: parities unchanged
-          if (rc != ENS_OK) break;
-          after_steps(b, 2);
-          BHIPC(hipEventRecord(e0, b->st));
-          rc = enqueue_steps(b, trial_steps);
-          if (rc != ENS_OK) break;
-          BHIPC(hipEventRecord(e1, b->st));
-          BHIPC(hipEventSynchronize(e1));
-          after_steps(b, trial_steps);
-          float ms = 0.f;
-          BHIPC(hipEventElapsedTime(&ms, e0, e1));
-          if (ms / trial_steps < best) {
-            best = ms / trial_steps;
-            bs = spl;
-            bt = tn;
-            bg = b->grid;
-            bone = gm == 0 ? 1 : 0;
-            bsplit = mode == 3 ? 1 : 0;
-          }
-          if (trial_steps & 1) build_desc(b);
-        }
+      b->split = mode == 3;
+      b->spl = spl;
+      rc = build_tiles(b);
+      if (rc == ENS_OK) rc = build_desc(b);
+      if (rc == ENS_OK) rc = enqueue_steps(b, 2);  // warm-up, even: parities unchanged
+      if (rc != ENS_OK) break;
+      after_steps(b, 2);
+      hipError_t e = hipEventRecord(e0, b->st);
+      if (e == hipSuccess) rc = enqueue_steps(b, trial_steps);
+      if (rc != ENS_OK) break;
+      if (e == hipSuccess) e = hipEventRecord(e1, b->st);
+      if (e == hipSuccess) e = hipEventSynchronize(e1);
+      float ms = 0.f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) {
+        rc = b->fail(ENS_EDEVICE, std::string("ens_batch_autotune: ") + hipGetErrorString(e));
+        break;
+      }
+      after_steps(b, trial_steps);
+      if (ms / trial_steps < best) {
+        best = ms / trial_steps;
+        bs = spl;
+        bsplit = mode == 3 ? 1 : 0;
+      }
+      if (trial_steps & 1) {
+        rc = build_desc(b);
         if (rc != ENS_OK) break;
       }
-      if (rc != ENS_OK) break;
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != ENS_OK) return rc;
     b->spl = bs;
-    b->tile_nodes = bt;
-    b->grid = bg;
-    b->one_per_tile = bone != 0;
     b->split = bsplit != 0;
     b->tuned_ms = best;
     rc = build_tiles(b);

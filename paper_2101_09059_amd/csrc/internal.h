@@ -171,13 +171,14 @@ hipError_t launch_starter_f32(int32_t n_nodes, int32_t ld, const float* R, const
 hipError_t launch_split_f32(int64_t n, const double* u0, float* uh, float* uc, hipStream_t st);
 hipError_t launch_qoi_init(int32_t n_nodes, int32_t ld, const double* radial, const double* u_f64,
                            const float* uh, const float* uc, double* q, hipStream_t st);
-// spl samples per lane; with spl = 2, tiles [n_wide, n_tiles) are 64-sample
-// blocks run on half a wave
+// spl samples per lane; tiles [n_wide, n_tiles) are tail blocks of
+// min(64, ld - sample0) samples run on the lower lanes of a wave
 hipError_t launch_batch_step(const BatchTile* tiles, int32_t n_tiles, int32_t n_wide, int spl, const StepArgs* desc,
-                             int32_t j, bool apply_f32, int mode, bool qoi, int grid, hipStream_t st);
-hipError_t launch_qoi_resolve(int32_t n_nodes, int32_t ld, int sample_block, const double* radial,
-                              const double* u_f64, const float* uh, const float* uc, double* q,
-                              const uint64_t* qmask, hipStream_t st);
+                             int32_t j, bool apply_f32, int mode, bool qoi, hipStream_t st);
+// Folds each sample's open rise (its rising bit) into q.
+hipError_t launch_qoi_resolve(int32_t n_nodes, int32_t ld, const double* radial, const double* u_f64,
+                              const float* uh, const float* uc, double* q, const uint64_t* qmask,
+                              hipStream_t st);
 hipError_t launch_combine_f32(int64_t n, const float* uh, const float* uc, double* out,
                               hipStream_t st);
 // out_row: optional row of each node in the outputs (nullptr: node i -> row i)

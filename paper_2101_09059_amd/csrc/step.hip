@@ -80,18 +80,6 @@ __device__ __forceinline__ ConstPtr<T> cst(const T* ptr) {
   return (ConstPtr<T>)ptr;
 }
 
-// Copy of an argument block from a device table, word by word through the
-// constant address space (scalar loads for a uniform table index).
-__device__ __forceinline__ StepArgs load_args(const StepArgs* src) {
-  static_assert(sizeof(StepArgs) % 8 == 0, "argument block is copied in 8-byte words");
-  const ConstPtr<unsigned long long> w = (ConstPtr<unsigned long long>)cst(src);
-  StepArgs a;
-  unsigned long long* d = reinterpret_cast<unsigned long long*>(&a);
-#pragma unroll
-  for (int i = 0; i < (int)(sizeof(StepArgs) / 8); ++i) d[i] = w[i];
-  return a;
-}
-
 // Move a wave-uniform value into a scalar register.  Where the compiler
 // already loads it through the scalar unit this folds away; where it had to
 // use a vector load (arrays reached through a device table may alias the
@@ -796,14 +784,16 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
   }
 }
 
-// Batched step: one launch per step for every mesh of a batch.  Persistent
-// workgroups walk a list of tiles (mesh, first node, node count, first
-// sample) ordered mesh by mesh and node-fastest; each XCD takes a
-// contiguous eighth of the list and its workgroups sweep it in order, so
-// tiles that share neighbours run close in time on one L2.  Each wave takes
-// every 4th node of a tile with 64 lanes x SPL samples; with SPL = 2, tiles
-// from n_wide on hold the 64-sample block that ends an odd multiple of 64
-// and run on the wave's lower 32 lanes (one kernel, one register budget).
+// Batched step: one launch per step for every mesh of a batch, one
+// workgroup per tile (mesh, first node, node count <= 4, first sample) of a
+// list ordered mesh by mesh and node-fastest; workgroups are dealt to the 8
+// XCDs so that each XCD takes a contiguous eighth of the list (tiles that
+// share neighbours run close in time on one L2).  Each wave takes one node
+// of its tile (no loop: a node loop keeps hoisted addresses live and costs
+// a wave per SIMD) with 64 lanes x SPL samples.  Tiles from n_wide on hold
+// the last samples of a mesh when fewer than 64 x SPL remain (64 or 32 at
+// SPL = 2, 32 at SPL = 1 for a padded width that is an odd multiple of 32)
+// and run on the wave's lower lanes (one kernel, one register budget).
 // Per-mesh arguments come from a device table indexed by mesh and by the
 // parity of the step (which state buffer is current).
 template <typename AT, int MODE, int SPL, bool QOI>
@@ -812,29 +802,26 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(const BatchTile* __restri
                                                        int32_t j) {
   const int wave = threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
-  const int per = gridDim.x >> 3;
   const int x = blockIdx.x & 7, rank = blockIdx.x >> 3;
-  const int beg = (int)(((int64_t)n_tiles * x) >> 3);
-  const int end = (int)(((int64_t)n_tiles * (x + 1)) >> 3);
-#pragma nounroll
-  for (int t = beg + rank; t < end; t += per) {
-    // tile and mesh arguments are uniform: keep them in scalar registers
-    const ConstPtr<BatchTile> tile = cst(tiles) + t;
-    const int mesh = __builtin_amdgcn_readfirstlane(tile->mesh);
-    const int node0 = __builtin_amdgcn_readfirstlane(tile->node0);
-    const int count = __builtin_amdgcn_readfirstlane(tile->count);
-    const int sample0 = __builtin_amdgcn_readfirstlane(tile->sample0);
-    const StepArgs p = load_args(desc + 2 * mesh + (j & 1));
-    const bool half = SPL == 2 && t >= n_wide;
-#pragma nounroll
-    for (int n = wave; n < count; n += kBlock / 64) {
-      const int node = __builtin_amdgcn_readfirstlane(node0 + n);
-      double e_loc[SPL];
-      if (!half || lane < 32)
-        step_node<AT, MODE, 64, SPL, QOI, false, false, false, false>(p, j, node, sample0, lane, e_loc,
-                                                                      half ? 1 : SPL);
-    }
-  }
+  const int t = (int)(((int64_t)n_tiles * x) >> 3) + rank;
+  if (t >= (int)(((int64_t)n_tiles * (x + 1)) >> 3)) return;  // uniform over the workgroup
+  // tile and mesh arguments are uniform: keep them in scalar registers
+  const ConstPtr<BatchTile> tile = cst(tiles) + t;
+  const int mesh = __builtin_amdgcn_readfirstlane(tile->mesh);
+  const int count = __builtin_amdgcn_readfirstlane(tile->count);
+  if (wave >= count) return;
+  const int node = __builtin_amdgcn_readfirstlane(tile->node0 + wave);
+  const int sample0 = __builtin_amdgcn_readfirstlane(tile->sample0);
+  // the mesh's arguments are read in place (scalar loads where they are
+  // used) rather than copied: a copy holds them all in registers
+  const StepArgs& p = *(const StepArgs*)(cst(desc) + 2 * mesh + (j & 1));
+  // a tail tile covers min(64, ld - sample0) samples on as many lanes as
+  // that takes, within the block's first rising-bit word
+  const bool tail = t >= n_wide;
+  const int lanes = tail ? min(64, p.ld - sample0) / SPL : 64;
+  double e_loc[SPL];
+  if (lane < lanes)
+    step_node<AT, MODE, 64, SPL, QOI, false, false, false, true>(p, j, node, sample0, lane, e_loc, tail ? 1 : SPL);
 }
 
 // Stand-alone apply; with MAP the rows of U and R are in the numbering
@@ -1211,9 +1198,13 @@ hipError_t launch_apply(const StepArgs& a, bool f32, int sample_block, bool shar
 }
 
 hipError_t launch_batch_step(const BatchTile* tiles, int32_t n_tiles, int32_t n_wide, int spl, const StepArgs* desc,
-                             int32_t j, bool apply_f32, int mode, bool qoi, int grid, hipStream_t st) {
+                             int32_t j, bool apply_f32, int mode, bool qoi, hipStream_t st) {
   if (n_tiles == 0) return hipSuccess;
-  if (grid % 8 != 0 || (spl != 1 && spl != 2)) return hipErrorInvalidValue;
+  if (n_tiles < 0 || n_wide < 0 || n_wide > n_tiles || (spl != 1 && spl != 2)) return hipErrorInvalidValue;
+  // One workgroup per tile: eight equal slices of workgroups (one per XCD
+  // under round-robin dispatch), each covering a contiguous eighth of the
+  // tile list.
+  const int grid = (int)(((int64_t)n_tiles + 7) / 8 * 8);
 #define ENSFEM_BATCH_Q(AT, MODE, SPL)                                                                     \
   do {                                                                                                    \
     if (qoi) k_batch_step<AT, MODE, SPL, true><<<grid, kBlock, 0, st>>>(tiles, n_tiles, n_wide, desc, j); \
@@ -1312,11 +1303,11 @@ hipError_t launch_qoi_init(int32_t n_nodes, int32_t ld, const double* radial, co
   return hipGetLastError();
 }
 
-hipError_t launch_qoi_resolve(int32_t n_nodes, int32_t ld, int sample_block, const double* radial,
-                              const double* u_f64, const float* uh, const float* uc, double* q,
-                              const uint64_t* qmask, hipStream_t st) {
+hipError_t launch_qoi_resolve(int32_t n_nodes, int32_t ld, const double* radial, const double* u_f64,
+                              const float* uh, const float* uc, double* q, const uint64_t* qmask,
+                              hipStream_t st) {
   const int64_t n = (int64_t)n_nodes * ld;
-  if (n == 0 || sample_block < 64) return hipSuccess;
+  if (n == 0) return hipSuccess;
   k_qoi_resolve<<<grid_for(n, 256), 256, 0, st>>>(n_nodes, ld, radial, u_f64, uh, uc, q, qmask);
   return hipGetLastError();
 }

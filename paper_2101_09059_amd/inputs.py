@@ -423,6 +423,6 @@ def kl_fields(mesh: Mesh, lam: np.ndarray, phi: np.ndarray, xi_E: np.ndarray, xi
 CONFIGS["c5_learned"] = dict(R=1.0, L=10.0, n_theta=400, n_z=500, n_modes=64, p0=1.33e5, ramp="sine_pulse",
                              T_ramp=0.02, period=1.0, pulse_amp=0.3, window=0.03, nu=0.49, shear_k=5.0 / 6.0,
                              rho=1.0, alpha=50.0, safety=0.9, width=1024, n_hidden=3, n_train=4096,
-                             n_hf=256, n_lf=65536, n_ref=8192, epochs=600, batch=256, lr=1e-3,
+                             n_hf=1024, n_lf=65536, n_ref=8192, epochs=600, batch=256, lr=1e-3,
                              weight_decay=3.0, val=0.1,
                              seeds=dict(train=5, hf=6, lf=7, ref=8, init=9))
