@@ -1507,6 +1507,7 @@ struct ens_batch {
   // device tables (small, owned)
   BatchTile* d_tiles = nullptr;
   int32_t n_tiles = 0, n_wide = 0;  // tiles [0, n_wide) are full blocks of 64 * spl samples
+  int32_t n_pairs = 0;              // then 32-sample blocks on lane groups, after the n_tiles
   bool split = false;               // one launch per lane class (full, tail) instead of one per step
   size_t tiles_cap = 0;
   StepArgs* d_desc = nullptr;
@@ -1547,31 +1548,38 @@ void drop_graph(ens_batch* b) {
 // sample block, mesh by mesh, node-fastest.  With spl = 2 a mesh's samples
 // go in blocks of 128 (2 per lane) while 128 remain, then a tail block of 64
 // or 32; with spl = 1 in blocks of 64 and a last one of 32 when the padded
-// width is an odd multiple of 32.  Tail blocks go after the full ones.
+// width is an odd multiple of 32.  Full blocks come first, then the tails;
+// a 32-sample tail goes to the lane-group kernel in tiles of 8 nodes
+// (stored after the others).
 int32_t build_tiles(ens_batch* b) {
-  std::vector<BatchTile> wide, narrow;  // 2 samples per lane, then 1
+  std::vector<BatchTile> wide, narrow, pairs;
   for (size_t m = 0; m < b->ctx.size(); ++m) {
     const ens_ctx* c = b->ctx[m];
     for (int s0 = 0; s0 < c->ld;) {
       const int blk = 64 * b->spl;
       const bool full = s0 + blk <= c->ld;
-      for (int64_t n0 = 0; n0 < c->n_nodes; n0 += b->tile_nodes)
-        (full ? wide : narrow)
-            .push_back(BatchTile{(int32_t)m, (int32_t)n0, (int32_t)std::min<int64_t>(b->tile_nodes, c->n_nodes - n0), s0});
+      const bool pair = ENSFEM_BATCH_PAIRS && c->ld - s0 < 64;
+      const int tn = pair ? 2 * b->tile_nodes : b->tile_nodes;
+      std::vector<BatchTile>& dst = full ? wide : pair ? pairs : narrow;
+      for (int64_t n0 = 0; n0 < c->n_nodes; n0 += tn)
+        dst.push_back(BatchTile{(int32_t)m, (int32_t)n0, (int32_t)std::min<int64_t>(tn, c->n_nodes - n0), s0});
       s0 += full ? blk : 64;
     }
   }
   b->n_wide = (int32_t)wide.size();
+  b->n_tiles = (int32_t)(wide.size() + narrow.size());
+  b->n_pairs = (int32_t)pairs.size();
   std::vector<BatchTile> tiles(wide);
   tiles.insert(tiles.end(), narrow.begin(), narrow.end());
+  tiles.insert(tiles.end(), pairs.begin(), pairs.end());
   if (tiles.size() > b->tiles_cap) {
     if (b->d_tiles) BHIPC(hipFree(b->d_tiles));
     b->d_tiles = nullptr;
     BHIPC(hipMalloc(&b->d_tiles, sizeof(BatchTile) * tiles.size()));
     b->tiles_cap = tiles.size();
   }
-  BHIPC(hipMemcpy(b->d_tiles, tiles.data(), sizeof(BatchTile) * tiles.size(), hipMemcpyHostToDevice));
-  b->n_tiles = (int32_t)tiles.size();
+  if (!tiles.empty())
+    BHIPC(hipMemcpy(b->d_tiles, tiles.data(), sizeof(BatchTile) * tiles.size(), hipMemcpyHostToDevice));
   drop_graph(b);
   return ENS_OK;
 }
@@ -1630,6 +1638,8 @@ int32_t enqueue_steps(ens_batch* b, int64_t k_total) {
         BHIPC(launch_batch_step(b->d_tiles, b->n_tiles, b->n_wide, b->spl, b->d_desc, j, b->apply_f32, b->mode,
                                 b->qoi, b->st));
       }
+      BHIPC(launch_batch_pairs(b->d_tiles + b->n_tiles, b->n_pairs, b->d_desc, j, b->apply_f32, b->mode, b->qoi,
+                               b->st));
     }
     for (ens_ctx* c : b->ctx) BHIPC(launch_advance(c->p<int64_t>(c->L.base), k, b->st));
     done += k;
@@ -1720,12 +1730,13 @@ const char* ens_batch_last_error(const ens_batch* b) { return b ? b->err.c_str()
 int32_t ens_batch_info(ens_batch* b, ens_batch_info_t* out) {
   if (!b || !out) return ENS_EINVAL;
   out->n_meshes = (int32_t)b->ctx.size();
-  out->n_tiles = b->n_tiles;
+  out->n_tiles = b->n_tiles + b->n_pairs;
   out->samples_per_lane = b->spl;
   out->tile_nodes = b->tile_nodes;
   out->grid = 0;
   out->graph_steps = b->graph_k;
-  out->launches_per_step = (b->split && b->n_wide > 0 && b->n_wide < b->n_tiles) ? 2 : 1;
+  out->launches_per_step = ((b->split && b->n_wide > 0 && b->n_wide < b->n_tiles) ? 2 : b->n_tiles > 0 ? 1 : 0) +
+                           (b->n_pairs > 0 ? 1 : 0);
   out->tuned_ms_per_step = b->tuned_ms;
   return ENS_OK;
 }

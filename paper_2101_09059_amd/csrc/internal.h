@@ -12,6 +12,11 @@
 namespace ensfem {
 
 constexpr int kBlock = 256;       // threads per workgroup for the ensemble kernels
+// Batched stepping runs 32-sample blocks on lane groups of 32 (two nodes
+// per wave) rather than on the lower half of a wave.
+#ifndef ENSFEM_BATCH_PAIRS
+#define ENSFEM_BATCH_PAIRS 1
+#endif
 // The element that closes a node's fan takes the walk's first neighbour
 // from registers instead of loading it again (host marking and kernels).
 #ifndef ENSFEM_CLOSE_REUSE
@@ -106,7 +111,9 @@ struct StepArgs {
 };
 
 // One work item of the batched step: `count` nodes from `node0` of mesh
-// `mesh`, samples sample0 .. sample0 + 64*spl - 1 (spl fixed per launch).
+// `mesh` (at most 4, one per wave; 8 for 32-sample blocks on lane groups),
+// samples from sample0: a full block of 64 * spl (spl fixed per launch) or
+// a mesh's last min(64, ld - sample0).
 struct BatchTile {
   int32_t mesh;
   int32_t node0;
@@ -176,6 +183,9 @@ hipError_t launch_qoi_init(int32_t n_nodes, int32_t ld, const double* radial, co
 hipError_t launch_batch_step(const BatchTile* tiles, int32_t n_tiles, int32_t n_wide, int spl, const StepArgs* desc,
                              int32_t j, bool apply_f32, int mode, bool qoi, hipStream_t st);
 // Folds each sample's open rise (its rising bit) into q.
+// 32-sample blocks on lane groups of 32 (8 nodes per tile, q kept directly)
+hipError_t launch_batch_pairs(const BatchTile* tiles, int32_t n_tiles, const StepArgs* desc, int32_t j,
+                              bool apply_f32, int mode, bool qoi, hipStream_t st);
 hipError_t launch_qoi_resolve(int32_t n_nodes, int32_t ld, const double* radial, const double* u_f64,
                               const float* uh, const float* uc, double* q, const uint64_t* qmask,
                               hipStream_t st);

@@ -824,6 +824,30 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(const BatchTile* __restri
     step_node<AT, MODE, 64, SPL, QOI, false, false, false, true>(p, j, node, sample0, lane, e_loc, tail ? 1 : SPL);
 }
 
+// Batched step, 32-sample blocks: lane groups of 32, two nodes per wave
+// and eight per workgroup (a 32-sample block on a full wave per node would
+// leave half of every wave idle).  The two nodes of a wave differ, so
+// adjacency and stiffness blocks are vector loads; the running peak is
+// kept in q directly (no rising bits), as in the single-mesh step of a
+// 32-sample block.
+template <typename AT, int MODE, bool QOI>
+__global__ __launch_bounds__(kBlock) void k_batch_step_pairs(const BatchTile* __restrict__ tiles, int32_t n_tiles,
+                                                             const StepArgs* __restrict__ desc, int32_t j) {
+  const int x = blockIdx.x & 7, rank = blockIdx.x >> 3;
+  const int t = (int)(((int64_t)n_tiles * x) >> 3) + rank;
+  if (t >= (int)(((int64_t)n_tiles * (x + 1)) >> 3)) return;  // uniform over the workgroup
+  const ConstPtr<BatchTile> tile = cst(tiles) + t;
+  const int mesh = __builtin_amdgcn_readfirstlane(tile->mesh);
+  const int count = __builtin_amdgcn_readfirstlane(tile->count);
+  const int g = (int)threadIdx.x / 32;
+  if (g >= count) return;
+  const int node = __builtin_amdgcn_readfirstlane(tile->node0) + g;
+  const int sample0 = __builtin_amdgcn_readfirstlane(tile->sample0);
+  const StepArgs& p = *(const StepArgs*)(cst(desc) + 2 * mesh + (j & 1));
+  double e_loc[1];
+  step_node<AT, MODE, 32, 1, QOI, false, false, false, true>(p, j, node, sample0, (int)threadIdx.x % 32, e_loc);
+}
+
 // Stand-alone apply; with MAP the rows of U and R are in the numbering
 // given by map (internal node -> buffer node).
 template <typename AT, int LPN, int SPL, bool SHARED, bool MAP>
@@ -1225,6 +1249,28 @@ hipError_t launch_batch_step(const BatchTile* tiles, int32_t n_tiles, int32_t n_
   if (mode == kStateF32) ENSFEM_BATCH(float, kStateF32);
 #undef ENSFEM_BATCH
 #undef ENSFEM_BATCH_Q
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_pairs(const BatchTile* tiles, int32_t n_tiles, const StepArgs* desc, int32_t j,
+                              bool apply_f32, int mode, bool qoi, hipStream_t st) {
+  if (n_tiles == 0) return hipSuccess;
+  if (n_tiles < 0) return hipErrorInvalidValue;
+  const int grid = (int)(((int64_t)n_tiles + 7) / 8 * 8);
+#define ENSFEM_PAIRS(AT, MODE)                                                                      \
+  do {                                                                                              \
+    if (qoi) k_batch_step_pairs<AT, MODE, true><<<grid, kBlock, 0, st>>>(tiles, n_tiles, desc, j);  \
+    else k_batch_step_pairs<AT, MODE, false><<<grid, kBlock, 0, st>>>(tiles, n_tiles, desc, j);     \
+    return hipGetLastError();                                                                       \
+  } while (0)
+  if (!apply_f32) {
+    if (mode != kStateF64) return hipErrorInvalidValue;
+    ENSFEM_PAIRS(double, kStateF64);
+  }
+  if (mode == kStateF64) ENSFEM_PAIRS(float, kStateF64);
+  if (mode == kStateF32Kahan) ENSFEM_PAIRS(float, kStateF32Kahan);
+  if (mode == kStateF32) ENSFEM_PAIRS(float, kStateF32);
+#undef ENSFEM_PAIRS
   return hipErrorInvalidValue;
 }
 
