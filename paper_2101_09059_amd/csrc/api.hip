@@ -1506,8 +1506,7 @@ struct ens_batch {
   double tuned_ms = 0.0;
   // device tables (small, owned)
   BatchTile* d_tiles = nullptr;
-  int32_t n_tiles = 0, n_wide = 0;  // tiles [0, n_wide) are full blocks of 64 * spl samples
-  int32_t n_pairs = 0;              // then 32-sample blocks on lane groups, after the n_tiles
+  int32_t n_tiles = 0, n_wide = 0;  // split: tiles [0, n_wide) are full blocks, the rest tails
   bool split = false;               // one launch per lane class (full, tail) instead of one per step
   size_t tiles_cap = 0;
   StepArgs* d_desc = nullptr;
@@ -1545,33 +1544,37 @@ void drop_graph(ens_batch* b) {
 }
 
 // Tiles of `tile_nodes` (= 4, one per wave) consecutive nodes times one
-// sample block, mesh by mesh, node-fastest.  With spl = 2 a mesh's samples
-// go in blocks of 128 (2 per lane) while 128 remain, then a tail block of 64
-// or 32; with spl = 1 in blocks of 64 and a last one of 32 when the padded
-// width is an odd multiple of 32.  Full blocks come first, then the tails;
-// a 32-sample tail goes to the lane-group kernel in tiles of 8 nodes
-// (stored after the others).
+// sample block, mesh by mesh.  With spl = 2 a mesh's samples go in blocks
+// of 128 (2 per lane) while 128 remain, then a tail block of 64 or 32; with
+// spl = 1 in blocks of 64 and a last one of 32 when the padded width is an
+// odd multiple of 32.  Within a mesh the order is node tile by node tile
+// with the sample blocks together (or block by block, see
+// ENSFEM_BATCH_NODE_MAJOR).  Split: the full blocks first, then the tails
+// (one launch each); else tails stay in place.
 int32_t build_tiles(ens_batch* b) {
-  std::vector<BatchTile> wide, narrow, pairs;
+  std::vector<BatchTile> wide, narrow;
+  const int blk = 64 * b->spl;
   for (size_t m = 0; m < b->ctx.size(); ++m) {
     const ens_ctx* c = b->ctx[m];
-    for (int s0 = 0; s0 < c->ld;) {
-      const int blk = 64 * b->spl;
-      const bool full = s0 + blk <= c->ld;
-      const bool pair = ENSFEM_BATCH_PAIRS && c->ld - s0 < 64;
-      const int tn = pair ? 2 * b->tile_nodes : b->tile_nodes;
-      std::vector<BatchTile>& dst = full ? wide : pair ? pairs : narrow;
-      for (int64_t n0 = 0; n0 < c->n_nodes; n0 += tn)
-        dst.push_back(BatchTile{(int32_t)m, (int32_t)n0, (int32_t)std::min<int64_t>(tn, c->n_nodes - n0), s0});
-      s0 += full ? blk : 64;
+    std::vector<int> starts;
+    for (int s0 = 0; s0 < c->ld; s0 += s0 + blk <= c->ld ? blk : 64) starts.push_back(s0);
+    auto put = [&](int64_t n0, int s0) {
+      const bool tail = s0 + blk > c->ld;
+      const int32_t cnt = (int32_t)std::min<int64_t>(b->tile_nodes, c->n_nodes - n0);
+      (tail && b->split ? narrow : wide).push_back(BatchTile{(int32_t)m, (int32_t)n0, cnt | (tail ? kTileTail : 0), s0});
+    };
+    if (ENSFEM_BATCH_NODE_MAJOR) {
+      for (int64_t n0 = 0; n0 < c->n_nodes; n0 += b->tile_nodes)
+        for (int s0 : starts) put(n0, s0);
+    } else {
+      for (int s0 : starts)
+        for (int64_t n0 = 0; n0 < c->n_nodes; n0 += b->tile_nodes) put(n0, s0);
     }
   }
   b->n_wide = (int32_t)wide.size();
   b->n_tiles = (int32_t)(wide.size() + narrow.size());
-  b->n_pairs = (int32_t)pairs.size();
   std::vector<BatchTile> tiles(wide);
   tiles.insert(tiles.end(), narrow.begin(), narrow.end());
-  tiles.insert(tiles.end(), pairs.begin(), pairs.end());
   if (tiles.size() > b->tiles_cap) {
     if (b->d_tiles) BHIPC(hipFree(b->d_tiles));
     b->d_tiles = nullptr;
@@ -1629,17 +1632,8 @@ int32_t enqueue_steps(ens_batch* b, int64_t k_total) {
     // sample per lane for the tails
     const int32_t n_tail = b->n_tiles - b->n_wide;
     for (int j = 0; j < k; ++j) {
-      if (b->split && b->n_wide > 0 && n_tail > 0) {
-        BHIPC(launch_batch_step(b->d_tiles, b->n_wide, b->n_wide, b->spl, b->d_desc, j, b->apply_f32, b->mode,
-                                b->qoi, b->st));
-        BHIPC(launch_batch_step(b->d_tiles + b->n_wide, n_tail, 0, 1, b->d_desc, j, b->apply_f32, b->mode,
-                                b->qoi, b->st));
-      } else {
-        BHIPC(launch_batch_step(b->d_tiles, b->n_tiles, b->n_wide, b->spl, b->d_desc, j, b->apply_f32, b->mode,
-                                b->qoi, b->st));
-      }
-      BHIPC(launch_batch_pairs(b->d_tiles + b->n_tiles, b->n_pairs, b->d_desc, j, b->apply_f32, b->mode, b->qoi,
-                               b->st));
+      BHIPC(launch_batch_step(b->d_tiles, b->n_wide, b->spl, b->d_desc, j, b->apply_f32, b->mode, b->qoi, b->st));
+      BHIPC(launch_batch_step(b->d_tiles + b->n_wide, n_tail, 1, b->d_desc, j, b->apply_f32, b->mode, b->qoi, b->st));
     }
     for (ens_ctx* c : b->ctx) BHIPC(launch_advance(c->p<int64_t>(c->L.base), k, b->st));
     done += k;
@@ -1730,13 +1724,12 @@ const char* ens_batch_last_error(const ens_batch* b) { return b ? b->err.c_str()
 int32_t ens_batch_info(ens_batch* b, ens_batch_info_t* out) {
   if (!b || !out) return ENS_EINVAL;
   out->n_meshes = (int32_t)b->ctx.size();
-  out->n_tiles = b->n_tiles + b->n_pairs;
+  out->n_tiles = b->n_tiles;
   out->samples_per_lane = b->spl;
   out->tile_nodes = b->tile_nodes;
   out->grid = 0;
   out->graph_steps = b->graph_k;
-  out->launches_per_step = ((b->split && b->n_wide > 0 && b->n_wide < b->n_tiles) ? 2 : b->n_tiles > 0 ? 1 : 0) +
-                           (b->n_pairs > 0 ? 1 : 0);
+  out->launches_per_step = (b->n_wide > 0 ? 1 : 0) + (b->n_tiles > b->n_wide ? 1 : 0);
   out->tuned_ms_per_step = b->tuned_ms;
   return ENS_OK;
 }

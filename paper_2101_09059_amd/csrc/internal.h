@@ -12,10 +12,11 @@
 namespace ensfem {
 
 constexpr int kBlock = 256;       // threads per workgroup for the ensemble kernels
-// Batched stepping runs 32-sample blocks on lane groups of 32 (two nodes
-// per wave) rather than on the lower half of a wave.
-#ifndef ENSFEM_BATCH_PAIRS
-#define ENSFEM_BATCH_PAIRS 1
+// Batch tile order within a mesh: 1 node tile by node tile with its sample
+// blocks together (a node's stiffness blocks are reused from L2 by its
+// other sample blocks), 0 sample block by sample block.
+#ifndef ENSFEM_BATCH_NODE_MAJOR
+#define ENSFEM_BATCH_NODE_MAJOR 1
 #endif
 // The element that closes a node's fan takes the walk's first neighbour
 // from registers instead of loading it again (host marking and kernels).
@@ -110,16 +111,18 @@ struct StepArgs {
   int32_t pad_;
 };
 
-// One work item of the batched step: `count` nodes from `node0` of mesh
-// `mesh` (at most 4, one per wave; 8 for 32-sample blocks on lane groups),
-// samples from sample0: a full block of 64 * spl (spl fixed per launch) or
-// a mesh's last min(64, ld - sample0).
+// One work item of the batched step: nodes node0 .. node0 + (count &
+// kTileCount) - 1 of mesh `mesh` (at most 4, one per wave), samples from
+// sample0: a full block of 64 * spl (spl fixed per launch) or, with
+// kTileTail set in count, a mesh's last min(64, ld - sample0).
 struct BatchTile {
   int32_t mesh;
   int32_t node0;
   int32_t count;
   int32_t sample0;
 };
+constexpr int32_t kTileCount = 0xff;
+constexpr int32_t kTileTail = 0x100;
 
 // ---- set-up kernels (setup.hip) -------------------------------------------
 // Doubles per element in the frame table written by the element set-up:
@@ -178,14 +181,11 @@ hipError_t launch_starter_f32(int32_t n_nodes, int32_t ld, const float* R, const
 hipError_t launch_split_f32(int64_t n, const double* u0, float* uh, float* uc, hipStream_t st);
 hipError_t launch_qoi_init(int32_t n_nodes, int32_t ld, const double* radial, const double* u_f64,
                            const float* uh, const float* uc, double* q, hipStream_t st);
-// spl samples per lane; tiles [n_wide, n_tiles) are tail blocks of
-// min(64, ld - sample0) samples run on the lower lanes of a wave
-hipError_t launch_batch_step(const BatchTile* tiles, int32_t n_tiles, int32_t n_wide, int spl, const StepArgs* desc,
-                             int32_t j, bool apply_f32, int mode, bool qoi, hipStream_t st);
+// spl samples per lane; tail tiles (kTileTail) hold min(64, ld - sample0)
+// samples run on the lower lanes of a wave
+hipError_t launch_batch_step(const BatchTile* tiles, int32_t n_tiles, int spl, const StepArgs* desc, int32_t j,
+                             bool apply_f32, int mode, bool qoi, hipStream_t st);
 // Folds each sample's open rise (its rising bit) into q.
-// 32-sample blocks on lane groups of 32 (8 nodes per tile, q kept directly)
-hipError_t launch_batch_pairs(const BatchTile* tiles, int32_t n_tiles, const StepArgs* desc, int32_t j,
-                              bool apply_f32, int mode, bool qoi, hipStream_t st);
 hipError_t launch_qoi_resolve(int32_t n_nodes, int32_t ld, const double* radial, const double* u_f64,
                               const float* uh, const float* uc, double* q, const uint64_t* qmask,
                               hipStream_t st);

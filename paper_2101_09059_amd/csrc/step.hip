@@ -785,21 +785,20 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
 }
 
 // Batched step: one launch per step for every mesh of a batch, one
-// workgroup per tile (mesh, first node, node count <= 4, first sample) of a
-// list ordered mesh by mesh and node-fastest; workgroups are dealt to the 8
+// workgroup per tile (mesh, first node, node count <= 4, tail flag, first
+// sample) of a list ordered mesh by mesh; workgroups are dealt to the 8
 // XCDs so that each XCD takes a contiguous eighth of the list (tiles that
 // share neighbours run close in time on one L2).  Each wave takes one node
 // of its tile (no loop: a node loop keeps hoisted addresses live and costs
-// a wave per SIMD) with 64 lanes x SPL samples.  Tiles from n_wide on hold
-// the last samples of a mesh when fewer than 64 x SPL remain (64 or 32 at
+// a wave per SIMD) with 64 lanes x SPL samples.  A tail tile holds the
+// last samples of a mesh when fewer than 64 x SPL remain (64 or 32 at
 // SPL = 2, 32 at SPL = 1 for a padded width that is an odd multiple of 32)
-// and run on the wave's lower lanes (one kernel, one register budget).
+// and runs on the wave's lower lanes (one kernel, one register budget).
 // Per-mesh arguments come from a device table indexed by mesh and by the
 // parity of the step (which state buffer is current).
 template <typename AT, int MODE, int SPL, bool QOI>
 __global__ __launch_bounds__(kBlock) void k_batch_step(const BatchTile* __restrict__ tiles, int32_t n_tiles,
-                                                       int32_t n_wide, const StepArgs* __restrict__ desc,
-                                                       int32_t j) {
+                                                       const StepArgs* __restrict__ desc, int32_t j) {
   const int wave = threadIdx.x / 64;
   const int lane = threadIdx.x % 64;
   const int x = blockIdx.x & 7, rank = blockIdx.x >> 3;
@@ -808,8 +807,8 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(const BatchTile* __restri
   // tile and mesh arguments are uniform: keep them in scalar registers
   const ConstPtr<BatchTile> tile = cst(tiles) + t;
   const int mesh = __builtin_amdgcn_readfirstlane(tile->mesh);
-  const int count = __builtin_amdgcn_readfirstlane(tile->count);
-  if (wave >= count) return;
+  const int cw = __builtin_amdgcn_readfirstlane(tile->count);
+  if (wave >= (cw & kTileCount)) return;
   const int node = __builtin_amdgcn_readfirstlane(tile->node0 + wave);
   const int sample0 = __builtin_amdgcn_readfirstlane(tile->sample0);
   // the mesh's arguments are read in place (scalar loads where they are
@@ -817,35 +816,11 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(const BatchTile* __restri
   const StepArgs& p = *(const StepArgs*)(cst(desc) + 2 * mesh + (j & 1));
   // a tail tile covers min(64, ld - sample0) samples on as many lanes as
   // that takes, within the block's first rising-bit word
-  const bool tail = t >= n_wide;
+  const bool tail = (cw & kTileTail) != 0;
   const int lanes = tail ? min(64, p.ld - sample0) / SPL : 64;
   double e_loc[SPL];
   if (lane < lanes)
     step_node<AT, MODE, 64, SPL, QOI, false, false, false, true>(p, j, node, sample0, lane, e_loc, tail ? 1 : SPL);
-}
-
-// Batched step, 32-sample blocks: lane groups of 32, two nodes per wave
-// and eight per workgroup (a 32-sample block on a full wave per node would
-// leave half of every wave idle).  The two nodes of a wave differ, so
-// adjacency and stiffness blocks are vector loads; the running peak is
-// kept in q directly (no rising bits), as in the single-mesh step of a
-// 32-sample block.
-template <typename AT, int MODE, bool QOI>
-__global__ __launch_bounds__(kBlock) void k_batch_step_pairs(const BatchTile* __restrict__ tiles, int32_t n_tiles,
-                                                             const StepArgs* __restrict__ desc, int32_t j) {
-  const int x = blockIdx.x & 7, rank = blockIdx.x >> 3;
-  const int t = (int)(((int64_t)n_tiles * x) >> 3) + rank;
-  if (t >= (int)(((int64_t)n_tiles * (x + 1)) >> 3)) return;  // uniform over the workgroup
-  const ConstPtr<BatchTile> tile = cst(tiles) + t;
-  const int mesh = __builtin_amdgcn_readfirstlane(tile->mesh);
-  const int count = __builtin_amdgcn_readfirstlane(tile->count);
-  const int g = (int)threadIdx.x / 32;
-  if (g >= count) return;
-  const int node = __builtin_amdgcn_readfirstlane(tile->node0) + g;
-  const int sample0 = __builtin_amdgcn_readfirstlane(tile->sample0);
-  const StepArgs& p = *(const StepArgs*)(cst(desc) + 2 * mesh + (j & 1));
-  double e_loc[1];
-  step_node<AT, MODE, 32, 1, QOI, false, false, false, true>(p, j, node, sample0, (int)threadIdx.x % 32, e_loc);
 }
 
 // Stand-alone apply; with MAP the rows of U and R are in the numbering
@@ -1221,18 +1196,18 @@ hipError_t launch_apply(const StepArgs& a, bool f32, int sample_block, bool shar
              : dispatch_apply_map<double, false>(a, sample_block, U, R, map, st);
 }
 
-hipError_t launch_batch_step(const BatchTile* tiles, int32_t n_tiles, int32_t n_wide, int spl, const StepArgs* desc,
-                             int32_t j, bool apply_f32, int mode, bool qoi, hipStream_t st) {
+hipError_t launch_batch_step(const BatchTile* tiles, int32_t n_tiles, int spl, const StepArgs* desc, int32_t j,
+                             bool apply_f32, int mode, bool qoi, hipStream_t st) {
   if (n_tiles == 0) return hipSuccess;
-  if (n_tiles < 0 || n_wide < 0 || n_wide > n_tiles || (spl != 1 && spl != 2)) return hipErrorInvalidValue;
+  if (n_tiles < 0 || (spl != 1 && spl != 2)) return hipErrorInvalidValue;
   // One workgroup per tile: eight equal slices of workgroups (one per XCD
   // under round-robin dispatch), each covering a contiguous eighth of the
   // tile list.
   const int grid = (int)(((int64_t)n_tiles + 7) / 8 * 8);
 #define ENSFEM_BATCH_Q(AT, MODE, SPL)                                                                     \
   do {                                                                                                    \
-    if (qoi) k_batch_step<AT, MODE, SPL, true><<<grid, kBlock, 0, st>>>(tiles, n_tiles, n_wide, desc, j); \
-    else k_batch_step<AT, MODE, SPL, false><<<grid, kBlock, 0, st>>>(tiles, n_tiles, n_wide, desc, j);   \
+    if (qoi) k_batch_step<AT, MODE, SPL, true><<<grid, kBlock, 0, st>>>(tiles, n_tiles, desc, j); \
+    else k_batch_step<AT, MODE, SPL, false><<<grid, kBlock, 0, st>>>(tiles, n_tiles, desc, j);   \
   } while (0)
 #define ENSFEM_BATCH(AT, MODE)                  \
   do {                                          \
@@ -1249,28 +1224,6 @@ hipError_t launch_batch_step(const BatchTile* tiles, int32_t n_tiles, int32_t n_
   if (mode == kStateF32) ENSFEM_BATCH(float, kStateF32);
 #undef ENSFEM_BATCH
 #undef ENSFEM_BATCH_Q
-  return hipErrorInvalidValue;
-}
-
-hipError_t launch_batch_pairs(const BatchTile* tiles, int32_t n_tiles, const StepArgs* desc, int32_t j,
-                              bool apply_f32, int mode, bool qoi, hipStream_t st) {
-  if (n_tiles == 0) return hipSuccess;
-  if (n_tiles < 0) return hipErrorInvalidValue;
-  const int grid = (int)(((int64_t)n_tiles + 7) / 8 * 8);
-#define ENSFEM_PAIRS(AT, MODE)                                                                      \
-  do {                                                                                              \
-    if (qoi) k_batch_step_pairs<AT, MODE, true><<<grid, kBlock, 0, st>>>(tiles, n_tiles, desc, j);  \
-    else k_batch_step_pairs<AT, MODE, false><<<grid, kBlock, 0, st>>>(tiles, n_tiles, desc, j);     \
-    return hipGetLastError();                                                                       \
-  } while (0)
-  if (!apply_f32) {
-    if (mode != kStateF64) return hipErrorInvalidValue;
-    ENSFEM_PAIRS(double, kStateF64);
-  }
-  if (mode == kStateF64) ENSFEM_PAIRS(float, kStateF64);
-  if (mode == kStateF32Kahan) ENSFEM_PAIRS(float, kStateF32Kahan);
-  if (mode == kStateF32) ENSFEM_PAIRS(float, kStateF32);
-#undef ENSFEM_PAIRS
   return hipErrorInvalidValue;
 }
 
