@@ -244,6 +244,7 @@ def run_batch_config(args, torch):
         e.close()
     per = ms / args.steps
     achieved = bytes_per_step / (per * 1e-3) / 1e9
+    traffic = measured_traffic("c4_batch", "batch_step_f32apply_f64state", bytes_per_step)
     out = {
         "metric": "ensemble dof*sample*steps/s", "value": work_per_step / (per * 1e-3),
         "unit": "dof*sample*steps/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -255,7 +256,8 @@ def run_batch_config(args, torch):
                    "padding_node_samples_per_step": pad_per_step, "batch": info, "parallelism": "single GPU"},
         "ms_per_step_one_mesh_at_a_time": ms_seq,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_batch_step",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic[0] if traffic else None,
+                     "kernel": "k_batch_step (full-block and tail launches of one step)",
                      "algorithmic_bytes_per_launch": bytes_per_step},
     }
     print(json.dumps(out), flush=True)

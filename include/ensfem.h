@@ -318,6 +318,11 @@ int32_t ens_batch_step(ens_batch* b, int64_t n_steps, void* stream);
  * The trial steps ADVANCE every context's state: re-init the states
  * afterwards to restart from the initial condition. */
 int32_t ens_batch_autotune(ens_batch* b, int32_t trial_steps);
+/* Sets the tiling without timing trials: samples_per_lane 1 or 2; split 1
+ * runs the tail blocks in a launch of their own (one sample per lane), 0
+ * in the same launch.  ENS_EINVAL for other values.  Results do not depend
+ * on the tiling. */
+int32_t ens_batch_set_tiling(ens_batch* b, int32_t samples_per_lane, int32_t split);
 
 #ifdef __cplusplus
 }

@@ -1789,6 +1789,20 @@ int32_t ens_batch_step(ens_batch* b, int64_t n_steps, void* stream) {
   }
 }
 
+int32_t ens_batch_set_tiling(ens_batch* b, int32_t samples_per_lane, int32_t split) {
+  if (!b) return ENS_EINVAL;
+  try {
+    if ((samples_per_lane != 1 && samples_per_lane != 2) || (split != 0 && split != 1))
+      return b->fail(ENS_EINVAL, "ens_batch_set_tiling: samples_per_lane must be 1 or 2 and split 0 or 1");
+    BHIPC(hipSetDevice(b->device));
+    b->spl = samples_per_lane;
+    b->split = split != 0;
+    return build_tiles(b);
+  } catch (...) {
+    return b->fail(ENS_EINVAL, "ens_batch_set_tiling: host failure");
+  }
+}
+
 int32_t ens_batch_autotune(ens_batch* b, int32_t trial_steps) {
   if (!b) return ENS_EINVAL;
   try {

@@ -102,6 +102,7 @@ _SIGS = {
     "ens_batch_info": (_I32, [_P, ctypes.POINTER(BatchInfo)]),
     "ens_batch_step": (_I32, [_P, _I64, _P]),
     "ens_batch_autotune": (_I32, [_P, _I32]),
+    "ens_batch_set_tiling": (_I32, [_P, _I32, _I32]),
     "sur_create": (_I32, [_I32, _I32, _I32, _I32, _I32, _I32, ctypes.POINTER(_P)]),
     "sur_destroy": (_I32, [_P]),
     "sur_last_error": (ctypes.c_char_p, [_P]),
@@ -391,6 +392,9 @@ class Batch:
 
     def autotune(self, trial_steps: int = 10):
         self._check(self._lib.ens_batch_autotune(self._h, int(trial_steps)))
+
+    def set_tiling(self, samples_per_lane: int, split: bool = False):
+        self._check(self._lib.ens_batch_set_tiling(self._h, int(samples_per_lane), 1 if split else 0))
 
     def info(self) -> dict:
         inf = BatchInfo()

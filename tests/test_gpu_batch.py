@@ -84,6 +84,35 @@ def test_batch_matches_solo_bitwise(apply_prec, state_prec):
         b.close()
 
 
+@pytest.mark.parametrize("spl,split,state_prec", [(1, False, ensfem.STATE_F64), (1, True, ensfem.STATE_F64),
+                                                   (2, False, ensfem.STATE_F64), (2, True, ensfem.STATE_F64),
+                                                   (2, True, ensfem.STATE_F32_KAHAN), (1, True, ensfem.STATE_F32)])
+def test_batch_tilings_match_solo_bitwise(spl, split, state_prec):
+    """Every tiling (1 or 2 samples per lane; tail blocks in the same launch
+    or their own), switched between batch calls, gives the solo results
+    bit for bit."""
+    say(f"case: batch tiling spl={spl} split={split} state={state_prec}")
+    pairs = _members(ensfem.F32, state_prec)
+    _start(pairs)
+    batch = ensfem.Batch([b for _, b, _ in pairs])
+    for k, (s_, sp_) in enumerate([(spl, split), (3 - spl, not split), (spl, split)]):
+        batch.set_tiling(s_, sp_)
+        n = (70, 33, 64)[k]
+        say(f"  tiling {s_}/{sp_}: {batch.info()}, {n} steps")
+        batch.step(n)
+        for a, b, dt in pairs:
+            a.step(n, dt)
+        for a, b, _ in pairs:
+            assert np.array_equal(a.read_state(), b.read_state())
+            assert np.array_equal(a.read_qoi(), b.read_qoi())
+    with pytest.raises(ensfem.EnsfemError):
+        batch.set_tiling(3, False)
+    batch.close()
+    for a, b, _ in pairs:
+        a.close()
+        b.close()
+
+
 def test_batch_autotune_then_restart():
     say("case: batch autotune")
     pairs = _members(ensfem.F32, ensfem.STATE_F64)
