@@ -300,6 +300,9 @@ typedef struct {
   int32_t launches_per_step; /* 1, or 2 when the two lane classes are
                                 launched separately                      */
   double tuned_ms_per_step; /* best autotuner trial, 0 before autotune   */
+  int32_t concurrent_tails;  /* 1: the tail launches run on a second
+                                stream beside the full blocks          */
+  int32_t reserved_;
 } ens_batch_info_t;
 
 int32_t ens_batch_create(ens_ctx** ctxs, int32_t n, ens_batch** out);
@@ -319,9 +322,10 @@ int32_t ens_batch_step(ens_batch* b, int64_t n_steps, void* stream);
  * afterwards to restart from the initial condition. */
 int32_t ens_batch_autotune(ens_batch* b, int32_t trial_steps);
 /* Sets the tiling without timing trials: samples_per_lane 1 or 2; split 1
- * runs the tail blocks in a launch of their own (one sample per lane), 0
- * in the same launch.  ENS_EINVAL for other values.  Results do not depend
- * on the tiling. */
+ * runs the tail blocks in a launch of their own (one sample per lane), 2
+ * the same on a second stream of the batch beside the full blocks (a
+ * sample column's steps depend only on that column), 0 in the same launch.
+ * ENS_EINVAL for other values.  Results do not depend on the tiling. */
 int32_t ens_batch_set_tiling(ens_batch* b, int32_t samples_per_lane, int32_t split);
 
 #ifdef __cplusplus

@@ -1508,6 +1508,7 @@ struct ens_batch {
   BatchTile* d_tiles = nullptr;
   int32_t n_tiles = 0, n_wide = 0;  // split: tiles [0, n_wide) are full blocks, the rest tails
   bool split = false;               // one launch per lane class (full, tail) instead of one per step
+  bool concurrent = false;          // split: the tail launches on a second stream (st2)
   size_t tiles_cap = 0;
   StepArgs* d_desc = nullptr;
   std::vector<int> desc_cur;
@@ -1520,6 +1521,8 @@ struct ens_batch {
   int graph_sig[3] = {0, 0, 0};
   hipStream_t st = nullptr;
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipStream_t st2 = nullptr;  // concurrent tails
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   std::string err;
   int32_t fail(int32_t code, const std::string& m) {
     err = m;
@@ -1629,11 +1632,26 @@ int32_t enqueue_steps(ens_batch* b, int64_t k_total) {
       BHIPC(launch_schedule(c->p<double>(c->L.gtab), c->p<int64_t>(c->L.base), k, c->dt, c->sched, b->st));
     // one launch per step covers both lane classes (the tail blocks on the
     // lower lanes), or, split, one launch for the full blocks and one with a
-    // sample per lane for the tails
+    // sample per lane for the tails.  Concurrent: the tails of the whole
+    // chunk run on a second stream beside the full blocks (their sample
+    // columns and rising-bit words are disjoint from the full blocks', so
+    // the two chains of steps share nothing but the load factors), joined
+    // before the step counters advance.
     const int32_t n_tail = b->n_tiles - b->n_wide;
+    const bool two = b->concurrent && b->n_wide > 0 && n_tail > 0;
+    hipStream_t ts = b->st;
+    if (two) {
+      BHIPC(hipEventRecord(b->ev_fork, b->st));
+      BHIPC(hipStreamWaitEvent(b->st2, b->ev_fork, 0));
+      ts = b->st2;
+    }
     for (int j = 0; j < k; ++j) {
       BHIPC(launch_batch_step(b->d_tiles, b->n_wide, b->spl, b->d_desc, j, b->apply_f32, b->mode, b->qoi, b->st));
-      BHIPC(launch_batch_step(b->d_tiles + b->n_wide, n_tail, 1, b->d_desc, j, b->apply_f32, b->mode, b->qoi, b->st));
+      BHIPC(launch_batch_step(b->d_tiles + b->n_wide, n_tail, 1, b->d_desc, j, b->apply_f32, b->mode, b->qoi, ts));
+    }
+    if (two) {
+      BHIPC(hipEventRecord(b->ev_join, b->st2));
+      BHIPC(hipStreamWaitEvent(b->st, b->ev_join, 0));
     }
     for (ens_ctx* c : b->ctx) BHIPC(launch_advance(c->p<int64_t>(c->L.base), k, b->st));
     done += k;
@@ -1690,14 +1708,17 @@ int32_t ens_batch_create(ens_ctx** ctxs, int32_t n, ens_batch** out) {
   b->spl = 2;
   b->desc_cur.assign(n, -1);
   b->desc_gen.assign(n, ~0ull);
-  if (hipSetDevice(b->device) != hipSuccess || hipStreamCreate(&b->st) != hipSuccess || hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+  if (hipSetDevice(b->device) != hipSuccess || hipStreamCreate(&b->st) != hipSuccess ||
+      hipStreamCreate(&b->st2) != hipSuccess || hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess ||
       hipMalloc(&b->d_desc, sizeof(StepArgs) * 2 * n) != hipSuccess) {
-    delete b;
+    (void)ens_batch_destroy(b);  // releases whatever was created
     return ENS_EDEVICE;
   }
   if (build_tiles(b) != ENS_OK) {
-    delete b;
+    (void)ens_batch_destroy(b);
     return ENS_EDEVICE;
   }
   *out = b;
@@ -1714,6 +1735,9 @@ int32_t ens_batch_destroy(ens_batch* b) {
   if (b->d_desc) (void)hipFree(b->d_desc);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
   if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+  if (b->ev_join) (void)hipEventDestroy(b->ev_join);
+  if (b->st2) (void)hipStreamDestroy(b->st2);
   if (b->st) (void)hipStreamDestroy(b->st);
   delete b;
   return ENS_OK;
@@ -1730,6 +1754,7 @@ int32_t ens_batch_info(ens_batch* b, ens_batch_info_t* out) {
   out->grid = 0;
   out->graph_steps = b->graph_k;
   out->launches_per_step = (b->n_wide > 0 ? 1 : 0) + (b->n_tiles > b->n_wide ? 1 : 0);
+  out->concurrent_tails = b->concurrent && b->n_wide > 0 && b->n_tiles > b->n_wide ? 1 : 0;
   out->tuned_ms_per_step = b->tuned_ms;
   return ENS_OK;
 }
@@ -1753,7 +1778,7 @@ int32_t ens_batch_step(ens_batch* b, int64_t n_steps, void* stream) {
     }
     std::vector<uint64_t> gen(b->ctx.size());
     for (size_t m = 0; m < b->ctx.size(); ++m) gen[m] = b->ctx[m]->gen;
-    const int sig[3] = {b->spl * (b->split ? -1 : 1), b->tile_nodes, 0};
+    const int sig[3] = {b->spl * (b->split ? -1 : 1), b->tile_nodes, b->concurrent ? 1 : 0};
     if (b->exec && (gen != b->graph_gen || std::memcmp(sig, b->graph_sig, sizeof sig) != 0)) drop_graph(b);
     int64_t left = n_steps;
     if (left >= b->graph_k) {
@@ -1792,11 +1817,12 @@ int32_t ens_batch_step(ens_batch* b, int64_t n_steps, void* stream) {
 int32_t ens_batch_set_tiling(ens_batch* b, int32_t samples_per_lane, int32_t split) {
   if (!b) return ENS_EINVAL;
   try {
-    if ((samples_per_lane != 1 && samples_per_lane != 2) || (split != 0 && split != 1))
-      return b->fail(ENS_EINVAL, "ens_batch_set_tiling: samples_per_lane must be 1 or 2 and split 0 or 1");
+    if ((samples_per_lane != 1 && samples_per_lane != 2) || split < 0 || split > 2)
+      return b->fail(ENS_EINVAL, "ens_batch_set_tiling: samples_per_lane must be 1 or 2 and split 0, 1 or 2");
     BHIPC(hipSetDevice(b->device));
     b->spl = samples_per_lane;
     b->split = split != 0;
+    b->concurrent = split == 2;
     return build_tiles(b);
   } catch (...) {
     return b->fail(ENS_EINVAL, "ens_batch_set_tiling: host failure");
@@ -1815,10 +1841,13 @@ int32_t ens_batch_autotune(ens_batch* b, int32_t trial_steps) {
     BHIPC(hipEventCreate(&e1));
     double best = 1e300;
     int bs = b->spl;
-    int bsplit = b->split ? 1 : 0;
-    for (int mode : {1, 2, 3}) {  // 1: one sample per lane; 2: two, one launch; 3: two, a launch per class
+    int bsplit = b->split ? (b->concurrent ? 2 : 1) : 0;
+    // 1: one sample per lane; 2: two, one launch; 3: two, a launch per class;
+    // 4: as 3 with the tails on a second stream
+    for (int mode : {1, 2, 3, 4}) {
       const int spl = mode == 1 ? 1 : 2;
-      b->split = mode == 3;
+      b->split = mode >= 3;
+      b->concurrent = mode == 4;
       b->spl = spl;
       rc = build_tiles(b);
       if (rc == ENS_OK) rc = build_desc(b);
@@ -1840,7 +1869,7 @@ int32_t ens_batch_autotune(ens_batch* b, int32_t trial_steps) {
       if (ms / trial_steps < best) {
         best = ms / trial_steps;
         bs = spl;
-        bsplit = mode == 3 ? 1 : 0;
+        bsplit = mode == 4 ? 2 : mode == 3 ? 1 : 0;
       }
       if (trial_steps & 1) {
         rc = build_desc(b);
@@ -1852,6 +1881,7 @@ int32_t ens_batch_autotune(ens_batch* b, int32_t trial_steps) {
     if (rc != ENS_OK) return rc;
     b->spl = bs;
     b->split = bsplit != 0;
+    b->concurrent = bsplit == 2;
     b->tuned_ms = best;
     rc = build_tiles(b);
     if (rc != ENS_OK) return rc;

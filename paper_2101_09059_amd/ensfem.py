@@ -59,7 +59,8 @@ class BatchInfo(ctypes.Structure):
     _fields_ = [("n_meshes", ctypes.c_int32), ("n_tiles", ctypes.c_int32),
                 ("samples_per_lane", ctypes.c_int32), ("tile_nodes", ctypes.c_int32),
                 ("grid", ctypes.c_int32), ("graph_steps", ctypes.c_int32),
-                ("launches_per_step", ctypes.c_int32), ("tuned_ms_per_step", ctypes.c_double)]
+                ("launches_per_step", ctypes.c_int32), ("tuned_ms_per_step", ctypes.c_double),
+                ("concurrent_tails", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
 
 _lib = None
@@ -393,8 +394,10 @@ class Batch:
     def autotune(self, trial_steps: int = 10):
         self._check(self._lib.ens_batch_autotune(self._h, int(trial_steps)))
 
-    def set_tiling(self, samples_per_lane: int, split: bool = False):
-        self._check(self._lib.ens_batch_set_tiling(self._h, int(samples_per_lane), 1 if split else 0))
+    def set_tiling(self, samples_per_lane: int, split: int = 0):
+        """split: 0 tails in the same launch, 1 a launch of their own, 2 the
+        same on a second stream beside the full blocks."""
+        self._check(self._lib.ens_batch_set_tiling(self._h, int(samples_per_lane), int(split)))
 
     def info(self) -> dict:
         inf = BatchInfo()

@@ -84,18 +84,19 @@ def test_batch_matches_solo_bitwise(apply_prec, state_prec):
         b.close()
 
 
-@pytest.mark.parametrize("spl,split,state_prec", [(1, False, ensfem.STATE_F64), (1, True, ensfem.STATE_F64),
-                                                   (2, False, ensfem.STATE_F64), (2, True, ensfem.STATE_F64),
-                                                   (2, True, ensfem.STATE_F32_KAHAN), (1, True, ensfem.STATE_F32)])
+@pytest.mark.parametrize("spl,split,state_prec", [(1, 0, ensfem.STATE_F64), (1, 1, ensfem.STATE_F64),
+                                                   (2, 0, ensfem.STATE_F64), (2, 1, ensfem.STATE_F64),
+                                                   (2, 2, ensfem.STATE_F64), (1, 2, ensfem.STATE_F64),
+                                                   (2, 2, ensfem.STATE_F32_KAHAN), (1, 1, ensfem.STATE_F32)])
 def test_batch_tilings_match_solo_bitwise(spl, split, state_prec):
-    """Every tiling (1 or 2 samples per lane; tail blocks in the same launch
-    or their own), switched between batch calls, gives the solo results
-    bit for bit."""
+    """Every tiling (1 or 2 samples per lane; tail blocks in the same launch,
+    their own, or their own on a second stream), switched between batch
+    calls, gives the solo results bit for bit."""
     say(f"case: batch tiling spl={spl} split={split} state={state_prec}")
     pairs = _members(ensfem.F32, state_prec)
     _start(pairs)
     batch = ensfem.Batch([b for _, b, _ in pairs])
-    for k, (s_, sp_) in enumerate([(spl, split), (3 - spl, not split), (spl, split)]):
+    for k, (s_, sp_) in enumerate([(spl, split), (3 - spl, (split + 1) % 3), (spl, split)]):
         batch.set_tiling(s_, sp_)
         n = (70, 33, 64)[k]
         say(f"  tiling {s_}/{sp_}: {batch.info()}, {n} steps")
@@ -106,7 +107,9 @@ def test_batch_tilings_match_solo_bitwise(spl, split, state_prec):
             assert np.array_equal(a.read_state(), b.read_state())
             assert np.array_equal(a.read_qoi(), b.read_qoi())
     with pytest.raises(ensfem.EnsfemError):
-        batch.set_tiling(3, False)
+        batch.set_tiling(3, 0)
+    with pytest.raises(ensfem.EnsfemError):
+        batch.set_tiling(2, 3)
     batch.close()
     for a, b, _ in pairs:
         a.close()
