@@ -15,20 +15,24 @@
 namespace ensfem {
 namespace {
 
-// UNI: ld is a multiple of 64, so a wave's 64 threads share one element and
-// the element's connectivity, frame and tangent are wave-uniform (scalar
-// loads).
-template <bool UNI>
+// SPL consecutive samples per thread (one 8 * SPL-byte access per row).
+// UNI: ld is a multiple of 64 * SPL, so a wave's 64 threads share one
+// element and the element's connectivity, frame and tangent are
+// wave-uniform (scalar loads).
+template <int SPL, bool UNI>
 __global__ __launch_bounds__(256) void k_stress(int64_t n_el, int32_t ld, const int32_t* __restrict__ tri,
                                                 const double* __restrict__ frame, const double* __restrict__ u,
                                                 const float* __restrict__ uh, const float* __restrict__ uc,
                                                 const double* __restrict__ eh, const double* __restrict__ h,
                                                 const double* __restrict__ axial, double nu, double shear_k,
                                                 int comp, double* __restrict__ out, int32_t* __restrict__ bad) {
+  typedef double D __attribute__((ext_vector_type(SPL)));
+  typedef float F __attribute__((ext_vector_type(SPL)));
+  const int64_t per = ld / SPL;  // threads per element
   const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= n_el * ld) return;
-  const int64_t e = UNI ? (int64_t)__builtin_amdgcn_readfirstlane((int)(t / ld)) : t / ld;
-  const int s = (int)(t % ld);
+  if (t >= n_el * per) return;
+  const int64_t e = UNI ? (int64_t)__builtin_amdgcn_readfirstlane((int)(t / per)) : t / per;
+  const int s = (int)(t % per) * SPL;
   const double* f = frame + (int64_t)kFrameWords * e;
   double R[3][3];
 #pragma unroll
@@ -36,37 +40,31 @@ __global__ __launch_bounds__(256) void k_stress(int64_t n_el, int32_t ld, const 
 #pragma unroll
     for (int c = 0; c < 3; ++c) R[i][c] = f[3 * i + c];
   // local displacements of the three nodes
-  double ul[3][3];
+  double ul[3][3][SPL];
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
     const int64_t node = tri[3 * e + v];
-    double ug[3];
+    double ug[3][SPL];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       const int64_t idx = (node * 3 + c) * ld + s;
-      if (u) ug[c] = u[idx];
-      else ug[c] = (double)uh[idx] - (uc ? (double)uc[idx] : 0.0);
+      if (u) {
+        const D x = *reinterpret_cast<const D*>(u + idx);
+#pragma unroll
+        for (int k = 0; k < SPL; ++k) ug[c][k] = x[k];
+      } else {
+        const F a = *reinterpret_cast<const F*>(uh + idx);
+        F b = {};
+        if (uc) b = *reinterpret_cast<const F*>(uc + idx);
+#pragma unroll
+        for (int k = 0; k < SPL; ++k) ug[c][k] = (double)a[k] - (uc ? (double)b[k] : 0.0);
+      }
     }
 #pragma unroll
-    for (int i = 0; i < 3; ++i) ul[v][i] = R[i][0] * ug[0] + R[i][1] * ug[1] + R[i][2] * ug[2];
-  }
-  double exx = 0.0, eyy = 0.0, gxy = 0.0, gxz = 0.0, gyz = 0.0;
+    for (int i = 0; i < 3; ++i)
 #pragma unroll
-  for (int v = 0; v < 3; ++v) {
-    const double bx = f[9 + v], by = f[12 + v];
-    exx += bx * ul[v][0];
-    eyy += by * ul[v][1];
-    gxy += by * ul[v][0] + bx * ul[v][1];
-    gxz += bx * ul[v][2];
-    gyz += by * ul[v][2];
+      for (int k = 0; k < SPL; ++k) ul[v][i][k] = R[i][0] * ug[0][k] + R[i][1] * ug[1][k] + R[i][2] * ug[2][k];
   }
-  const double E = eh[e * ld + s] / h[e * ld + s];
-  const double cE = E / (1.0 - nu * nu);
-  const double sxx = cE * (exx + nu * eyy);
-  const double syy = cE * (nu * exx + eyy);
-  const double txy = cE * 0.5 * (1.0 - nu) * gxy;
-  const double txz = cE * 0.5 * shear_k * (1.0 - nu) * gxz;
-  const double tyz = cE * 0.5 * shear_k * (1.0 - nu) * gyz;
   // cylindrical frame: r = e_z of the element, z the tangent without its
   // normal part, theta = r x z; all three in local coordinates
   const double a[3] = {axial[3 * e], axial[3 * e + 1], axial[3 * e + 2]};
@@ -74,21 +72,46 @@ __global__ __launch_bounds__(256) void k_stress(int64_t n_el, int32_t ld, const 
                         R[1][0] * a[0] + R[1][1] * a[1] + R[1][2] * a[2]};  // in-plane part
   const double zn = sqrt(za[0] * za[0] + za[1] * za[1]);
   const double an = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+  D res;
   if (!(zn > 1e-9 * an)) {
     if (s == 0) atomicOr(bad, 1);
-    out[t] = 0.0;
+    res = 0.0;
+    *reinterpret_cast<D*>(out + e * ld + s) = res;
     return;
   }
   const double zx = za[0] / zn, zy = za[1] / zn;  // z = (zx, zy, 0)
   const double tx = -zy, ty = zx;                  // theta = (0,0,1) x z
-  double v;
-  switch (comp) {
-    case 0: v = tx * (sxx * tx + txy * ty) + ty * (txy * tx + syy * ty); break;
-    case 1: v = zx * (sxx * zx + txy * zy) + zy * (txy * zx + syy * zy); break;
-    case 2: v = tx * (sxx * zx + txy * zy) + ty * (txy * zx + syy * zy); break;
-    default: v = txz * zx + tyz * zy; break;
+  const D ehv = *reinterpret_cast<const D*>(eh + e * ld + s);
+  const D hv = *reinterpret_cast<const D*>(h + e * ld + s);
+#pragma unroll
+  for (int k = 0; k < SPL; ++k) {
+    double exx = 0.0, eyy = 0.0, gxy = 0.0, gxz = 0.0, gyz = 0.0;
+#pragma unroll
+    for (int v = 0; v < 3; ++v) {
+      const double bx = f[9 + v], by = f[12 + v];
+      exx += bx * ul[v][0][k];
+      eyy += by * ul[v][1][k];
+      gxy += by * ul[v][0][k] + bx * ul[v][1][k];
+      gxz += bx * ul[v][2][k];
+      gyz += by * ul[v][2][k];
+    }
+    const double E = ehv[k] / hv[k];
+    const double cE = E / (1.0 - nu * nu);
+    const double sxx = cE * (exx + nu * eyy);
+    const double syy = cE * (nu * exx + eyy);
+    const double txy = cE * 0.5 * (1.0 - nu) * gxy;
+    const double txz = cE * 0.5 * shear_k * (1.0 - nu) * gxz;
+    const double tyz = cE * 0.5 * shear_k * (1.0 - nu) * gyz;
+    double v;
+    switch (comp) {
+      case 0: v = tx * (sxx * tx + txy * ty) + ty * (txy * tx + syy * ty); break;
+      case 1: v = zx * (sxx * zx + txy * zy) + zy * (txy * zx + syy * zy); break;
+      case 2: v = tx * (sxx * zx + txy * zy) + ty * (txy * zx + syy * zy); break;
+      default: v = txz * zx + tyz * zy; break;
+    }
+    res[k] = v;
   }
-  out[t] = v;
+  *reinterpret_cast<D*>(out + e * ld + s) = res;
 }
 
 // One workgroup per row (S > 512): bitonic sort of the row's S values
@@ -255,12 +278,23 @@ hipError_t launch_stress(int64_t n_el, int32_t ld, const int32_t* tri, const dou
   const int64_t n = n_el * ld;
   if (n == 0) return hipSuccess;
   if (comp < 0 || comp > 3) return hipErrorInvalidValue;
-  if (ld % 64 == 0 && n_el <= INT32_MAX)
-    k_stress<true><<<grid_for(n, 256), 256, 0, st>>>(n_el, ld, tri, frame, u, uh, uc, eh, h, axial, nu, shear_k,
-                                                      comp, out, bad);
-  else
-    k_stress<false><<<grid_for(n, 256), 256, 0, st>>>(n_el, ld, tri, frame, u, uh, uc, eh, h, axial, nu, shear_k,
+  // two samples per thread when the padded width is even (it always is a
+  // multiple of 8); a wave shares one element when ld is a multiple of 128
+  if (ld % 2 == 0) {
+    const int64_t nt = n / 2;
+    if (ld % 128 == 0 && n_el <= INT32_MAX)
+      k_stress<2, true><<<grid_for(nt, 256), 256, 0, st>>>(n_el, ld, tri, frame, u, uh, uc, eh, h, axial, nu, shear_k,
+                                                          comp, out, bad);
+    else
+      k_stress<2, false><<<grid_for(nt, 256), 256, 0, st>>>(n_el, ld, tri, frame, u, uh, uc, eh, h, axial, nu,
+                                                           shear_k, comp, out, bad);
+  } else if (ld % 64 == 0 && n_el <= INT32_MAX) {
+    k_stress<1, true><<<grid_for(n, 256), 256, 0, st>>>(n_el, ld, tri, frame, u, uh, uc, eh, h, axial, nu, shear_k,
                                                        comp, out, bad);
+  } else {
+    k_stress<1, false><<<grid_for(n, 256), 256, 0, st>>>(n_el, ld, tri, frame, u, uh, uc, eh, h, axial, nu, shear_k,
+                                                        comp, out, bad);
+  }
   return hipGetLastError();
 }
 

@@ -20,9 +20,10 @@ def _axial(n_el, seed):
     return a / np.linalg.norm(a, axis=1, keepdims=True)
 
 
-@pytest.mark.parametrize("mode,tol", [("f64", 1e-11), ("kahan", 1e-10)])
-def test_stress_and_bands_match_oracle(mode, tol):
-    S = 40
+# S = 40 pads to 64 (two samples per thread, a wave spans two elements);
+# S = 128 has a wave per element (scalar element data)
+@pytest.mark.parametrize("mode,tol,S", [("f64", 1e-11, 40), ("kahan", 1e-10, 40), ("f64", 1e-11, 128)])
+def test_stress_and_bands_match_oracle(mode, tol, S):
     cs = small_case(30, 16, S, seed=12)
     kw = {} if mode == "f64" else dict(apply_prec=ensfem.F32, state_prec=ensfem.STATE_F32_KAHAN)
     say(f"case: stress 30x16 S={S} {mode}")
