@@ -13,6 +13,7 @@ pytestmark = pytest.mark.gpu
 CFG = dict(p0=1.33e5, T_ramp=0.02, period=1.0, pulse_amp=0.3, window=0.03, nu=0.49, shear_k=5.0 / 6.0,
            rho=1.0, alpha=50.0, safety=0.9)
 N_MODES = 8
+N_HF, N_LF, N_REF = 16384, 262144, 65536
 
 
 @pytest.fixture(scope="module")
@@ -25,11 +26,16 @@ def setup():
     net = learned.Network(2 * N_MODES, 128, 3, mesh.n_nodes, seed=9, max_batch=256)
     rmse, hist = net.fit(Xtr, Qtr, epochs=150, batch=128, lr=2e-3, seed=10)
     say(f"  held-out rel RMSE {rmse:.4f}, loss {hist[0]:.3e} -> {hist[-1]:.3e}")
-    Xh = learned.draw_xi(6, 64, N_MODES)
-    qH, (pm, pv) = prob.solve(Xh, return_moments=True)
-    Xl = learned.draw_xi(7, 16384, N_MODES)
-    Xr = learned.draw_xi(8, 4096, N_MODES)
-    qR = np.concatenate([prob.solve(Xr[i:i + 256]) for i in range(0, 4096, 256)], axis=1)
+    # The variance is judged within max(1 %, 2 SE_ref) of a 65,536-sample
+    # reference (SE_ref 0.6 %), so the control variate's own error must be
+    # well below that: N = 16,384 paired samples (at 1,024 its variance
+    # carries about 1.5 % of its own) and M = 262,144 network draws.
+    Xh = learned.draw_xi(6, N_HF, N_MODES)
+    qH = np.concatenate([prob.solve(Xh[i:i + 256]) for i in range(0, N_HF, 256)], axis=1)
+    pm, pv = qH.mean(axis=1), qH.var(axis=1, ddof=1)
+    Xl = learned.draw_xi(7, N_LF, N_MODES)
+    Xr = learned.draw_xi(8, N_REF, N_MODES)
+    qR = np.concatenate([prob.solve(Xr[i:i + 256]) for i in range(0, N_REF, 256)], axis=1)
     yield dict(mesh=mesh, prob=prob, net=net, rmse=rmse, Xh=Xh, qH=qH, pm=pm, pv=pv, Xl=Xl, qR=qR)
     net.close()
 
@@ -59,7 +65,7 @@ def test_control_variate_matches_reference_and_gains(setup):
     say(f"  mean rel err CV {e_cv:.2e} plain(N={N}) {e_plain:.2e} ref SE {se_m:.2e}; "
         f"var rel err {e_var:.2e} ref SE {se_v:.2e}")
     assert e_cv < max(0.01, 3 * se_m)
-    assert e_var < 0.05
+    assert e_var < max(0.01, 2 * se_v)
     # gain: variance ratio of the CV mean to the plain N-sample mean
     ratio = 1.0 - est["rho"][act] ** 2 * M / (M + N)
     gain = 1.0 / np.median(ratio)
