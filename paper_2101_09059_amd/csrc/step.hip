@@ -793,7 +793,8 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
 // a wave per SIMD) with 64 lanes x SPL samples.  A tail tile holds the
 // last samples of a mesh when fewer than 64 x SPL remain (64 or 32 at
 // SPL = 2, 32 at SPL = 1 for a padded width that is an odd multiple of 32)
-// and runs on the wave's lower lanes (one kernel, one register budget).
+// and runs one sample per lane on as many lanes (one kernel, one register
+// budget).
 // Per-mesh arguments come from a device table indexed by mesh and by the
 // parity of the step (which state buffer is current).
 template <typename AT, int MODE, int SPL, bool QOI>
@@ -814,13 +815,18 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(const BatchTile* __restri
   // the mesh's arguments are read in place (scalar loads where they are
   // used) rather than copied: a copy holds them all in registers
   const StepArgs& p = *(const StepArgs*)(cst(desc) + 2 * mesh + (j & 1));
-  // a tail tile covers min(64, ld - sample0) samples on as many lanes as
-  // that takes, within the block's first rising-bit word
-  const bool tail = (cw & kTileTail) != 0;
-  const int lanes = tail ? min(64, p.ld - sample0) / SPL : 64;
+  // a tail tile covers min(64, ld - sample0) samples, one per lane, within
+  // the block's first rising-bit word (in a launch with 2 samples per lane
+  // the tails take the one-sample code path, so they interleave with the
+  // full blocks in one launch)
+  if (cw & kTileTail) {
+    double e1[1];
+    if (lane < min(64, p.ld - sample0))
+      step_node<AT, MODE, 64, 1, QOI, false, false, false, true>(p, j, node, sample0, lane, e1, 1);
+    return;
+  }
   double e_loc[SPL];
-  if (lane < lanes)
-    step_node<AT, MODE, 64, SPL, QOI, false, false, false, true>(p, j, node, sample0, lane, e_loc, tail ? 1 : SPL);
+  step_node<AT, MODE, 64, SPL, QOI, false, false, false, true>(p, j, node, sample0, lane, e_loc, SPL);
 }
 
 // Stand-alone apply; with MAP the rows of U and R are in the numbering
