@@ -198,6 +198,8 @@ int pick_sample_block(int S, int requested) {
 }
 
 // nodes per workgroup for a sample block
+// node blocks of a kBlock workgroup (the energy partials; each launch
+// derives the grid of its own workgroup size)
 int nodes_per_block(int SB) { return kBlock / (SB >= 64 ? 64 : SB); }
 
 bool use_shared(const ens_ctx* c);
@@ -1502,7 +1504,7 @@ struct ens_batch {
   bool apply_f32 = false, qoi = true;
   int mode = 0;
   // tuning
-  int spl = 1, tile_nodes = 4;  // nodes per tile: one per wave of the workgroup
+  int spl = 1, tile_nodes = 4;  // nodes per tile: one per wave of the workgroup (set at creation)
   double tuned_ms = 0.0;
   // device tables (small, owned)
   BatchTile* d_tiles = nullptr;
@@ -1705,6 +1707,7 @@ int32_t ens_batch_create(ens_ctx** ctxs, int32_t n, ens_batch** out) {
   b->apply_f32 = c0->apply_prec == ENS_F32;
   b->mode = c0->state_prec;
   b->qoi = (c0->qoi_mask & ENS_QOI_PEAK_RADIAL) != 0;
+  b->tile_nodes = kBlock / 64;
   b->spl = 2;
   b->desc_cur.assign(n, -1);
   b->desc_gen.assign(n, ~0ull);

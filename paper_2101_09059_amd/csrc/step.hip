@@ -751,11 +751,11 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int j, int node, in
 }
 
 // LPN lanes per node, SPL consecutive samples per lane: a workgroup covers
-// kBlock/LPN nodes times LPN*SPL samples.  With LPN = 64 a wave owns one
+// StepBlock/LPN nodes times LPN*SPL samples.  With LPN = 64 a wave owns one
 // node, so adjacency and stiffness blocks are wave-uniform (scalar loads).
 template <typename AT, int MODE, int LPN, int SPL, bool QOI, bool ENERGY, bool SHARED, bool GEOM = false>
-__global__ __launch_bounds__(kBlock) void k_step(StepArgs p) {
-  constexpr int NPB = kBlock / LPN;
+__global__ __launch_bounds__((StepBlock<AT, LPN, SPL, ENERGY>::value)) void k_step(StepArgs p) {
+  constexpr int NPB = StepBlock<AT, LPN, SPL, ENERGY>::value / LPN;
   int nb, sbk;
   if (!wg_coords(p, nb, sbk)) return;  // uniform over the workgroup
   const int ln = threadIdx.x / LPN;
@@ -832,10 +832,10 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(const BatchTile* __restri
 // Stand-alone apply; with MAP the rows of U and R are in the numbering
 // given by map (internal node -> buffer node).
 template <typename AT, int LPN, int SPL, bool SHARED, bool MAP>
-__global__ __launch_bounds__(kBlock) void k_apply(StepArgs p, const AT* __restrict__ U,
+__global__ __launch_bounds__((StepBlock<AT, LPN, SPL>::value)) void k_apply(StepArgs p, const AT* __restrict__ U,
                                                   AT* __restrict__ R, const int32_t* __restrict__ map) {
   constexpr int SB = LPN * SPL;
-  constexpr int NPB = kBlock / LPN;
+  constexpr int NPB = StepBlock<AT, LPN, SPL>::value / LPN;
   int nb, sbk;
   if (!wg_coords(p, nb, sbk)) return;
   int node = nb * NPB + (int)(threadIdx.x / LPN);
@@ -1095,13 +1095,28 @@ inline unsigned step_grid(const StepArgs& a) {
   return (unsigned)(((n + 7) / 8) * 8);
 }
 
+// The arguments with the node-block count of a workgroup of blk threads
+// at lpn lanes per node.
+inline StepArgs with_blocks(const StepArgs& a, int blk, int lpn) {
+  StepArgs b = a;
+  const int npb = blk / lpn;
+  b.n_nb = (int32_t)((a.n_nodes + npb - 1) / npb);
+  return b;
+}
+
+template <typename AT, int MODE, int LPN, int SPL, bool QOI, bool ENERGY, bool SH, bool GEOM = false>
+void launch_k_step(const StepArgs& a, hipStream_t st) {
+  constexpr int BLK = StepBlock<AT, LPN, SPL, ENERGY>::value;
+  const StepArgs b = with_blocks(a, BLK, LPN);
+  k_step<AT, MODE, LPN, SPL, QOI, ENERGY, SH, GEOM><<<step_grid(b), BLK, 0, st>>>(b);
+}
+
 template <typename AT, int MODE, int LPN, int SPL, bool SH>
 hipError_t dispatch_flags(const StepArgs& a, bool qoi, bool energy, hipStream_t st) {
-  const unsigned g = step_grid(a);
-  if (qoi && energy) k_step<AT, MODE, LPN, SPL, true, true, SH><<<g, kBlock, 0, st>>>(a);
-  else if (qoi) k_step<AT, MODE, LPN, SPL, true, false, SH><<<g, kBlock, 0, st>>>(a);
-  else if (energy) k_step<AT, MODE, LPN, SPL, false, true, SH><<<g, kBlock, 0, st>>>(a);
-  else k_step<AT, MODE, LPN, SPL, false, false, SH><<<g, kBlock, 0, st>>>(a);
+  if (qoi && energy) launch_k_step<AT, MODE, LPN, SPL, true, true, SH>(a, st);
+  else if (qoi) launch_k_step<AT, MODE, LPN, SPL, true, false, SH>(a, st);
+  else if (energy) launch_k_step<AT, MODE, LPN, SPL, false, true, SH>(a, st);
+  else launch_k_step<AT, MODE, LPN, SPL, false, false, SH>(a, st);
   return hipGetLastError();
 }
 
@@ -1120,9 +1135,8 @@ hipError_t dispatch_sb(const StepArgs& a, int sb, bool qoi, bool energy, hipStre
 
 template <typename AT, int LPN, int SPL>
 hipError_t dispatch_geom_flags(const StepArgs& a, bool qoi, hipStream_t st) {
-  const unsigned g = step_grid(a);
-  if (qoi) k_step<AT, kStateF64, LPN, SPL, true, false, false, true><<<g, kBlock, 0, st>>>(a);
-  else k_step<AT, kStateF64, LPN, SPL, false, false, false, true><<<g, kBlock, 0, st>>>(a);
+  if (qoi) launch_k_step<AT, kStateF64, LPN, SPL, true, false, false, true>(a, st);
+  else launch_k_step<AT, kStateF64, LPN, SPL, false, false, false, true>(a, st);
   return hipGetLastError();
 }
 
@@ -1148,18 +1162,24 @@ hipError_t dispatch_shared(const StepArgs& a, int sb, bool qoi, bool energy, boo
 template <typename AT, bool SH, bool MAP>
 hipError_t dispatch_apply(const StepArgs& a, int sb, const void* U, void* R, const int32_t* map,
                           hipStream_t st) {
-  const unsigned g = step_grid(a);
   const AT* u = static_cast<const AT*>(U);
   AT* r = static_cast<AT*>(R);
+#define ENSFEM_APPLY(LPN, SPL)                                                           \
+  do {                                                                                   \
+    constexpr int blk = StepBlock<AT, LPN, SPL>::value;                                  \
+    const StepArgs b = with_blocks(a, blk, LPN);                                         \
+    k_apply<AT, LPN, SPL, SH, MAP><<<step_grid(b), blk, 0, st>>>(b, u, r, map);          \
+  } while (0)
   switch (sb) {
-    case 8: k_apply<AT, 8, 1, SH, MAP><<<g, kBlock, 0, st>>>(a, u, r, map); break;
-    case 16: k_apply<AT, 16, 1, SH, MAP><<<g, kBlock, 0, st>>>(a, u, r, map); break;
-    case 32: k_apply<AT, 32, 1, SH, MAP><<<g, kBlock, 0, st>>>(a, u, r, map); break;
-    case 64: k_apply<AT, 64, 1, SH, MAP><<<g, kBlock, 0, st>>>(a, u, r, map); break;
-    case 128: k_apply<AT, 64, 2, SH, MAP><<<g, kBlock, 0, st>>>(a, u, r, map); break;
-    case 256: k_apply<AT, 64, 4, SH, MAP><<<g, kBlock, 0, st>>>(a, u, r, map); break;
+    case 8: ENSFEM_APPLY(8, 1); break;
+    case 16: ENSFEM_APPLY(16, 1); break;
+    case 32: ENSFEM_APPLY(32, 1); break;
+    case 64: ENSFEM_APPLY(64, 1); break;
+    case 128: ENSFEM_APPLY(64, 2); break;
+    case 256: ENSFEM_APPLY(64, 4); break;
     default: return hipErrorInvalidValue;
   }
+#undef ENSFEM_APPLY
   return hipGetLastError();
 }
 
