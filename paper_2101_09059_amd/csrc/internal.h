@@ -13,17 +13,18 @@ namespace ensfem {
 
 constexpr int kBlock = 256;       // threads per workgroup for the ensemble kernels
 // Workgroup of the single-mesh step and apply kernels: 512 threads (8
-// nodes of 64 lanes) for the FP32 apply with 2 or 4 samples per lane,
-// whose eight neighbouring nodes per workgroup share neighbour rows in L1
-// (2 % faster on the headline step); kBlock otherwise (the FP64 apply's 5
-// waves per SIMD would leave a CU 16 waves instead of 20 at 512, and
-// smaller sample blocks measured slower), and always for the steps that
+// nodes of 64 lanes) for the FP32 apply with 2 or 4 samples per lane and
+// the FP64 state (and the stand-alone apply), whose eight neighbouring
+// nodes per workgroup share neighbour rows in L1 (2 % faster on the
+// headline step); kBlock otherwise (the FP64 apply's 5 waves per SIMD
+// would leave a CU 16 waves instead of 20 at 512; smaller sample blocks
+// and the FP32 states measured slower), and always for the steps that
 // record energy, whose per-workgroup partial sums then group the same
 // nodes whatever the sample block.  The host's node-block count (energy
 // partials) is the kBlock one; each launch derives its own grid.
-template <typename AT, int LPN, int SPL, bool ENERGY = false>
+template <typename AT, int LPN, int SPL, bool ENERGY = false, bool F64_STATE = true>
 struct StepBlock {
-  static constexpr int value = (sizeof(AT) == 4 && LPN == 64 && SPL >= 2 && !ENERGY) ? 512 : kBlock;
+  static constexpr int value = (sizeof(AT) == 4 && LPN == 64 && SPL >= 2 && !ENERGY && F64_STATE) ? 512 : kBlock;
 };
 // Batch tile order within a mesh: 1 node tile by node tile with its sample
 // blocks together (a node's stiffness blocks are reused from L2 by its

@@ -754,8 +754,8 @@ __device__ __forceinline__ void step_node(const StepArgs& p, int j, int node, in
 // StepBlock/LPN nodes times LPN*SPL samples.  With LPN = 64 a wave owns one
 // node, so adjacency and stiffness blocks are wave-uniform (scalar loads).
 template <typename AT, int MODE, int LPN, int SPL, bool QOI, bool ENERGY, bool SHARED, bool GEOM = false>
-__global__ __launch_bounds__((StepBlock<AT, LPN, SPL, ENERGY>::value)) void k_step(StepArgs p) {
-  constexpr int NPB = StepBlock<AT, LPN, SPL, ENERGY>::value / LPN;
+__global__ __launch_bounds__((StepBlock<AT, LPN, SPL, ENERGY, MODE == kStateF64>::value)) void k_step(StepArgs p) {
+  constexpr int NPB = StepBlock<AT, LPN, SPL, ENERGY, MODE == kStateF64>::value / LPN;
   int nb, sbk;
   if (!wg_coords(p, nb, sbk)) return;  // uniform over the workgroup
   const int ln = threadIdx.x / LPN;
@@ -1106,7 +1106,7 @@ inline StepArgs with_blocks(const StepArgs& a, int blk, int lpn) {
 
 template <typename AT, int MODE, int LPN, int SPL, bool QOI, bool ENERGY, bool SH, bool GEOM = false>
 void launch_k_step(const StepArgs& a, hipStream_t st) {
-  constexpr int BLK = StepBlock<AT, LPN, SPL, ENERGY>::value;
+  constexpr int BLK = StepBlock<AT, LPN, SPL, ENERGY, MODE == kStateF64>::value;
   const StepArgs b = with_blocks(a, BLK, LPN);
   k_step<AT, MODE, LPN, SPL, QOI, ENERGY, SH, GEOM><<<step_grid(b), BLK, 0, st>>>(b);
 }
