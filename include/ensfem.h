@@ -297,7 +297,7 @@ typedef struct {
   int32_t tile_nodes;       /* nodes per tile (4: one per wave)          */
   int32_t grid;             /* 0: one workgroup per tile (the only form) */
   int32_t graph_steps;      /* steps per captured graph                  */
-  int32_t launches_per_step; /* 1, or 2 when the two lane classes are
+  int32_t launches_per_step; /* 1, or 2 when full and tail blocks are
                                 launched separately                      */
   double tuned_ms_per_step; /* best autotuner trial, 0 before autotune   */
   int32_t concurrent_tails;  /* 1: the tail launches run on a second
@@ -315,9 +315,10 @@ int32_t ens_batch_info(ens_batch* b, ens_batch_info_t* out);
 int32_t ens_batch_step(ens_batch* b, int64_t n_steps, void* stream);
 /* Times trial_steps steps for each candidate tiling and keeps the fastest:
  * samples per lane 1 or 2 (blocks of 64 or 128 samples; the samples left
- * at the end of a mesh, 64 or 32, form a tail block run on the lower lanes
- * of a wave) and, with 2, the tail blocks in the same launch or in a second
- * launch per step.  Every tiling has one workgroup per tile of 4 nodes.
+ * at the end of a mesh, 64 or 32, form a tail block run at one sample per
+ * lane) and, with 2, the tail blocks in the same launch, in a second
+ * launch per step, or in a second launch on a second stream.  Every tiling
+ * has one workgroup per tile of 4 nodes.
  * The trial steps ADVANCE every context's state: re-init the states
  * afterwards to restart from the initial condition. */
 int32_t ens_batch_autotune(ens_batch* b, int32_t trial_steps);
