@@ -428,16 +428,18 @@ def test_apply_parity_wide_sample_blocks(sb, prec):
     ens.close()
 
 
-@pytest.mark.parametrize("state", [ensfem.STATE_F64, ensfem.STATE_F32_KAHAN])
-def test_step_bitwise_independent_of_sample_block(state):
+@pytest.mark.parametrize("state,apply_prec", [(ensfem.STATE_F64, ensfem.F64), (ensfem.STATE_F32_KAHAN, ensfem.F32),
+                                              (ensfem.STATE_F64, ensfem.F32)])
+def test_step_bitwise_independent_of_sample_block(state, apply_prec):
     """Every (node, sample) does the same arithmetic in the same order
-    whatever the lane mapping, so the results must be bitwise equal."""
+    whatever the lane mapping and workgroup size (the FP32 apply with the
+    FP64 state runs 8-node workgroups at 128 and 256 samples per block, 4
+    at 64 and at energy records), so the results must be bitwise equal."""
     cs = small_case(26, 14, 256, seed=11)
-    kw = dict(state_prec=state, apply_prec=ensfem.F64 if state == ensfem.STATE_F64 else ensfem.F32,
-              energy_every=7)
+    kw = dict(state_prec=state, apply_prec=apply_prec, energy_every=7)
     outs = []
     for sb in (64, 128, 256):
-        say(f"case: bitwise sb={sb} state={state}")
+        say(f"case: bitwise sb={sb} state={state} apply={apply_prec}")
         ens = ensfem.setup_case(cs.mesh, cs.eh, cs.h, cs.F, sample_block=sb, **kw)
         ens.init_state()
         ens.step(300, cs.dt)
