@@ -1576,6 +1576,15 @@ int32_t build_tiles(ens_batch* b) {
         for (int64_t n0 = 0; n0 < c->n_nodes; n0 += b->tile_nodes) put(n0, s0);
     }
   }
+  if (!b->split) {
+    // one launch: each XCD's eighth of the list (the kernel's slices) runs
+    // its full blocks first, then its tails (8.24 against 8.69 ms per step
+    // on the 16-tube batch with the two kinds interleaved)
+    const size_t n = wide.size();
+    for (int x = 0; x < 8; ++x)
+      std::stable_partition(wide.begin() + n * x / 8, wide.begin() + n * (x + 1) / 8,
+                            [](const BatchTile& t) { return (t.count & kTileTail) == 0; });
+  }
   b->n_wide = (int32_t)wide.size();
   b->n_tiles = (int32_t)(wide.size() + narrow.size());
   std::vector<BatchTile> tiles(wide);
