@@ -1550,7 +1550,8 @@ void drop_graph(ens_batch* b) {
 
 // Tiles of `tile_nodes` (= 4, one per wave) consecutive nodes times one
 // sample block, mesh by mesh.  With spl = 2 a mesh's samples go in blocks
-// of 128 (2 per lane) while 128 remain, then a tail block of 64 or 32; with
+// of 128 (2 per lane) while 128 remain, a remainder of 96 in one block on
+// 48 lanes, then a tail block of 64 or 32; with
 // spl = 1 in blocks of 64 and a last one of 32 when the padded width is an
 // odd multiple of 32.  Within a mesh the order is node tile by node tile
 // with the sample blocks together (or block by block, see
@@ -1561,10 +1562,14 @@ int32_t build_tiles(ens_batch* b) {
   const int blk = 64 * b->spl;
   for (size_t m = 0; m < b->ctx.size(); ++m) {
     const ens_ctx* c = b->ctx[m];
+    // a block is wide (the spl launch) when it holds 64 * spl samples, or,
+    // at spl = 2, more than 64 (a 96-sample remainder on 48 lanes); the
+    // rest (64 or 32 samples) is a tail run at one sample per lane
+    auto wide_at = [&](int s0) { return c->ld - s0 >= blk || (b->spl == 2 && c->ld - s0 > 64); };
     std::vector<int> starts;
-    for (int s0 = 0; s0 < c->ld; s0 += s0 + blk <= c->ld ? blk : 64) starts.push_back(s0);
+    for (int s0 = 0; s0 < c->ld; s0 += wide_at(s0) ? std::min(blk, c->ld - s0) : 64) starts.push_back(s0);
     auto put = [&](int64_t n0, int s0) {
-      const bool tail = s0 + blk > c->ld;
+      const bool tail = !wide_at(s0);
       const int32_t cnt = (int32_t)std::min<int64_t>(b->tile_nodes, c->n_nodes - n0);
       (tail && b->split ? narrow : wide).push_back(BatchTile{(int32_t)m, (int32_t)n0, cnt | (tail ? kTileTail : 0), s0});
     };

@@ -825,8 +825,14 @@ __global__ __launch_bounds__(kBlock) void k_batch_step(const BatchTile* __restri
       step_node<AT, MODE, 64, 1, QOI, false, false, false, true>(p, j, node, sample0, lane, e1, 1);
     return;
   }
+  // a block of 64 < n < 128 samples (a padded width of 96 more than a
+  // multiple of 128) runs at two samples per lane on n / 2 lanes
+  const int rem = p.ld - sample0;
   double e_loc[SPL];
-  step_node<AT, MODE, 64, SPL, QOI, false, false, false, true>(p, j, node, sample0, lane, e_loc, SPL);
+  if (SPL == 1 || rem >= 64 * SPL)
+    step_node<AT, MODE, 64, SPL, QOI, false, false, false, true>(p, j, node, sample0, lane, e_loc, SPL);
+  else if (lane < rem / SPL)
+    step_node<AT, MODE, 64, SPL, QOI, false, false, false, true>(p, j, node, sample0, lane, e_loc, (rem + 63) / 64);
 }
 
 // Stand-alone apply; with MAP the rows of U and R are in the numbering

@@ -13,9 +13,11 @@ from tests._cases import say, rel_l2, per_sample_max_rel
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-# (n_theta, n_z, S): padded widths 64 .. 256 in steps of 64, and two members
+# (n_theta, n_z, S): padded widths 64 .. 256 in steps of 64, two members
 # padded to an odd multiple of 32 (32 and 160: a tail block of 32 samples)
-SPECS = [(12, 8, 64), (30, 21, 128), (47, 40, 192), (17, 9, 256), (64, 33, 64), (20, 13, 32), (26, 17, 160)]
+# and one of 96 (one block of 96 samples on 48 lanes at 2 per lane)
+SPECS = [(12, 8, 64), (30, 21, 128), (47, 40, 192), (17, 9, 256), (64, 33, 64), (20, 13, 32), (26, 17, 160),
+         (22, 12, 96)]
 
 
 T_RAMP = 0.003
@@ -156,9 +158,9 @@ def test_batch_rejects_incompatible_members():
 def test_batch_members_match_oracle(apply_prec, tol):
     """After an autotuner pass, 301 batched steps (graph replays plus an odd
     remainder; both lane classes: widths 64 and 192 have a tail block of 64
-    samples at 2 samples per lane, 32 and 160 one of 32): the first, a
-    middle and the last sample column of every member against the oracle's
-    per-sample run."""
+    samples, 32 and 160 one of 32, 96 a block of 96 on 48 lanes): the
+    first, a middle and the last sample column of every member against the
+    oracle's per-sample run."""
     say(f"case: batch vs oracle apply={apply_prec}")
     pairs = _members(apply_prec, ensfem.STATE_F64)
     _start(pairs)
