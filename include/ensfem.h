@@ -316,7 +316,8 @@ int32_t ens_batch_step(ens_batch* b, int64_t n_steps, void* stream);
 /* Times trial_steps steps for each candidate tiling and keeps the fastest:
  * samples per lane 1 or 2 (blocks of 64 or 128 samples; the samples left
  * at the end of a mesh, 64 or 32, form a tail block run at one sample per
- * lane) and, with 2, the tail blocks in the same launch, in a second
+ * lane; with 2 per lane, 96 left form one block on 48 lanes among the full
+ * ones) and, with 2, the tail blocks in the same launch, in a second
  * launch per step, or in a second launch on a second stream.  Every tiling
  * has one workgroup per tile of 4 nodes.
  * The trial steps ADVANCE every context's state: re-init the states
