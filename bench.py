@@ -59,16 +59,14 @@ def step_kernel_bytes(n_nodes: int, n_el: int, S: int, apply_f32: bool, state: s
 
 
 def source_hash() -> str:
-    """Hash of what decides the fused step's memory traffic: the kernel
-    sources and the library's node ordering."""
+    """Hash of what decides the step kernels' memory traffic: the kernel
+    sources and the host code that picks their launch shapes, the node
+    ordering and the batch tile list."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2101_09059_amd", "csrc")
-    for f in ("step.hip", "internal.h"):
+    for f in ("step.hip", "internal.h", "api.hip"):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
-    api = open(os.path.join(csrc, "api.hip")).read()
-    i = api.index("void rcb_order(")
-    h.update(api[i:api.index("\n}\n", i)].encode())
     return h.hexdigest()[:16]
 
 
