@@ -127,7 +127,8 @@ struct StepArgs {
 
 // One work item of the batched step: nodes node0 .. node0 + (count &
 // kTileCount) - 1 of mesh `mesh` (at most 4, one per wave), samples from
-// sample0: a full block of 64 * spl (spl fixed per launch) or, with
+// sample0: a full block of 64 * spl (spl fixed per launch; at spl = 2 a
+// mesh's last 96 samples also form one block, on 48 lanes) or, with
 // kTileTail set in count, a mesh's last min(64, ld - sample0).
 struct BatchTile {
   int32_t mesh;

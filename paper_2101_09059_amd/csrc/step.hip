@@ -791,10 +791,10 @@ __global__ __launch_bounds__((StepBlock<AT, LPN, SPL, ENERGY, MODE == kStateF64>
 // share neighbours run close in time on one L2).  Each wave takes one node
 // of its tile (no loop: a node loop keeps hoisted addresses live and costs
 // a wave per SIMD) with 64 lanes x SPL samples.  A tail tile holds the
-// last samples of a mesh when fewer than 64 x SPL remain (64 or 32 at
-// SPL = 2, 32 at SPL = 1 for a padded width that is an odd multiple of 32)
-// and runs one sample per lane on as many lanes (one kernel, one register
-// budget).
+// last samples of a mesh when no full block remains (64 or 32 at SPL = 2,
+// where a remainder of 96 runs as one block on 48 lanes instead; 32 at
+// SPL = 1 for a padded width that is an odd multiple of 32) and runs one
+// sample per lane on as many lanes (one kernel, one register budget).
 // Per-mesh arguments come from a device table indexed by mesh and by the
 // parity of the step (which state buffer is current).
 template <typename AT, int MODE, int SPL, bool QOI>
