@@ -1021,6 +1021,9 @@ int32_t ens_step(ens_ctx* ctx, int64_t n_steps, double dt, int32_t force, void* 
     const int32_t rc = resolve_qoi(ctx);
     if (rc != ENS_OK) return rc;
     HIPC(hipMemset(ctx->p<void>(L.qmask), 0, sizeof(uint64_t) * ctx->n_nodes * ((ctx->ld + 63) / 64)));
+    // the clear runs on the null stream: finish it before steps on `st`
+    // (possibly a non-blocking stream) or a later batch step reads the bits
+    HIPC(hipDeviceSynchronize());
     ctx->mask_live = false;
   }
   int64_t left = n_steps;
