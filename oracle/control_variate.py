@@ -14,13 +14,15 @@ estimator's variance is (sigma_H^2 / N) (1 - rho^2 M / (M + N)).
 
 The estimator is used only when the surrogate earns it: median per-node
 correlation >= 0.9 and held-out relative RMSE <= 5 %; otherwise the plain
-N-sample statistics are returned unchanged.
+N-sample statistics are returned unchanged.  The correlation is undefined
+at nodes whose high-fidelity QoI does not vary (the clamped rings), so the
+median runs over the varying nodes only.
 
 Pins (tests/test_oracle_control_variate.py): a Gaussian toy (H = X,
 L = X + sigma Z) where repeated trials show the estimator unbiased and its
 variance equal to the formula above; a perfect surrogate with exact
 low-fidelity moments recovers the exact mean; the fallback returns the
-plain statistics bit for bit.
+plain statistics bit for bit; constant nodes do not enter the median.
 """
 from __future__ import annotations
 
@@ -63,14 +65,20 @@ def predicted_variance_ratio(rho, N: int, M: int):
 
 
 def use_control_variate(rho: np.ndarray, heldout_rel_rmse: float, rho_min: float = 0.9,
-                        rmse_max: float = 0.05) -> bool:
-    return bool(np.median(rho) >= rho_min and heldout_rel_rmse <= rmse_max)
+                        rmse_max: float = 0.05, varying=None) -> bool:
+    """The fallback rule; varying (bool per node) marks the nodes whose
+    high-fidelity QoI varies, the only ones where rho is defined (all nodes
+    when None).  No varying node: plain statistics."""
+    r = rho if varying is None else rho[varying]
+    if r.size == 0:
+        return False
+    return bool(np.median(r) >= rho_min and heldout_rel_rmse <= rmse_max)
 
 
 def estimate(qH, qL, sumL_M, sumsqL_M, M, heldout_rel_rmse):
     """The estimator with its fallback: returns (mean, var, used_cv)."""
     cv = cv_moments(qH, qL, sumL_M, sumsqL_M, M)
-    if use_control_variate(cv["rho"], heldout_rel_rmse):
-        return cv["mean"], cv["var"], True
     mean, var = plain_moments(qH)
+    if use_control_variate(cv["rho"], heldout_rel_rmse, varying=var > 0):
+        return cv["mean"], cv["var"], True
     return mean, var, False

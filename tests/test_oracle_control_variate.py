@@ -47,3 +47,29 @@ def test_fallback_returns_plain_statistics():
     assert np.array_equal(m, pm) and np.array_equal(v, pv)
     m2, v2, used2 = cv.estimate(qH, qH + 1e-3 * junk, qH.sum(1) * 10, (qH ** 2).sum(1) * 10, 400, 0.01)
     assert used2
+
+
+def test_median_correlation_skips_nodes_whose_qoi_does_not_vary():
+    # 6 clamped nodes (Q_H identically 0, rho undefined and returned as 0)
+    # and 4 varying nodes with a near-perfect surrogate: over all 10 nodes
+    # the median would be 0 and the rule would fall back; over the varying
+    # ones it is ~1 and the control variate is used.
+    rng = np.random.default_rng(6)
+    N, M = 64, 4096
+    qH = np.zeros((10, N))
+    qH[6:] = 2.0 + rng.standard_normal((4, N))
+    qL = qH + 1e-3 * rng.standard_normal((10, N))
+    qL[:6] = rng.standard_normal((6, N))            # surrogate noise where Q_H is constant
+    sumL = qL.sum(1) * (M / N)
+    sumsqL = (qL ** 2).sum(1) * (M / N)
+    r = cv.cv_moments(qH, qL, sumL, sumsqL, M)
+    assert np.all(r["rho"][:6] == 0.0) and np.all(r["rho"][6:] > 0.99)
+    assert not cv.use_control_variate(r["rho"], 0.01)                       # all nodes: median 0
+    assert cv.use_control_variate(r["rho"], 0.01, varying=cv.plain_moments(qH)[1] > 0)
+    m, v, used = cv.estimate(qH, qL, sumL, sumsqL, M, 0.01)
+    assert used
+    # at the constant nodes beta = 0, so the estimate is the plain one: 0
+    assert np.all(m[:6] == 0.0) and np.all(v[:6] == 0.0)
+    # no varying node at all: plain statistics
+    m0, v0, used0 = cv.estimate(np.zeros((3, N)), qL[:3], sumL[:3], sumsqL[:3], M, 0.01)
+    assert not used0 and np.all(m0 == 0.0) and np.all(v0 == 0.0)
