@@ -43,6 +43,12 @@ def test_batch_specs_reproducible():
     b = inputs.tube_batch_specs(4)
     assert a == b and len(a) == 16
     assert all(32 <= s["S"] <= 512 and s["S"] % 32 == 0 for s in a)
+    # node counts log-uniform in [5e3, 4e5] up to the lattice rounding, and
+    # the cells near square (ring spacing 2 pi R / n_theta against L / n_z)
+    n = np.array([s["n_theta"] * s["n_z"] for s in a])
+    assert n.min() >= 0.95 * 5e3 and n.max() <= 1.05 * 4e5
+    aspect = np.array([(2 * np.pi * s["R"] / s["n_theta"]) / (s["L"] / (s["n_z"] - 1)) for s in a])
+    assert np.all((aspect > 0.5) & (aspect < 2.0))
 
 
 def test_device_fields_follow_the_lattice_distribution():
