@@ -12,6 +12,9 @@
  *  - Every call returns int32: ENS_OK (0) or a negative ENS_E* code.  The
  *    message of the last failure is ens_last_error(ctx) (valid until the
  *    next call on that context).  No C++ exception crosses this interface.
+ *    A NULL handle (context, batch, network, sampler) or a NULL output
+ *    pointer of a create call is ENS_EINVAL, checked before any device
+ *    call.
  *  - Host arrays passed in are COPIED before the call returns; the caller
  *    keeps ownership and may free them at once.
  *  - The library allocates no large device memory of its own: the caller
