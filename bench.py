@@ -586,13 +586,17 @@ def run_precision_config(args, torch):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--apply", choices=["f32", "f64"], default="f32")
-    ap.add_argument("--also-f64", action="store_true", default=True)
-    ap.add_argument("--no-also-f64", dest="also_f64", action="store_false")
-    ap.add_argument("--no-cpu-baseline", dest="cpu", action="store_false", default=True)
+    ap.add_argument("--gpus", type=int, default=1, help="must be 1: the benchmark runs on one GPU")
+    ap.add_argument("--steps", type=int, default=2000, help="timed steps")
+    ap.add_argument("--warmup", type=int, default=50, help="untimed steps before the timed ones")
+    ap.add_argument("--apply", choices=["f32", "f64"], default="f32",
+                    help="precision of the stiffness apply reported as value (state FP64)")
+    ap.add_argument("--also-f64", action="store_true", default=True,
+                    help="also time the other apply precision (default)")
+    ap.add_argument("--no-also-f64", dest="also_f64", action="store_false",
+                    help="skip timing the other apply precision")
+    ap.add_argument("--no-cpu-baseline", dest="cpu", action="store_false", default=True,
+                    help="skip timing the CPU oracle")
     ap.add_argument("--no-also-shared", dest="also_shared", action="store_false", default=True,
                     help="skip the shared-stiffness (block-row product) timing")
     ap.add_argument("--no-also-stress", dest="also_stress", action="store_false", default=True,
@@ -603,7 +607,7 @@ def main():
     ap.add_argument("--no-also-spde", dest="also_spde", action="store_false", default=True,
                     help="skip the SPDE field-sampler timing")
     ap.add_argument("--sample-block", type=int, default=0, help="0 = library default")
-    ap.add_argument("--sb-inner", action="store_true")
+    ap.add_argument("--sb-inner", action="store_true", help="order workgroups sample-block fastest")
     ap.add_argument("--config", choices=["c2_cylinder", "c3_curved", "c4_batch", "c5_learned", "c5_kernels"],
                     default="c2_cylinder",
                     help="c2_cylinder: the headline single-mesh workload; c3_curved: the precision form at "
