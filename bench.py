@@ -612,7 +612,7 @@ def main():
                     default="c2_cylinder",
                     help="c2_cylinder: the headline single-mesh workload; c3_curved: the precision form at "
                          "1M nodes x 1,024 samples (about 6 GPU-minutes); c4_batch: the batching form; "
-                         "c5_learned: the learned form (about 12 GPU-minutes); c5_kernels: the learned form's "
+                         "c5_learned: the learned form (about 17 GPU-minutes); c5_kernels: the learned form's "
                          "kernels at full size on random data (training step, forward, moments)")
     ap.add_argument("--c3-error-steps", type=int, default=20000,
                     help="c3_curved: steps of the error run")
