@@ -60,12 +60,12 @@ def step_kernel_bytes(n_nodes: int, n_el: int, S: int, apply_f32: bool, state: s
 
 def source_hash() -> str:
     """Hash of what decides the step kernels' memory traffic: the kernel
-    sources and the host code that picks their launch shapes, the node
-    ordering and the batch tile list."""
+    sources, the host code that picks their launch shapes, the node
+    ordering and the batch tile list, and the compiler flags."""
     h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_2101_09059_amd", "csrc")
-    for f in ("step.hip", "internal.h", "api.hip"):
-        with open(os.path.join(csrc, f), "rb") as fh:
+    pkg = os.path.join(ROOT, "paper_2101_09059_amd")
+    for f in ("csrc/step.hip", "csrc/internal.h", "csrc/api.hip", "build.py"):
+        with open(os.path.join(pkg, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 

@@ -20,22 +20,25 @@ def test_more_than_one_gpu_is_refused_before_any_gpu_work():
     assert r.stdout == ""
 
 
+FILES = ("csrc/step.hip", "csrc/internal.h", "csrc/api.hip", "build.py")
+
+
 def _copy_sources(tmp_path):
-    csrc = tmp_path / "paper_2101_09059_amd" / "csrc"
-    csrc.mkdir(parents=True)
-    for f in ("step.hip", "internal.h", "api.hip"):
-        shutil.copy(os.path.join(ROOT, "paper_2101_09059_amd", "csrc", f), csrc / f)
+    pkg = tmp_path / "paper_2101_09059_amd"
+    (pkg / "csrc").mkdir(parents=True)
+    for f in FILES:
+        shutil.copy(os.path.join(ROOT, "paper_2101_09059_amd", f), pkg / f)
     (tmp_path / "profiles").mkdir()
-    return csrc
+    return pkg
 
 
 def test_source_hash_follows_every_traffic_deciding_file(tmp_path, monkeypatch):
-    csrc = _copy_sources(tmp_path)
+    pkg = _copy_sources(tmp_path)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     h0 = bench.source_hash()
     assert h0 == bench.source_hash()
-    for f in ("step.hip", "internal.h", "api.hip"):
-        p = csrc / f
+    for f in FILES:
+        p = pkg / f
         text = p.read_text()
         p.write_text(text + "\n")
         assert bench.source_hash() != h0, f
@@ -44,7 +47,7 @@ def test_source_hash_follows_every_traffic_deciding_file(tmp_path, monkeypatch):
 
 
 def test_traffic_is_reported_only_for_the_sources_it_was_taken_on(tmp_path, monkeypatch):
-    csrc = _copy_sources(tmp_path)
+    pkg = _copy_sources(tmp_path)
     monkeypatch.setattr(bench, "ROOT", str(tmp_path))
     key = "c2_cylinder:fused_step_f32apply_f64state"
     assert bench.measured_traffic("c2_cylinder", "fused_step_f32apply_f64state", 0) is None  # no file
@@ -53,7 +56,7 @@ def test_traffic_is_reported_only_for_the_sources_it_was_taken_on(tmp_path, monk
     (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(rec))
     assert bench.measured_traffic("c2_cylinder", "fused_step_f32apply_f64state", 0) == (123456789, 120000000)
     assert bench.measured_traffic("c4_batch", "fused_step_f32apply_f64state", 0) is None  # other workload
-    p = csrc / "step.hip"
+    p = pkg / "csrc" / "step.hip"
     p.write_text(p.read_text() + "// changed\n")
     assert bench.measured_traffic("c2_cylinder", "fused_step_f32apply_f64state", 0) is None
 
